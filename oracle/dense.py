@@ -1,0 +1,142 @@
+"""ctypes wrapper of the FP64 dense-array oracle in ``lbm_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Arrays use the dense
+layout f[i, z, y, x] (x fastest) and mask[z, y, x] with True = solid.
+
+Physics (arXiv 1703.08015): BGK collision Eq. (2), quasi-compressible
+equilibrium Eq. (3), velocity Eq. (5), LBGK update Eq. (7), propagation only
+between non-solid nodes (Sec. 3.2) as half-way bounce-back, gather form of
+propagation (Sec. 3, Fig. 5).  Body force: Guo forcing (the paper has none).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+_lib = None
+
+
+def build(force=False):
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP for timing)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c99",
+           "-Wall", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, u32, dbl = ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+        lib.ora_lattice.argtypes = [ctypes.c_int, P, P, P]
+        lib.ora_feq.argtypes = [ctypes.c_int, dbl, P, P]
+        lib.ora_guo.argtypes = [ctypes.c_int, dbl, P, P, P]
+        lib.ora_collide.argtypes = [ctypes.c_int, P, dbl, P, P]
+        lib.ora_init.argtypes = [ctypes.c_int, P, P, dbl, P, P, P]
+        lib.ora_step.argtypes = [ctypes.c_int, P, u32, P, dbl, P, P, P, i64, ctypes.c_int]
+        lib.ora_moments.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        for fn in (lib.ora_lattice, lib.ora_feq, lib.ora_guo, lib.ora_collide, lib.ora_init,
+                   lib.ora_step, lib.ora_moments):
+            fn.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError("oracle call failed (%d)" % rc)
+
+
+def lattice(q):
+    """Velocities c[q,3] (int), weights w[q], opposite index opp[q]."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, np.float64)
+    opp = np.zeros(q, np.int32)
+    _check(_load().ora_lattice(q, _p(c), _p(w), _p(opp)))
+    return c, w, opp
+
+
+def feq(q, rho, u):
+    out = np.zeros(q)
+    u = np.ascontiguousarray(u, np.float64)
+    _check(_load().ora_feq(q, float(rho), _p(u), _p(out)))
+    return out
+
+
+def guo(q, rho, u, g):
+    """Guo source term without the (1 - omega/2) factor."""
+    out = np.zeros(q)
+    u = np.ascontiguousarray(u, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    _check(_load().ora_guo(q, float(rho), _p(u), _p(g), _p(out)))
+    return out
+
+
+def collide(q, f, tau, g):
+    f = np.ascontiguousarray(f, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    out = np.zeros(q)
+    _check(_load().ora_collide(q, _p(f), float(tau), _p(g), _p(out)))
+    return out
+
+
+def _shape3(mask):
+    nz, ny, nx = mask.shape
+    return np.array([nx, ny, nz], np.int32)
+
+
+def _periodic_bits(periodic):
+    if isinstance(periodic, (int, np.integer)):
+        return int(periodic)
+    return int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
+
+
+def init(q, mask, rho0=1.0, rho=None, u=None):
+    """Post-collision state at t = 0: f*_i = f_eq_i(rho, u) on fluid nodes."""
+    mask = np.ascontiguousarray(mask, np.uint8)
+    f = np.zeros((q,) + mask.shape, np.float64)
+    rho = None if rho is None else np.ascontiguousarray(rho, np.float64)
+    u = None if u is None else np.ascontiguousarray(u, np.float64)
+    rp = None if rho is None else _p(rho)
+    up = None if u is None else _p(u)
+    _check(_load().ora_init(q, _p(_shape3(mask)), _p(mask), float(rho0), rp, up, _p(f)))
+    return f
+
+
+def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1):
+    """Advance the post-collision state ``f`` by ``nsteps`` steps (in place copy)."""
+    mask = np.ascontiguousarray(mask, np.uint8)
+    f = np.array(f, np.float64, order="C", copy=True)
+    tmp = np.empty_like(f)
+    g = np.ascontiguousarray(g, np.float64)
+    _check(_load().ora_step(q, _p(_shape3(mask)), _periodic_bits(periodic), _p(mask), float(tau),
+                            _p(g), _p(f), _p(tmp), int(nsteps), int(nthreads)))
+    return f
+
+
+def moments(q, mask, f, g):
+    """rho[z,y,x], u[3,z,y,x] of the stored post-collision state; solid = 0."""
+    mask = np.ascontiguousarray(mask, np.uint8)
+    f = np.ascontiguousarray(f, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    rho = np.zeros(mask.shape)
+    u = np.zeros((3,) + mask.shape)
+    _check(_load().ora_moments(q, _p(_shape3(mask)), _p(mask), _p(g), _p(f), _p(rho), _p(u)))
+    return rho, u

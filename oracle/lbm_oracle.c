@@ -1,0 +1,297 @@
+/*
+ * Dense-array FP64 lattice Boltzmann oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this code.  It shares nothing
+ * with the GPU library: no headers, tables, helpers or build steps.
+ *
+ * What it computes (Tomczak & Szafran, "Sparse geometries handling in lattice
+ * Boltzmann method implementation for graphic processors", arXiv 1703.08015):
+ *   - BGK collision, Eq. (2), relaxation time tau, viscosity (tau - 1/2)/3;
+ *   - quasi-compressible equilibrium, Eq. (3) with c_s^2 = 1/3;
+ *   - quasi-compressible velocity, Eq. (5);
+ *   - the time-discrete LBGK update, Eq. (7), with delta_x = delta_t = 1;
+ *   - propagation only between non-solid nodes (Sec. 3.2), realised as
+ *     link-wise half-way bounce-back decided by the source node;
+ *   - the gather ("pull") form of propagation used by the two-copy tile
+ *     kernel (Sec. 3, Fig. 5): the stored array holds post-collision values,
+ *     a step first gathers f_i(x) = f*_i(x - c_i) and then collides.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - lattice weights and velocity ordering are the standard D2Q9 / D3Q19
+ *     sets (the paper's Fig. 1 is not reproduced in text);
+ *   - the body force g is an acceleration applied with Guo's forcing:
+ *     u = (sum_i c_i f_i)/rho + g/2 and a source term
+ *     F_i = w_i rho [3 (c_i - u).g + 9 (c_i.u)(c_i.g)] scaled by (1 - omega/2);
+ *   - a source position outside the domain on a non-periodic axis is solid;
+ *   - tau = +infinity gives omega = 0 (pure streaming, used with g = 0).
+ *
+ * Dense layout everywhere: f[i][z][y][x] (x fastest), mask[z][y][x] with
+ * nonzero = solid.  Solid entries of f are never read and are written as 0
+ * only by ora_init.  Plain loops, no blocking or fusion beyond the equations.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- lattice tables (standard velocity sets and weights) ------------- */
+
+static const int C9[9][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+static const double W9[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+static const int C19[19][3] = {
+    {0, 0, 0},   {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+    {0, 0, 1},   {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+    {-1, 1, 0},  {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const double W19[19] = {
+    1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+typedef struct {
+  int q;
+  const int (*c)[3];
+  const double *w;
+  int opp[19];
+} lattice_t;
+
+static int get_lattice(int q, lattice_t *L) {
+  if (q == 9) {
+    L->c = C9;
+    L->w = W9;
+  } else if (q == 19) {
+    L->c = C19;
+    L->w = W19;
+  } else {
+    return -1;
+  }
+  L->q = q;
+  /* the opposite direction is found by search, not assumed from the order */
+  for (int i = 0; i < q; ++i) {
+    L->opp[i] = -1;
+    for (int j = 0; j < q; ++j)
+      if (L->c[j][0] == -L->c[i][0] && L->c[j][1] == -L->c[i][1] &&
+          L->c[j][2] == -L->c[i][2])
+        L->opp[i] = j;
+  }
+  return 0;
+}
+
+int ora_lattice(int q, int32_t *c_out, double *w_out, int32_t *opp_out) {
+  lattice_t L;
+  if (get_lattice(q, &L)) return -1;
+  for (int i = 0; i < q; ++i) {
+    for (int a = 0; a < 3; ++a) c_out[3 * i + a] = L.c[i][a];
+    w_out[i] = L.w[i];
+    opp_out[i] = L.opp[i];
+  }
+  return 0;
+}
+
+/* ---- single-node physics -------------------------------------------- */
+
+/* Eq. (3): f_eq_i = w_i rho (1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)),
+ * cs2 = 1/3, i.e. coefficients 3, 9/2 and 3/2. */
+static void feq(const lattice_t *L, double rho, const double u[3], double *out) {
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < L->q; ++i) {
+    double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
+    out[i] = L->w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  }
+}
+
+/* Guo source term without the (1 - omega/2) prefactor:
+ * F_i = w_i rho [3 (c_i - u).g + 9 (c_i.u)(c_i.g)]. */
+static void guo(const lattice_t *L, double rho, const double u[3],
+                const double g[3], double *out) {
+  for (int i = 0; i < L->q; ++i) {
+    double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
+    double cg = L->c[i][0] * g[0] + L->c[i][1] * g[1] + L->c[i][2] * g[2];
+    double cmug = (L->c[i][0] - u[0]) * g[0] + (L->c[i][1] - u[1]) * g[1] +
+                  (L->c[i][2] - u[2]) * g[2];
+    out[i] = L->w[i] * rho * (3.0 * cmug + 9.0 * cu * cg);
+  }
+}
+
+/* Eq. (5) plus the half-force shift: rho = sum f, u = (sum c f)/rho + g/2. */
+static void macro(const lattice_t *L, const double *f, const double g[3],
+                  double *rho, double u[3]) {
+  double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < L->q; ++i) r += f[i];
+  for (int i = 0; i < L->q; ++i)
+    for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * f[i];
+  *rho = r;
+  for (int a = 0; a < 3; ++a) u[a] = j[a] / r + 0.5 * g[a];
+}
+
+/* Eqs. (2) and (7): f* = f + omega (f_eq - f) + (1 - omega/2) F. */
+static void collide(const lattice_t *L, const double *f, double tau,
+                    const double g[3], double *out) {
+  double rho, u[3], fe[19], F[19];
+  double omega = 1.0 / tau;
+  macro(L, f, g, &rho, u);
+  feq(L, rho, u, fe);
+  guo(L, rho, u, g, F);
+  for (int i = 0; i < L->q; ++i)
+    out[i] = f[i] + omega * (fe[i] - f[i]) + (1.0 - 0.5 * omega) * F[i];
+}
+
+int ora_feq(int q, double rho, const double *u, double *out) {
+  lattice_t L;
+  if (get_lattice(q, &L)) return -1;
+  feq(&L, rho, u, out);
+  return 0;
+}
+
+int ora_guo(int q, double rho, const double *u, const double *g, double *out) {
+  lattice_t L;
+  if (get_lattice(q, &L)) return -1;
+  guo(&L, rho, u, g, out);
+  return 0;
+}
+
+int ora_collide(int q, const double *f, double tau, const double *g,
+                double *out) {
+  lattice_t L;
+  if (get_lattice(q, &L)) return -1;
+  collide(&L, f, tau, g, out);
+  return 0;
+}
+
+/* ---- dense field operations ---------------------------------------- */
+
+typedef struct {
+  int n[3];
+  int periodic[3];
+  int64_t N;
+} grid_t;
+
+static void make_grid(const int32_t *shape, uint32_t periodic, grid_t *G) {
+  for (int a = 0; a < 3; ++a) {
+    G->n[a] = shape[a];
+    G->periodic[a] = (periodic >> a) & 1u;
+  }
+  G->N = (int64_t)shape[0] * shape[1] * shape[2];
+}
+
+static int64_t node_index(const grid_t *G, int x, int y, int z) {
+  return ((int64_t)z * G->n[1] + y) * G->n[0] + x;
+}
+
+/* Position of x - c_i, or -1 when it lies outside a non-periodic axis. */
+static int64_t source_of(const grid_t *G, const int p[3], const int c[3]) {
+  int s[3];
+  for (int a = 0; a < 3; ++a) {
+    s[a] = p[a] - c[a];
+    if (s[a] < 0 || s[a] >= G->n[a]) {
+      if (!G->periodic[a]) return -1;
+      s[a] = (s[a] % G->n[a] + G->n[a]) % G->n[a];
+    }
+  }
+  return node_index(G, s[0], s[1], s[2]);
+}
+
+/* Cold start (rho == NULL -> rho0, u == NULL -> 0) or given fields:
+ * fluid f*_i = f_eq_i(rho, u); solid entries 0. */
+int ora_init(int q, const int32_t *shape, const uint8_t *mask, double rho0,
+             const double *rho, const double *u, double *f) {
+  lattice_t L;
+  grid_t G;
+  if (get_lattice(q, &L)) return -1;
+  make_grid(shape, 0u, &G);
+  for (int64_t n = 0; n < G.N; ++n) {
+    double fe[19], uu[3] = {0.0, 0.0, 0.0}, r = rho0;
+    if (mask[n]) {
+      for (int i = 0; i < q; ++i) f[i * G.N + n] = 0.0;
+      continue;
+    }
+    if (rho) r = rho[n];
+    if (u)
+      for (int a = 0; a < 3; ++a) uu[a] = u[a * G.N + n];
+    feq(&L, r, uu, fe);
+    for (int i = 0; i < q; ++i) f[i * G.N + n] = fe[i];
+  }
+  return 0;
+}
+
+/* One pull-stream + collide pass from src into dst over fluid nodes. */
+static void one_step(const lattice_t *L, const grid_t *G, const uint8_t *mask,
+                     double tau, const double g[3], const double *src,
+                     double *dst, int nthreads) {
+  (void)nthreads;
+#pragma omp parallel for num_threads(nthreads) collapse(2) schedule(static)
+  for (int z = 0; z < G->n[2]; ++z) {
+    for (int y = 0; y < G->n[1]; ++y) {
+      for (int x = 0; x < G->n[0]; ++x) {
+        int p[3] = {x, y, z};
+        int64_t n = node_index(G, x, y, z);
+        double f[19], out[19];
+        if (mask[n]) continue;
+        for (int i = 0; i < L->q; ++i) {
+          int64_t s = source_of(G, p, L->c[i]);
+          if (s >= 0 && !mask[s])
+            f[i] = src[i * G->N + s];
+          else
+            f[i] = src[L->opp[i] * G->N + n]; /* half-way bounce-back */
+        }
+        collide(L, f, tau, g, out);
+        for (int i = 0; i < L->q; ++i) dst[i * G->N + n] = out[i];
+      }
+    }
+  }
+}
+
+/* nsteps time steps; f holds post-collision values on entry and on return.
+ * tmp is caller scratch of the same size as f. */
+int ora_step(int q, const int32_t *shape, uint32_t periodic,
+             const uint8_t *mask, double tau, const double *g, double *f,
+             double *tmp, int64_t nsteps, int nthreads) {
+  lattice_t L;
+  grid_t G;
+  if (get_lattice(q, &L)) return -1;
+  if (nthreads < 1) nthreads = 1;
+  make_grid(shape, periodic, &G);
+  /* solid entries of tmp mirror f so that the result is complete either way */
+  memcpy(tmp, f, sizeof(double) * (size_t)q * (size_t)G.N);
+  double *a = f, *b = tmp;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    one_step(&L, &G, mask, tau, g, a, b, nthreads);
+    double *s = a;
+    a = b;
+    b = s;
+  }
+  if (a != f) memcpy(f, a, sizeof(double) * (size_t)q * (size_t)G.N);
+  return 0;
+}
+
+/* Macroscopic fields of the stored post-collision state:
+ * rho = sum f*, u = (sum c f*)/rho - g/2 (equal to the step's Guo velocity
+ * because the collision adds rho g to the first moment).  Solid nodes: 0. */
+int ora_moments(int q, const int32_t *shape, const uint8_t *mask,
+                const double *g, const double *f, double *rho, double *u) {
+  lattice_t L;
+  grid_t G;
+  if (get_lattice(q, &L)) return -1;
+  make_grid(shape, 0u, &G);
+  for (int64_t n = 0; n < G.N; ++n) {
+    if (mask[n]) {
+      rho[n] = 0.0;
+      for (int a = 0; a < 3; ++a) u[a * G.N + n] = 0.0;
+      continue;
+    }
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < q; ++i) r += f[i * G.N + n];
+    for (int i = 0; i < q; ++i)
+      for (int a = 0; a < 3; ++a) j[a] += L.c[i][a] * f[i * G.N + n];
+    rho[n] = r;
+    for (int a = 0; a < 3; ++a) u[a * G.N + n] = j[a] / r - 0.5 * g[a];
+  }
+  return 0;
+}
