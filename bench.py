@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the sparse-tile D3Q19 lattice Boltzmann step on one MI355X.
+
+Workload: D3Q19 BGK quasi-compressible, FP64 PDFs, 256^3 periodic box filled
+with seeded overlapping solid spheres (radius 4-12) down to porosity 0.3,
+tau = 0.7, body force 1e-6 along x, 4x4x4 tiles.  A step is one full time step
+(gather propagation + bounce-back + collision) over every non-empty tile;
+inputs are resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS over non-solid nodes (the paper's counting,
+Sec. 4.2), the roofline of the step kernel (algorithmic bytes 2*q*s_d per
+non-solid node per step, Eq. 10, over the HIP-event-timed launch duration)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D3Q19 sparse MLUPS & % HBM peak; time-to-steady-state, warm vs cold, FP32 vs FP64"
+SD = {"f64": 8, "f32": 4, "f16": 2}
+
+
+def workload(args):
+    from paper_1703_08015_amd import inputs
+    if args.geometry == "spheres":
+        mask, phi = inputs.spheres_3d(args.n, args.porosity, 4.0, 12.0, seed=args.seed)
+        desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, overlapping solid spheres r 4-12 to porosity %.2f "
+                "(seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles" % (args.n, args.porosity, args.seed, args.tau,
+                                                                     args.g))
+    elif args.geometry == "vessel":
+        mask, phi = inputs.vessel_tree(args.n, 0.08, seed=args.seed)
+        desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
+                "fluid fraction >= 0.08, seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles"
+                % (args.n, args.seed, args.tau, args.g))
+    else:  # dense sanity point
+        mask, phi = np.zeros((args.n,) * 3, bool), 1.0
+        desc = "D3Q19 BGK quasi-compressible, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (args.n, args.tau)
+    return mask, phi, desc
+
+
+def traffic_for(kernel_name, workload_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    rec = table.get(kernel_name, {}).get(workload_key)
+    if not rec:
+        return None
+    with open(os.path.join(ROOT, "paper_1703_08015_amd", "csrc", "kernels.hip"), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(mask, args):
+    """The FP64 oracle on the same geometry, all host cores, a few steps."""
+    from oracle import dense
+    dense.build()
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    f = dense.init(19, mask)
+    g = [args.g, 0.0, 0.0]
+    t0 = time.perf_counter()
+    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores)
+    dt = time.perf_counter() - t0
+    nf = int((~mask).sum())
+    return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d steps of the full %d^3 geometry (%d non-solid nodes), FP64 dense C oracle, OpenMP, "
+                      "%.1f s" % (args.cpu_steps, args.n, nf, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
+    ap.add_argument("--geometry", default="spheres", choices=["spheres", "vessel", "dense"])
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--porosity", type=float, default=0.3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tau", type=float, default=0.7)
+    ap.add_argument("--g", type=float, default=1e-6)
+    ap.add_argument("--tiles-per-block", type=int, default=0)
+    ap.add_argument("--f16-scale-log2", type=int, default=22)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sparse-tile step is built and timed on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1703_08015_amd import lbm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mask, phi, desc = workload(args)
+    tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
+    info = tiles.info
+    solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
+                        tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2)
+    solver.init()
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+
+    stream = solver.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solver.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = ev0.elapsed_time(ev1) / args.steps
+
+    # the state must still be physical after the timed steps
+    tot = solver.reduce()[0]
+    if not np.all(np.isfinite(tot)):
+        raise RuntimeError("non-finite state after the timed steps")
+
+    nf = info["n_fluid"]
+    q, sd = 19, SD[args.storage]
+    mlups = nf * args.steps / wall / 1e6
+    alg_bytes = nf * 2 * q * sd  # Eq. (10) per non-solid node, per launch
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    kernel = "k_step<D3Q19,4x4x4,%s>" % args.storage
+    wkey = "%s_%d_%s" % (args.geometry, args.n, args.storage)
+    traffic = traffic_for(kernel, wkey)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "n_fluid": nf, "n_ftiles": info["n_ftiles"], "n_tiles": info["n_tiles"],
+            "phi": round(info["phi"], 4), "phi_t": round(info["phi_t"], 4),
+            "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": round(launch_ms, 5),
+        },
+        "bu_eq43": round(mlups * 1e6 * 2 * q * sd / (HBM_PEAK_GBS * 1e9), 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mask, args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

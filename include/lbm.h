@@ -1,0 +1,190 @@
+/*
+ * lbm.h -- C ABI of the sparse-tile lattice Boltzmann library (liblbm.so).
+ *
+ * Method: Tomczak & Szafran, "Sparse geometries handling in lattice
+ * Boltzmann method implementation for graphic processors" (arXiv 1703.08015).
+ * The geometry is covered by a uniform mesh of fixed-size tiles; tiles with
+ * no non-solid node are dropped (Sec. 3); a tile map with -1 for empty tiles
+ * locates neighbour tiles during propagation (two-copy method, Sec. 3).  One
+ * time step fuses gather propagation, half-way bounce-back (propagation only
+ * between non-solid nodes, Sec. 3.2) and the BGK collision, Eqs. (2), (3),
+ * (5), (7), with Guo forcing for a body acceleration g.
+ *
+ * Conventions for every call
+ *   - Return value: LBM_OK (0) or a negative LBM_ERR_* code.  Nothing throws
+ *     across the ABI.  lbm_last_error() returns a thread-local description of
+ *     the most recent failure on the calling thread.
+ *   - Dense host or device arrays are x-fastest: element (x, y, z) of an
+ *     (nx, ny, nz) lattice is at x + nx*(y + ny*z) (a torch tensor of shape
+ *     (nz, ny, nx)).  Vector fields are [component][z][y][x]; PDF fields are
+ *     [i][z][y][x] with the velocity order given by lbm_lattice().  For a
+ *     batch (lbm_tiles_concat) dense arrays are the concatenation, sample
+ *     after sample, of each sample's own dense array.
+ *   - The caller owns every host and device buffer and must keep the solver's
+ *     workspace alive until lbm_destroy.  The library owns only the opaque
+ *     lbm_tiles and lbm_solver objects; it never allocates device memory.
+ *   - Device work is enqueued on the HIP stream given to lbm_create (NULL =
+ *     the default stream) and is asynchronous unless a call says otherwise.
+ *   - A solver is not thread-safe; distinct solvers may be used concurrently.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_ERR_ARG (-1)         /* bad argument (NULL, tau <= 1/2, ...) */
+#define LBM_ERR_SHAPE (-2)       /* periodic axis not a multiple of the tile edge, bad size */
+#define LBM_ERR_UNSUPPORTED (-3) /* lattice / tile / storage combination not built */
+#define LBM_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed */
+#define LBM_ERR_NONFINITE (-5)   /* a reduction met a NaN or infinity */
+#define LBM_ERR_STATE (-6)       /* call out of order (e.g. step before init) */
+#define LBM_ERR_NOMEM (-7)       /* workspace too small, host allocation failed */
+
+/* ---- PDF storage forms ---------------------------------------------- */
+#define LBM_F64 0        /* f_i as IEEE binary64, arithmetic in FP64 */
+#define LBM_F32_OFFSET 1 /* f_i - w_i rho0 as binary32, arithmetic in FP32 */
+#define LBM_F16_OFFSET 2 /* (f_i - w_i rho0) * 2^s as binary16, arithmetic in FP32 */
+
+typedef struct lbm_tiles lbm_tiles;
+typedef struct lbm_solver lbm_solver;
+
+/* Statistics of a tiling (Sec. 2.3, Eqs. 11 and 17). */
+typedef struct {
+  int32_t shape[3];      /* lattice size given to lbm_tiles_build (one sample) */
+  int32_t grid[3];       /* size after padding non-periodic axes with solid */
+  int32_t tile[3];       /* tile edges (ax, ay, az) */
+  int32_t tgrid[3];      /* tiles per axis */
+  uint32_t periodic;     /* bit 0 x, bit 1 y, bit 2 z */
+  int32_t words;         /* 64-bit fluid-mask words per tile = ax*ay*az/64 */
+  int32_t n_samples;     /* 1, or the number of concatenated samples */
+  int32_t reserved;
+  int64_t n_tiles;       /* N_tiles: all tiles (summed over samples) */
+  int64_t n_ftiles;      /* N_ftiles: non-empty tiles */
+  int64_t n_fluid;       /* non-solid nodes */
+  int64_t n_nodes;       /* nodes of the unpadded lattice (summed over samples) */
+  double phi;            /* porosity, Eq. (11) */
+  double phi_t;          /* average tile porosity, Eq. (17) */
+  double tiles_ratio;    /* N_tiles / N_ftiles (Sec. 3.1.1.1) */
+} lbm_tiles_info_t;
+
+/* Solver parameters. */
+typedef struct {
+  int32_t lattice;         /* 9 = D2Q9 (tile 16x16x1) or 19 = D3Q19 (tile 4x4x4 or 4x4x8) */
+  int32_t storage;         /* LBM_F64, LBM_F32_OFFSET or LBM_F16_OFFSET */
+  double tau;              /* BGK relaxation time, Eq. (2): > 1/2, or +inf = pure streaming */
+  double g[3];             /* body acceleration (every sample; see lbm_set_sample_force) */
+  double rho0;             /* reference density: cold start and offset storage */
+  int32_t f16_scale_log2;  /* s of LBM_F16_OFFSET (0..24) */
+  int32_t tiles_per_block; /* waves per workgroup for the D3Q19 step: 1, 2, 4 or 8 (0 = 4) */
+} lbm_params;
+
+/* Velocity set and weights of a lattice (q = 9 or 19): c[3*q] (x, y, z per
+ * direction), w[q], opp[q].  Standard D2Q9 / D3Q19 sets; the paper's Fig. 1
+ * shows the D2Q9 set, the weights are those of Eq. (3) with c_s^2 = 1/3. */
+int lbm_lattice(int32_t q, int32_t *c, double *w, int32_t *opp);
+
+/* ---- tiling (host only, once per geometry: Sec. 3) ------------------
+ * solid: host uint8 [nz][ny][nx], nonzero = solid.  shape = {nx, ny, nz}
+ * (nz = 1 in 2D).  tile = {4,4,4}, {4,4,8} or {16,16,1}.  Non-periodic axes
+ * are padded at the high end with solid nodes; a periodic axis must be a
+ * multiple of its tile edge (else LBM_ERR_SHAPE).  Non-empty tiles are
+ * numbered row-major over tile coordinates, tx fastest.  *out is owned by
+ * the caller and released with lbm_tiles_free. */
+int lbm_tiles_build(const uint8_t *solid, const int32_t shape[3], const int32_t tile[3],
+                    uint32_t periodic, lbm_tiles **out);
+
+int lbm_tiles_info(const lbm_tiles *t, lbm_tiles_info_t *out);
+
+/* Copy the tiling into caller-sized host arrays (any pointer may be NULL):
+ *   tile_map   int32 [n_tiles]     index of the non-empty tile or -1 (the paper's tileMap)
+ *   tile_coord int32 [3*n_ftiles]  (tx, ty, tz) of each non-empty tile
+ *   nbr        int32 [27*n_ftiles] neighbour row, entry (dx+1)+3(dy+1)+9(dz+1),
+ *                                  wrapped on periodic axes, -1 outside or empty
+ *   fluid      uint64 [words*n_ftiles] node l = lx + ax*(ly + ay*lz) of a tile is
+ *                                  bit l%64 of word l/64, set = non-solid
+ * For a batch, tile_map holds each sample's map in turn and all tile indices
+ * are global (into the concatenated list). */
+int lbm_tiles_export(const lbm_tiles *t, int32_t *tile_map, int32_t *tile_coord, int32_t *nbr,
+                     uint64_t *fluid);
+
+/* Concatenate k tilings (same tile shape) into one tile list for a batched
+ * run: neighbour rows are offset, no link crosses samples.  The parts stay
+ * owned by the caller. */
+int lbm_tiles_concat(const lbm_tiles *const *parts, int32_t k, lbm_tiles **out);
+
+void lbm_tiles_free(lbm_tiles *t);
+
+/* ---- solver ----------------------------------------------------------
+ * Device workspace size for a tiling and parameters (both PDF copies of the
+ * two-copy method, Sec. 3, plus tile tables and reduction scratch). */
+int lbm_workspace_bytes(const lbm_tiles *t, const lbm_params *p, size_t *bytes);
+
+/* Create a solver.  ws: device memory of at least lbm_workspace_bytes bytes,
+ * 256-byte aligned, kept alive by the caller until lbm_destroy.  stream: a
+ * hipStream_t (NULL = default stream).  Uploads the tile tables (blocking). */
+int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, size_t bytes, void *stream,
+               lbm_solver **out);
+
+void lbm_destroy(lbm_solver *s);
+
+/* Change the stream later calls enqueue on. */
+int lbm_set_stream(lbm_solver *s, void *stream);
+
+/* Per-sample body acceleration g[3*n_samples] (host), for batches. */
+int lbm_set_sample_force(lbm_solver *s, const double *g);
+
+/* Initial state, Eq. (3): on every non-solid node the stored post-collision
+ * PDFs become f_eq(rho, u).  rho: device dense FP64 (NULL = rho0 everywhere);
+ * u: device dense FP64 [3][...] (NULL = 0).  Resets the step counter. */
+int lbm_init(lbm_solver *s, const double *rho, const double *u);
+
+/* n >= 0 time steps: gather propagation with half-way bounce-back, then the
+ * collision of Eqs. (2), (3), (5), (7) with Guo forcing; the two PDF copies
+ * swap roles after each step (Sec. 3).  Asynchronous. */
+int lbm_step(lbm_solver *s, int32_t n);
+
+/* Macroscopic fields of the current state: rho = sum f*_i and
+ * u = (sum c_i f*_i)/rho - g/2 (the velocity the last collision used).
+ * rho: device dense FP64, u: device dense FP64 [3][...]; solid nodes get 0.
+ * Either pointer may be NULL.  Asynchronous. */
+int lbm_moments(lbm_solver *s, double *rho, double *u);
+
+/* FP64 totals over non-solid nodes, per sample: out_host[4*sample + k] =
+ * mass, then momentum x, y, z (sum of rho u with u as in lbm_moments).
+ * Fixed-order reduction (run-to-run identical).  Synchronises the stream.
+ * LBM_ERR_NONFINITE if any total is not finite. */
+int lbm_reduce(lbm_solver *s, double *out_host);
+
+/* Steady-state residual per sample: out_host[sample] =
+ * ||u - u_ref||_2 / ||u||_2 over non-solid nodes, where u_ref is the velocity
+ * recorded at the previous lbm_residual or lbm_init call; then records the
+ * current velocity as the new reference.  FP64, fixed order.  Synchronises.
+ * LBM_ERR_NONFINITE if a residual is not finite. */
+int lbm_residual(lbm_solver *s, double *out_host);
+
+/* Dense FP64 copy of the stored PDFs, [i][z][y][x] (solid entries 0), device
+ * pointer.  Offset storage forms are expanded as f = w_i rho0 + offset. */
+int lbm_pdfs_export(lbm_solver *s, double *dev_dense);
+
+/* Load stored PDFs from a dense FP64 device array of the same layout (solid
+ * entries ignored); offset forms round to their storage type. */
+int lbm_pdfs_import(lbm_solver *s, const double *dev_dense);
+
+/* Number of steps taken since lbm_init. */
+int64_t lbm_step_count(const lbm_solver *s);
+
+const char *lbm_strerror(int code);
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,134 @@
+// Device-side definitions shared by the liblbm kernels: lattices, PDF storage
+// forms, tile records and kernel arguments.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// ---- lattices --------------------------------------------------------------
+// Standard D2Q9 and D3Q19 velocity sets; weights of the equilibrium, Eq. (3),
+// with c_s^2 = 1/3.  Opposite pairs are adjacent: (1,2), (3,4), ...
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int C[9][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+  static constexpr double Wt[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int Opp[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+};
+
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int C[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                   {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                   {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                   {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  static constexpr double Wt[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int Opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+};
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---- storage forms -----------------------------------------------------------
+// F64: the PDF itself.  F32/F16: the offset f_i - w_i rho0 (FP16 scaled by
+// 2^s), so that the stored values carry the deviation from rest rather than
+// the large constant w_i rho0.
+template <int S>
+struct Store;
+
+template <>
+struct Store<LBM_F64> {
+  using T = double;      // stored element
+  using R = double;      // arithmetic type of the step
+  static constexpr bool offset = false;
+  __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
+  __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
+};
+
+template <>
+struct Store<LBM_F32_OFFSET> {
+  using T = float;
+  using R = float;
+  static constexpr bool offset = true;
+  __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
+  __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
+};
+
+template <>
+struct Store<LBM_F16_OFFSET> {
+  using T = __half;
+  using R = float;
+  static constexpr bool offset = true;
+  // inv / scale are exact powers of two, so scaling is exact barring over/underflow
+  __device__ static __forceinline__ R load(const T *p, int64_t i, float inv) { return __half2float(p[i]) * inv; }
+  __device__ static __forceinline__ void store(T *p, int64_t i, R v, float scale) {
+    p[i] = __float2half_rn(v * scale);
+  }
+};
+
+// ---- tables ------------------------------------------------------------------
+// Per non-empty tile: first PDF entry of its region and fluid-node count.  The
+// region holds q blocks of n entries (direction-major), entry i*n + r being
+// direction i of the r-th non-solid node in lane order; regions start on
+// 128-byte boundaries.
+struct TileRec {
+  int64_t off;     // first PDF entry
+  int32_t n;       // non-solid nodes
+  int32_t sample;  // sample index (batches)
+};
+
+struct SampleRec {
+  double g[3];      // body acceleration
+  int64_t dense0;   // first node in concatenated dense arrays
+  int64_t n_nodes;  // nx*ny*nz
+  int64_t tile0;    // first tile
+  int64_t n_ftiles; // tiles of this sample
+  int64_t nbase0;   // first fluid node (compact numbering)
+  int64_t n_fluid;  // fluid nodes of this sample
+  int32_t shape[3]; // nx, ny, nz
+  int32_t pad;
+};
+
+// Arguments shared by the per-tile kernels.
+struct TileArgs {
+  const TileRec *rec;
+  const uint64_t *fluid;   // words per tile
+  const int32_t *pre;      // per tile and word: fluid nodes in earlier words
+  const int32_t *nbr;      // 27 per tile
+  const int32_t *coord;    // 3 per tile
+  const int64_t *nbase;    // first compact fluid-node index of each tile
+  const SampleRec *samples;
+  int64_t n_waves;         // non-empty tiles * words
+  int64_t n_fluid;
+  double rho0;
+  float f16_scale;         // 2^s
+  float f16_inv;           // 2^-s
+};
+
+// Workgroup -> logical block remap: the hardware hands workgroups to the 8
+// XCDs round-robin; this gives each XCD one contiguous range of blocks (and
+// so of tiles), keeping neighbour tiles inside one XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t k = b & 7, q = nb >> 3, r = nb & 7;
+  return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+}  // namespace lbm

@@ -1,0 +1,44 @@
+// Host-callable launchers of the liblbm kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+struct TileArgs;
+struct SampleRec;
+
+// Compile-time variant of the kernels: lattice, tile shape, storage form and
+// waves per workgroup of the step kernel.
+struct Variant {
+  int q;           // 9 or 19
+  int ax, ay, az;  // tile edges
+  int storage;     // LBM_F64 / LBM_F32_OFFSET / LBM_F16_OFFSET
+  int wpb;         // waves per workgroup (D2Q9 16x16: 4 = one tile)
+};
+
+bool variant_supported(const Variant &v);
+int storage_bytes(int storage);
+
+hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileArgs &a, double omega,
+                       hipStream_t s);
+hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,
+                       hipStream_t s);
+hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, double *rho, double *u,
+                          hipStream_t s);
+hipError_t launch_export(const Variant &v, const void *src, const TileArgs &a, double *dense, hipStream_t s);
+hipError_t launch_import(const Variant &v, void *dst, const TileArgs &a, const double *dense, hipStream_t s);
+// per-wave partial sums: 4 per wave (mass, rho u) ...
+hipError_t launch_reduce_partial(const Variant &v, const void *src, const TileArgs &a, double *part,
+                                 hipStream_t s);
+// ... and 2 per wave (|u - u_ref|^2, |u|^2), updating u_ref ([3][n_fluid])
+hipError_t launch_residual_partial(const Variant &v, const void *src, const TileArgs &a, double *uref,
+                                   double *part, int accumulate, hipStream_t s);
+// fixed-order sum of per-wave partials over each sample's waves
+hipError_t launch_reduce_final(const double *part, int ncomp, const SampleRec *samples, int n_samples,
+                               int words, double *out, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+
+}  // namespace lbm

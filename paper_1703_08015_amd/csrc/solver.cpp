@@ -1,0 +1,357 @@
+// Solver runtime behind the C ABI of lbm.h: validates parameters, lays out
+// the caller's device workspace (two PDF copies of the two-copy method,
+// Sec. 3, tile tables and reduction scratch), uploads the tiling and
+// enqueues the kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+#include "kernels.h"
+
+using lbm::set_error;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Byte offsets of every workspace array, plus the host tables to upload.
+struct Plan {
+  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, part, out, uref, total;
+  int64_t entries = 0;  // PDF entries per copy (with region alignment padding)
+  std::vector<lbm::TileRec> rec_h;
+  std::vector<int32_t> pre_h;
+  std::vector<int64_t> nbase_h;
+  std::vector<lbm::SampleRec> samples_h;
+};
+
+int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
+  if (!t || !p) return set_error(LBM_ERR_ARG, "NULL tiles or params");
+  if (lbm::storage_bytes(p->storage) == 0) return set_error(LBM_ERR_ARG, "unknown storage form %d", p->storage);
+  const bool tau_inf = std::isinf(p->tau) && p->tau > 0;
+  if (!tau_inf && !(std::isfinite(p->tau) && p->tau > 0.5))
+    return set_error(LBM_ERR_ARG, "tau = %g: must exceed 1/2 (or be +inf)", p->tau);
+  if (!(std::isfinite(p->rho0) && p->rho0 > 0)) return set_error(LBM_ERR_ARG, "rho0 = %g", p->rho0);
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->g[a])) return set_error(LBM_ERR_ARG, "g[%d] is not finite", a);
+  if (p->f16_scale_log2 < 0 || p->f16_scale_log2 > 24)
+    return set_error(LBM_ERR_ARG, "f16_scale_log2 = %d outside 0..24", p->f16_scale_log2);
+  int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
+  if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
+  v->q = p->lattice;
+  v->ax = t->tile[0];
+  v->ay = t->tile[1];
+  v->az = t->tile[2];
+  v->storage = p->storage;
+  v->wpb = wpb;
+  if (!lbm::variant_supported(*v))
+    return set_error(LBM_ERR_UNSUPPORTED, "lattice D%dQ%d with tile %dx%dx%d and %d waves per block not built",
+                     p->lattice == 9 ? 2 : 3, p->lattice, v->ax, v->ay, v->az, p->tiles_per_block);
+  return LBM_OK;
+}
+
+int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Plan &P) {
+  const int q = v.q, sd = lbm::storage_bytes(v.storage), W = t->words;
+  const int64_t A = 128 / sd;  // entries per 128-byte line
+  const int64_t nft = t->n_ftiles;
+  try {
+    P.rec_h.resize((size_t)nft);
+    P.pre_h.resize((size_t)(nft * W));
+    P.nbase_h.resize((size_t)nft);
+    int64_t off = 0, nb = 0;
+    for (int64_t k = 0; k < nft; ++k) {
+      int n = 0;
+      for (int w = 0; w < W; ++w) {
+        P.pre_h[(size_t)(k * W + w)] = n;
+        n += __builtin_popcountll(t->fluid[(size_t)(k * W + w)]);
+      }
+      P.rec_h[(size_t)k] = lbm::TileRec{off, n, t->sample_of[(size_t)k]};
+      P.nbase_h[(size_t)k] = nb;
+      off += ((int64_t)q * n + A - 1) / A * A;
+      nb += n;
+    }
+    P.entries = off;
+    P.samples_h.resize(t->samples.size());
+    for (size_t s = 0; s < t->samples.size(); ++s) {
+      const lbm::Sample &S = t->samples[s];
+      lbm::SampleRec &R = P.samples_h[s];
+      std::memset(&R, 0, sizeof R);
+      for (int a = 0; a < 3; ++a) {
+        R.g[a] = p->g[a];
+        R.shape[a] = S.shape[a];
+      }
+      R.dense0 = S.dense0;
+      R.n_nodes = S.n_nodes;
+      R.tile0 = S.tile0;
+      R.n_ftiles = S.n_ftiles;
+      R.nbase0 = S.n_ftiles ? P.nbase_h[(size_t)S.tile0] : 0;
+      R.n_fluid = S.n_fluid;
+    }
+  } catch (const std::bad_alloc &) {
+    return set_error(LBM_ERR_NOMEM, "out of host memory planning the workspace");
+  }
+  const int64_t waves = nft * W;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, kAlign);
+    return at;
+  };
+  P.buf[0] = take((size_t)P.entries * sd);
+  P.buf[1] = take((size_t)P.entries * sd);
+  P.rec = take((size_t)nft * sizeof(lbm::TileRec));
+  P.fluid = take((size_t)(nft * W) * sizeof(uint64_t));
+  P.pre = take((size_t)(nft * W) * sizeof(int32_t));
+  P.nbr = take((size_t)(nft * 27) * sizeof(int32_t));
+  P.coord = take((size_t)(nft * 3) * sizeof(int32_t));
+  P.nbase = take((size_t)nft * sizeof(int64_t));
+  P.samples = take(t->samples.size() * sizeof(lbm::SampleRec));
+  P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
+  P.out = take(t->samples.size() * 4 * sizeof(double));
+  P.uref = take((size_t)(3 * (t->n_fluid > 0 ? t->n_fluid : 1)) * sizeof(double));
+  P.total = o;
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_solver {
+  lbm::Variant var{};
+  lbm_params p{};
+  hipStream_t stream = nullptr;
+  lbm::TileArgs args{};
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t steps = 0;
+  bool initialized = false;
+  int n_samples = 0;
+  int words = 0;
+  double omega = 0.0;
+  int64_t dense_nodes = 0;
+  std::vector<lbm::SampleRec> samples_h;
+  lbm::SampleRec *samples_d = nullptr;
+  double *part = nullptr, *out = nullptr, *uref = nullptr;
+  std::vector<double> out_h;
+};
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return set_error(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" int lbm_lattice(int32_t q, int32_t *c, double *w, int32_t *opp) {
+  if (!c || !w || !opp) return set_error(LBM_ERR_ARG, "lbm_lattice: NULL argument");
+  auto fill = [&](const auto &L) {
+    using LT = std::decay_t<decltype(L)>;
+    for (int i = 0; i < LT::Q; ++i) {
+      for (int a = 0; a < 3; ++a) c[3 * i + a] = LT::C[i][a];
+      w[i] = LT::Wt[i];
+      opp[i] = LT::Opp[i];
+    }
+  };
+  if (q == 9)
+    fill(lbm::D2Q9{});
+  else if (q == 19)
+    fill(lbm::D3Q19{});
+  else
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_lattice: q = %d", q);
+  return LBM_OK;
+}
+
+extern "C" int lbm_workspace_bytes(const lbm_tiles *t, const lbm_params *p, size_t *bytes) {
+  if (!bytes) return set_error(LBM_ERR_ARG, "lbm_workspace_bytes: NULL bytes");
+  lbm::Variant v;
+  int rc = check_params(t, p, &v);
+  if (rc) return rc;
+  Plan P;
+  rc = make_plan(t, p, v, P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return LBM_OK;
+}
+
+extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, size_t bytes, void *stream,
+                          lbm_solver **out) {
+  if (!out) return set_error(LBM_ERR_ARG, "lbm_create: NULL out");
+  *out = nullptr;
+  lbm::Variant v;
+  int rc = check_params(t, p, &v);
+  if (rc) return rc;
+  if (!ws) return set_error(LBM_ERR_ARG, "lbm_create: NULL workspace");
+  if ((uintptr_t)ws % kAlign) return set_error(LBM_ERR_ARG, "lbm_create: workspace not %zu-byte aligned", kAlign);
+  Plan P;
+  rc = make_plan(t, p, v, P);
+  if (rc) return rc;
+  if (bytes < P.total)
+    return set_error(LBM_ERR_NOMEM, "lbm_create: workspace of %zu bytes, %zu needed", bytes, P.total);
+
+  lbm_solver *s = new (std::nothrow) lbm_solver();
+  if (!s) return set_error(LBM_ERR_NOMEM, "lbm_create: out of host memory");
+  char *base = static_cast<char *>(ws);
+  s->var = v;
+  s->p = *p;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->buf[0] = base + P.buf[0];
+  s->buf[1] = base + P.buf[1];
+  s->n_samples = (int)t->samples.size();
+  s->words = t->words;
+  s->omega = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
+  s->dense_nodes = t->n_nodes;
+  s->samples_h = P.samples_h;
+  s->samples_d = reinterpret_cast<lbm::SampleRec *>(base + P.samples);
+  s->part = reinterpret_cast<double *>(base + P.part);
+  s->out = reinterpret_cast<double *>(base + P.out);
+  s->uref = reinterpret_cast<double *>(base + P.uref);
+  s->out_h.assign((size_t)s->n_samples * 4, 0.0);
+
+  lbm::TileArgs &a = s->args;
+  a.rec = reinterpret_cast<const lbm::TileRec *>(base + P.rec);
+  a.fluid = reinterpret_cast<const uint64_t *>(base + P.fluid);
+  a.pre = reinterpret_cast<const int32_t *>(base + P.pre);
+  a.nbr = reinterpret_cast<const int32_t *>(base + P.nbr);
+  a.coord = reinterpret_cast<const int32_t *>(base + P.coord);
+  a.nbase = reinterpret_cast<const int64_t *>(base + P.nbase);
+  a.samples = s->samples_d;
+  a.n_waves = t->n_ftiles * t->words;
+  a.n_fluid = t->n_fluid;
+  a.rho0 = p->rho0;
+  a.f16_scale = std::ldexp(1.0f, p->f16_scale_log2);
+  a.f16_inv = std::ldexp(1.0f, -p->f16_scale_log2);
+
+  auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s->stream);
+  };
+  hipError_t e = hipSuccess;
+  const int64_t nft = t->n_ftiles, W = t->words;
+  if (e == hipSuccess) e = up(P.rec, P.rec_h.data(), (size_t)nft * sizeof(lbm::TileRec));
+  if (e == hipSuccess) e = up(P.fluid, t->fluid.data(), (size_t)(nft * W) * sizeof(uint64_t));
+  if (e == hipSuccess) e = up(P.pre, P.pre_h.data(), (size_t)(nft * W) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.nbr, t->nbr.data(), (size_t)(nft * 27) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.coord, t->coord.data(), (size_t)(nft * 3) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.nbase, P.nbase_h.data(), (size_t)nft * sizeof(int64_t));
+  if (e == hipSuccess) e = up(P.samples, P.samples_h.data(), P.samples_h.size() * sizeof(lbm::SampleRec));
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host tables may be freed after return
+  if (e != hipSuccess) {
+    delete s;
+    return set_error(LBM_ERR_HIP, "lbm_create: upload failed: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_solver *s) { delete s; }
+
+extern "C" int lbm_set_stream(lbm_solver *s, void *stream) {
+  if (!s) return set_error(LBM_ERR_ARG, "lbm_set_stream: NULL solver");
+  s->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_sample_force(lbm_solver *s, const double *g) {
+  if (!s || !g) return set_error(LBM_ERR_ARG, "lbm_set_sample_force: NULL argument");
+  for (int k = 0; k < 3 * s->n_samples; ++k)
+    if (!std::isfinite(g[k])) return set_error(LBM_ERR_ARG, "lbm_set_sample_force: g[%d] not finite", k);
+  for (int k = 0; k < s->n_samples; ++k)
+    for (int a = 0; a < 3; ++a) s->samples_h[(size_t)k].g[a] = g[3 * k + a];
+  HIP_TRY(hipMemcpyAsync(s->samples_d, s->samples_h.data(), s->samples_h.size() * sizeof(lbm::SampleRec),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_init(lbm_solver *s, const double *rho, const double *u) {
+  if (!s) return set_error(LBM_ERR_ARG, "lbm_init: NULL solver");
+  HIP_TRY(lbm::launch_init(s->var, s->buf[0], s->args, rho, u, s->stream));
+  s->cur = 0;
+  s->steps = 0;
+  s->initialized = true;
+  // record the reference velocity of the residual
+  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[0], s->args, s->uref, s->part, 0, s->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_solver *s, int32_t n) {
+  if (!s) return set_error(LBM_ERR_ARG, "lbm_step: NULL solver");
+  if (n < 0) return set_error(LBM_ERR_ARG, "lbm_step: n = %d", n);
+  if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_step: call lbm_init or lbm_pdfs_import first");
+  for (int32_t k = 0; k < n; ++k) {
+    HIP_TRY(lbm::launch_step(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->omega, s->stream));
+    s->cur ^= 1;
+    ++s->steps;
+  }
+  return LBM_OK;
+}
+
+extern "C" int64_t lbm_step_count(const lbm_solver *s) { return s ? s->steps : -1; }
+
+extern "C" int lbm_moments(lbm_solver *s, double *rho, double *u) {
+  if (!s) return set_error(LBM_ERR_ARG, "lbm_moments: NULL solver");
+  if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_moments: solver not initialised");
+  if (rho) HIP_TRY(lbm::launch_fill(rho, s->dense_nodes, 0.0, s->stream));
+  if (u) HIP_TRY(lbm::launch_fill(u, 3 * s->dense_nodes, 0.0, s->stream));
+  HIP_TRY(lbm::launch_moments(s->var, s->buf[s->cur], s->args, rho, u, s->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_reduce(lbm_solver *s, double *out_host) {
+  if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_reduce: NULL argument");
+  if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_reduce: solver not initialised");
+  HIP_TRY(lbm::launch_reduce_partial(s->var, s->buf[s->cur], s->args, s->part, s->stream));
+  HIP_TRY(lbm::launch_reduce_final(s->part, 4, s->samples_d, s->n_samples, s->words, s->out, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 4 * sizeof(double),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  std::memcpy(out_host, s->out_h.data(), (size_t)s->n_samples * 4 * sizeof(double));
+  for (int k = 0; k < 4 * s->n_samples; ++k)
+    if (!std::isfinite(out_host[k])) return set_error(LBM_ERR_NONFINITE, "lbm_reduce: total %d is not finite", k);
+  return LBM_OK;
+}
+
+extern "C" int lbm_residual(lbm_solver *s, double *out_host) {
+  if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_residual: NULL argument");
+  if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_residual: solver not initialised");
+  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[s->cur], s->args, s->uref, s->part, 1, s->stream));
+  HIP_TRY(lbm::launch_reduce_final(s->part, 2, s->samples_d, s->n_samples, s->words, s->out, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  int bad = -1;
+  for (int k = 0; k < s->n_samples; ++k) {
+    const double d2 = s->out_h[(size_t)(2 * k)], n2 = s->out_h[(size_t)(2 * k + 1)];
+    double r;
+    if (n2 > 0.0)
+      r = std::sqrt(d2 / n2);
+    else
+      r = d2 > 0.0 ? INFINITY : 0.0;
+    if (!std::isfinite(d2) || !std::isfinite(n2)) {
+      r = NAN;
+      bad = k;
+    }
+    out_host[k] = r;
+  }
+  if (bad >= 0) return set_error(LBM_ERR_NONFINITE, "lbm_residual: sample %d is not finite", bad);
+  return LBM_OK;
+}
+
+extern "C" int lbm_pdfs_export(lbm_solver *s, double *dev_dense) {
+  if (!s || !dev_dense) return set_error(LBM_ERR_ARG, "lbm_pdfs_export: NULL argument");
+  if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_pdfs_export: solver not initialised");
+  HIP_TRY(lbm::launch_fill(dev_dense, (int64_t)s->var.q * s->dense_nodes, 0.0, s->stream));
+  HIP_TRY(lbm::launch_export(s->var, s->buf[s->cur], s->args, dev_dense, s->stream));
+  return LBM_OK;
+}
+
+extern "C" int lbm_pdfs_import(lbm_solver *s, const double *dev_dense) {
+  if (!s || !dev_dense) return set_error(LBM_ERR_ARG, "lbm_pdfs_import: NULL argument");
+  HIP_TRY(lbm::launch_import(s->var, s->buf[s->cur], s->args, dev_dense, s->stream));
+  s->initialized = true;
+  return LBM_OK;
+}

@@ -1,0 +1,308 @@
+"""Python binding of liblbm (``include/lbm.h``): argument marshalling only.
+
+Every computation runs in the HIP library; torch supplies device memory (the
+solver workspace and dense fields) and the HIP stream.  The library must have
+been built (``paper_1703_08015_amd.build``): a missing library raises instead
+of falling back to anything else.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lbm.h")
+
+LBM_OK = 0
+LBM_ERR_ARG = -1
+LBM_ERR_SHAPE = -2
+LBM_ERR_UNSUPPORTED = -3
+LBM_ERR_HIP = -4
+LBM_ERR_NONFINITE = -5
+LBM_ERR_STATE = -6
+LBM_ERR_NOMEM = -7
+
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, where, detail):
+        super().__init__("%s failed (%d): %s" % (where, code, detail))
+        self.code = code
+
+
+class TilesInfo(ctypes.Structure):
+    _fields_ = [
+        ("shape", ctypes.c_int32 * 3), ("grid", ctypes.c_int32 * 3), ("tile", ctypes.c_int32 * 3),
+        ("tgrid", ctypes.c_int32 * 3), ("periodic", ctypes.c_uint32), ("words", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_tiles", ctypes.c_int64), ("n_ftiles", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+        ("n_nodes", ctypes.c_int64), ("phi", ctypes.c_double), ("phi_t", ctypes.c_double),
+        ("tiles_ratio", ctypes.c_double),
+    ]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
+        ("g", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("f16_scale_log2", ctypes.c_int32),
+        ("tiles_per_block", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions ``include/lbm.h`` declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbm.so is not built (%s); run paper_1703_08015_amd.build.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "lbm_lattice": (ctypes.c_int, [I32, P, P, P]),
+            "lbm_tiles_build": (ctypes.c_int, [P, P, P, U32, PP]),
+            "lbm_tiles_info": (ctypes.c_int, [P, ctypes.POINTER(TilesInfo)]),
+            "lbm_tiles_export": (ctypes.c_int, [P, P, P, P, P]),
+            "lbm_tiles_concat": (ctypes.c_int, [P, I32, PP]),
+            "lbm_tiles_free": (None, [P]),
+            "lbm_workspace_bytes": (ctypes.c_int, [P, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+            "lbm_create": (ctypes.c_int, [P, ctypes.POINTER(Params), P, ctypes.c_size_t, P, PP]),
+            "lbm_destroy": (None, [P]),
+            "lbm_set_stream": (ctypes.c_int, [P, P]),
+            "lbm_set_sample_force": (ctypes.c_int, [P, P]),
+            "lbm_init": (ctypes.c_int, [P, P, P]),
+            "lbm_step": (ctypes.c_int, [P, I32]),
+            "lbm_moments": (ctypes.c_int, [P, P, P]),
+            "lbm_reduce": (ctypes.c_int, [P, P]),
+            "lbm_residual": (ctypes.c_int, [P, P]),
+            "lbm_pdfs_export": (ctypes.c_int, [P, P]),
+            "lbm_pdfs_import": (ctypes.c_int, [P, P]),
+            "lbm_step_count": (I64, [P]),
+            "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "lbm_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, where):
+    if rc != LBM_OK:
+        detail = lib().lbm_last_error()
+        raise LbmError(rc, where, detail.decode() if detail else "")
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice(q):
+    """Velocities c[q,3], weights w[q], opposite indices opp[q] of liblbm."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, np.float64)
+    opp = np.zeros(q, np.int32)
+    _check(lib().lbm_lattice(q, _np_ptr(c), _np_ptr(w), _np_ptr(opp)), "lbm_lattice")
+    return c, w, opp
+
+
+def _periodic_bits(periodic):
+    if isinstance(periodic, (int, np.integer)):
+        return int(periodic)
+    return int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
+
+
+class Tiles:
+    """A tiling (lbm_tiles_build / lbm_tiles_concat)."""
+
+    def __init__(self, solid=None, tile=(4, 4, 4), periodic=(1, 1, 1), _handle=None, _parts=None):
+        self._h = ctypes.c_void_p()
+        self._parts = _parts
+        if _handle is not None:
+            self._h = _handle
+        else:
+            solid = np.ascontiguousarray(np.asarray(solid).astype(np.uint8))
+            if solid.ndim != 3:
+                raise ValueError("solid mask must be (nz, ny, nx)")
+            nz, ny, nx = solid.shape
+            shape = np.array([nx, ny, nz], np.int32)
+            t = np.array(tile, np.int32)
+            _check(lib().lbm_tiles_build(_np_ptr(solid), _np_ptr(shape), _np_ptr(t), _periodic_bits(periodic),
+                                         ctypes.byref(self._h)), "lbm_tiles_build")
+        self.info = self._info()
+
+    @classmethod
+    def concat(cls, parts):
+        arr = (ctypes.c_void_p * len(parts))(*[p._h.value for p in parts])
+        h = ctypes.c_void_p()
+        _check(lib().lbm_tiles_concat(arr, len(parts), ctypes.byref(h)), "lbm_tiles_concat")
+        return cls(_handle=h, _parts=list(parts))
+
+    def _info(self):
+        i = TilesInfo()
+        _check(lib().lbm_tiles_info(self._h, ctypes.byref(i)), "lbm_tiles_info")
+        return dict(shape=tuple(i.shape), grid=tuple(i.grid), tile=tuple(i.tile), tgrid=tuple(i.tgrid),
+                    periodic=i.periodic, words=i.words, n_samples=i.n_samples, n_tiles=i.n_tiles,
+                    n_ftiles=i.n_ftiles, n_fluid=i.n_fluid, n_nodes=i.n_nodes, phi=i.phi, phi_t=i.phi_t,
+                    tiles_ratio=i.tiles_ratio)
+
+    def export(self):
+        i = self.info
+        tm = np.zeros(i["n_tiles"], np.int32)
+        co = np.zeros(3 * i["n_ftiles"], np.int32)
+        nb = np.zeros(27 * i["n_ftiles"], np.int32)
+        fl = np.zeros(i["words"] * i["n_ftiles"], np.uint64)
+        _check(lib().lbm_tiles_export(self._h, _np_ptr(tm), _np_ptr(co), _np_ptr(nb), _np_ptr(fl)),
+               "lbm_tiles_export")
+        return dict(tile_map=tm, tile_coord=co, nbr=nb, fluid=fl)
+
+    def __del__(self):
+        try:
+            if self._h and self._h.value:
+                lib().lbm_tiles_free(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
+                tiles_per_block=0):
+    p = Params()
+    p.lattice = lattice
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.tau = float(tau)
+    for k in range(3):
+        p.g[k] = float(g[k])
+    p.rho0 = float(rho0)
+    p.f16_scale_log2 = int(f16_scale_log2)
+    p.tiles_per_block = int(tiles_per_block)
+    return p
+
+
+def workspace_bytes(tiles, **params):
+    n = ctypes.c_size_t()
+    p = make_params(**params)
+    _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(p), ctypes.byref(n)), "lbm_workspace_bytes")
+    return n.value
+
+
+class Solver:
+    """A solver on one tiling; device memory and stream come from torch."""
+
+    def __init__(self, tiles, lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
+                 tiles_per_block=0, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.tiles = tiles
+        self.q = lattice
+        self.params = make_params(lattice, storage, tau, g, rho0, f16_scale_log2, tiles_per_block)
+        self.device = torch.device(device)
+        n = ctypes.c_size_t()
+        _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(self.params), ctypes.byref(n)),
+               "lbm_workspace_bytes")
+        self.workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        _check(lib().lbm_create(tiles._h, ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                n.value, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)),
+               "lbm_create")
+        info = tiles.info
+        self.n_samples = info["n_samples"]
+        self.dense_shape = (info["shape"][2], info["shape"][1], info["shape"][0]) if self.n_samples == 1 else None
+        self.n_nodes = info["n_nodes"]
+
+    # shapes of dense fields
+    def _scalar_shape(self):
+        return self.dense_shape if self.dense_shape else (self.n_nodes,)
+
+    def _vec_shape(self):
+        return (3,) + self.dense_shape if self.dense_shape else (3 * self.n_nodes,)
+
+    def _pdf_shape(self):
+        return (self.q,) + self.dense_shape if self.dense_shape else (self.q * self.n_nodes,)
+
+    def _dev(self, t, shape):
+        torch = self.torch
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if t.numel() != int(np.prod(shape)):
+            raise ValueError("expected %d elements, got %d" % (int(np.prod(shape)), t.numel()))
+        return t
+
+    def init(self, rho=None, u=None):
+        r = None if rho is None else self._dev(rho, self._scalar_shape())
+        v = None if u is None else self._dev(u, self._vec_shape())
+        _check(lib().lbm_init(self._h, ctypes.c_void_p(r.data_ptr()) if r is not None else None,
+                              ctypes.c_void_p(v.data_ptr()) if v is not None else None), "lbm_init")
+        self._keep = (r, v)  # alive until the stream has consumed them
+        self.stream.synchronize()
+        self._keep = None
+
+    def step(self, n=1):
+        _check(lib().lbm_step(self._h, int(n)), "lbm_step")
+
+    def moments(self):
+        torch = self.torch
+        rho = torch.empty(self._scalar_shape(), dtype=torch.float64, device=self.device)
+        u = torch.empty(self._vec_shape(), dtype=torch.float64, device=self.device)
+        _check(lib().lbm_moments(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr())),
+               "lbm_moments")
+        return rho, u
+
+    def reduce(self):
+        out = np.zeros(4 * self.n_samples)
+        _check(lib().lbm_reduce(self._h, _np_ptr(out)), "lbm_reduce")
+        return out.reshape(self.n_samples, 4)
+
+    def residual(self):
+        out = np.zeros(self.n_samples)
+        _check(lib().lbm_residual(self._h, _np_ptr(out)), "lbm_residual")
+        return out
+
+    def pdfs_export(self):
+        torch = self.torch
+        f = torch.empty(self._pdf_shape(), dtype=torch.float64, device=self.device)
+        _check(lib().lbm_pdfs_export(self._h, ctypes.c_void_p(f.data_ptr())), "lbm_pdfs_export")
+        return f
+
+    def pdfs_import(self, f):
+        f = self._dev(f, self._pdf_shape())
+        _check(lib().lbm_pdfs_import(self._h, ctypes.c_void_p(f.data_ptr())), "lbm_pdfs_import")
+        self.stream.synchronize()
+
+    def set_sample_force(self, g):
+        g = np.ascontiguousarray(np.asarray(g, np.float64).reshape(-1))
+        if g.size != 3 * self.n_samples:
+            raise ValueError("need 3 values per sample")
+        _check(lib().lbm_set_sample_force(self._h, _np_ptr(g)), "lbm_set_sample_force")
+
+    @property
+    def step_count(self):
+        return lib().lbm_step_count(self._h)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def __del__(self):
+        try:
+            if self._h and self._h.value:
+                lib().lbm_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass

@@ -1,0 +1,252 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: bit-exact where no arithmetic happens (pure streaming with tau = +inf
+and g = 0, checkpoint export/import, the tiling), FP64 PDFs within 1e-12
+relative after 1000 steps, FP64 reductions against math.fsum of the oracle's
+fields.  Shapes span several tiles with ragged (padded) edges.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from paper_1703_08015_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _tiles(mask, q, tile=None, periodic=(1, 1, 1)):
+    if tile is None:
+        tile = (16, 16, 1) if q == 9 else (4, 4, 4)
+    return lbm.Tiles(mask, tile, periodic)
+
+
+def _gpu_run(torch, mask, q, tau, g, steps, periodic, f0=None, rho=None, u=None, storage="f64", tile=None,
+             tpb=0, f16_scale_log2=20):
+    t = _tiles(mask, q, tile, periodic)
+    s = lbm.Solver(t, lattice=q, storage=storage, tau=tau, g=g, tiles_per_block=tpb,
+                   f16_scale_log2=f16_scale_log2)
+    if f0 is not None:
+        s.pdfs_import(torch.from_numpy(f0).cuda())
+    else:
+        s.init(None if rho is None else torch.from_numpy(rho).cuda(), None if u is None else torch.from_numpy(u).cuda())
+    s.step(steps)
+    f = s.pdfs_export().cpu().numpy()
+    r, v = s.moments()
+    torch.cuda.synchronize()
+    return f, r.cpu().numpy(), v.cpu().numpy(), s
+
+
+def _geoms(q):
+    """(name, mask, periodic) with several tiles and ragged padded edges."""
+    if q == 9:
+        yield "channel64", inputs.channel_2d(64, 64, seed=0)[0], (1, 0, 0)
+        yield "ragged", inputs.channel_2d(48, 37, porosity=0.7, seed=3)[0], (1, 0, 0)
+    else:
+        yield "spheres_periodic", inputs.spheres_3d(24, 0.4, rmin=2, rmax=5, seed=1)[0], (1, 1, 1)
+        yield "ragged", inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=2, periodic=(1, 0, 0))[0], (1, 0, 0)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_permutation_mode_bitexact(torch, q):
+    """tau = +inf, g = 0: the step only moves values, so GPU == oracle exactly."""
+    for name, mask, per in _geoms(q):
+        _log("permutation", q, name, mask.shape)
+        f0 = inputs.random_pdfs(q, mask, seed=21)
+        f, _, _, _ = _gpu_run(torch, mask, q, math.inf, (0, 0, 0), 7, per, f0=f0)
+        want = dense.step(q, mask, f0, math.inf, [0, 0, 0], 7, periodic=per)
+        assert np.array_equal(f, want), name
+
+
+@pytest.mark.parametrize("tpb", [1, 2, 8])
+def test_permutation_mode_bitexact_launch_shapes(torch, tpb):
+    """Every workgroup size of the D3Q19 step visits every tile exactly once."""
+    mask = inputs.spheres_3d((28, 20, 16), 0.5, rmin=2, rmax=5, seed=5)[0]
+    f0 = inputs.random_pdfs(19, mask, seed=22)
+    f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 3, (1, 1, 1), f0=f0, tpb=tpb)
+    assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 3, periodic=7))
+
+
+def test_permutation_mode_bitexact_tall_tiles(torch):
+    mask = inputs.spheres_3d((16, 12, 24), 0.45, rmin=2, rmax=5, seed=6)[0]
+    f0 = inputs.random_pdfs(19, mask, seed=23)
+    f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 5, (1, 1, 1), f0=f0, tile=(4, 4, 8))
+    assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 5, periodic=7))
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def test_fp64_1000_steps_channel_2d(torch):
+    """D2Q9 64x64 channel with discs, tau 0.8, g = 1e-6 in x, 1000 steps."""
+    mask, _ = inputs.channel_2d(64, 64, seed=0)
+    g = (1e-6, 0.0, 0.0)
+    f, r, u, _ = _gpu_run(torch, mask, 9, 0.8, g, 1000, (1, 0, 0))
+    f0 = dense.init(9, mask)
+    want = dense.step(9, mask, f0, 0.8, g, 1000, periodic=(1, 0, 0))
+    fl = ~mask
+    assert np.max(np.abs(f - want)[:, fl] / np.abs(want)[:, fl]) <= 1e-12
+    rw, uw = dense.moments(9, mask, want, g)
+    assert _rel(u, uw) <= 1e-9 and np.max(np.abs(r - rw)) <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["spheres_periodic", "ragged_random_state"])
+def test_fp64_1000_steps_3d(torch, case):
+    """D3Q19 porous crops: from rest with g (tau 0.7), and from a random state."""
+    if case == "spheres_periodic":
+        mask = inputs.spheres_3d(32, 0.3, seed=8)[0]
+        per, rho, u, g = (1, 1, 1), None, None, (1e-6, 0.0, 0.0)
+    else:
+        mask = inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=9, periodic=(1, 0, 0))[0]
+        per, g = (1, 0, 0), (2e-5, -1e-5, 3e-6)
+        rho, u = inputs.random_macro(mask, seed=10)
+    f, r, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, per, rho=rho, u=u)
+    f0 = dense.init(19, mask, rho=rho, u=u)
+    want = dense.step(19, mask, f0, 0.7, g, 1000, periodic=per, nthreads=8)
+    fl = ~mask
+    assert np.max(np.abs(f - want)[:, fl] / np.abs(want)[:, fl]) <= 1e-12
+    rw, uw = dense.moments(19, mask, want, g)
+    assert _rel(v, uw) <= 1e-9
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_init_and_moments_match_oracle(torch, q):
+    mask = inputs.channel_2d(48, 37, seed=3)[0] if q == 9 else inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5,
+                                                                                  seed=2, periodic=(1, 0, 0))[0]
+    rho, u = inputs.random_macro(mask, seed=11)
+    if q == 9:
+        u[2] = 0.0
+    g = (3e-6, -2e-6, 0.0 if q == 9 else 1e-6)
+    f, r, v, _ = _gpu_run(torch, mask, q, 0.9, g, 0, (1, 0, 0), rho=rho, u=u)
+    want = dense.init(q, mask, rho=rho, u=u)
+    assert np.max(np.abs(f - want)) <= 4e-16
+    rw, uw = dense.moments(q, mask, want, g)
+    assert np.max(np.abs(r - rw)) <= 1e-15 and np.max(np.abs(v - uw)) <= 1e-15
+    assert np.all(r[mask] == 0) and np.all(v[:, mask] == 0) and np.all(f[:, mask] == 0)
+
+
+def test_reduce_and_residual(torch):
+    mask = inputs.spheres_3d(24, 0.4, rmin=2, rmax=5, seed=12)[0]
+    g = (1e-5, 0.0, -2e-6)
+    t = _tiles(mask, 19)
+    s = lbm.Solver(t, lattice=19, tau=0.75, g=g)
+    rho, u = inputs.random_macro(mask, seed=13)
+    s.init(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    tot0 = s.reduce()[0]
+    s.step(10)
+    r1, u1 = [x.cpu().numpy() for x in s.moments()]
+    tot = s.reduce()[0]
+    assert math.isclose(tot[0], math.fsum(r1.ravel()), rel_tol=1e-13)
+    for k in range(3):
+        assert math.isclose(tot[1 + k], math.fsum((r1 * u1[k]).ravel()), rel_tol=1e-11, abs_tol=1e-15)
+    assert math.isclose(tot[0], tot0[0], rel_tol=1e-13)  # mass is conserved
+    # residual against the velocity recorded at init
+    res = s.residual()[0]
+    ri, ui = dense.moments(19, mask, dense.init(19, mask, rho=rho, u=u), g)
+    fl = ~mask
+    want = math.sqrt(math.fsum(((u1 - ui)[:, fl] ** 2).ravel()) / math.fsum((u1[:, fl] ** 2).ravel()))
+    assert math.isclose(res, want, rel_tol=1e-12)
+    s.step(3)
+    r2, u2 = [x.cpu().numpy() for x in s.moments()]
+    want2 = math.sqrt(math.fsum(((u2 - u1)[:, fl] ** 2).ravel()) / math.fsum((u2[:, fl] ** 2).ravel()))
+    assert math.isclose(s.residual()[0], want2, rel_tol=1e-12)
+    # fixed-order reductions repeat exactly
+    assert np.array_equal(s.reduce(), s.reduce())
+
+
+def test_checkpoint_resume_bitexact(torch):
+    mask = inputs.spheres_3d(24, 0.35, rmin=2, rmax=6, seed=14)[0]
+    g = (1e-6, 0, 0)
+    t = _tiles(mask, 19)
+    a = lbm.Solver(t, lattice=19, tau=0.7, g=g)
+    a.init()
+    a.step(40)
+    fa = a.pdfs_export()
+    b = lbm.Solver(t, lattice=19, tau=0.7, g=g)
+    b.init()
+    b.step(20)
+    ck = b.pdfs_export().clone()
+    c = lbm.Solver(t, lattice=19, tau=0.7, g=g)
+    c.pdfs_import(ck)
+    c.step(20)
+    assert torch.equal(fa, c.pdfs_export())
+    assert a.step_count == 40 and c.step_count == 20
+
+
+def test_degenerate_geometries(torch):
+    # all solid: no tiles, every call succeeds and fields are zero
+    mask = np.ones((8, 8, 8), bool)
+    f, r, v, s = _gpu_run(torch, mask, 19, 0.7, (1e-6, 0, 0), 3, (1, 1, 1))
+    assert s.tiles.info["n_ftiles"] == 0 and not f.any() and not r.any()
+    # a single fluid node bounces everything back: f* stays the same closed form
+    mask = np.ones((8, 8, 8), bool)
+    mask[3, 5, 2] = False
+    f0 = inputs.random_pdfs(19, mask, seed=15)
+    f, _, _, _ = _gpu_run(torch, mask, 19, 0.8, (1e-6, 2e-6, 0), 4, (1, 1, 1), f0=f0)
+    want = dense.step(19, mask, f0, 0.8, [1e-6, 2e-6, 0], 4, periodic=7)
+    assert np.max(np.abs(f - want)) <= 1e-15
+    # fully fluid periodic box
+    mask = np.zeros((8, 12, 16), bool)
+    rho, u = inputs.random_macro(mask, seed=16)
+    f, _, _, _ = _gpu_run(torch, mask, 19, 0.6, (1e-5, 0, 0), 50, (1, 1, 1), rho=rho, u=u)
+    want = dense.step(19, mask, dense.init(19, mask, rho=rho, u=u), 0.6, [1e-5, 0, 0], 50, periodic=7)
+    assert np.max(np.abs(f - want) / np.abs(want)) <= 1e-13
+
+
+def test_step_before_init_is_an_error(torch):
+    t = _tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0], 19)
+    s = lbm.Solver(t, lattice=19, tau=0.7)
+    with pytest.raises(lbm.LbmError) as e:
+        s.step(1)
+    assert e.value.code == lbm.LBM_ERR_STATE
+
+
+@pytest.mark.parametrize("storage,scale", [("f32", 0), ("f16", 12)])
+def test_offset_storage_permutation_bitexact(torch, storage, scale):
+    """Pure streaming moves stored offsets unchanged; with PDFs whose offsets
+    are representable in the storage type, GPU == oracle exactly."""
+    q = 19
+    mask = inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=2, periodic=(1, 0, 0))[0]
+    _, w, _ = dense.lattice(q)
+    rng = np.random.default_rng(17)
+    off = rng.uniform(-1e-3, 1e-3, size=(q,) + mask.shape)
+    if storage == "f32":
+        off = off.astype(np.float32).astype(np.float64)
+    else:
+        off = (off * 2.0 ** scale).astype(np.float16).astype(np.float64) / 2.0 ** scale
+    f0 = w[:, None, None, None] + off
+    f0[:, mask] = 0.0
+    f, _, _, _ = _gpu_run(torch, mask, q, math.inf, (0, 0, 0), 6, (1, 0, 0), f0=f0, storage=storage,
+                          f16_scale_log2=scale)
+    want = dense.step(q, mask, f0, math.inf, [0, 0, 0], 6, periodic=(1, 0, 0))
+    assert np.array_equal(f, want)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16", 2e-2)])
+def test_offset_storage_error_vs_fp64(torch, storage, tol):
+    """FP32 / FP16-offset storage with FP32 arithmetic: velocity error against
+    the FP64 oracle after 1000 steps (D3Q19 periodic porous crop)."""
+    mask = inputs.spheres_3d(32, 0.3, seed=8)[0]
+    g = (1e-6, 0.0, 0.0)
+    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 1, 1), storage=storage, f16_scale_log2=22)
+    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=7, nthreads=8)
+    _, uw = dense.moments(19, mask, want, g)
+    fl = ~mask
+    err = np.linalg.norm((v - uw)[:, fl]) / np.linalg.norm(uw[:, fl])
+    _log("offset storage", storage, "velocity rel-L2 error after 1000 steps:", err)
+    assert err <= tol

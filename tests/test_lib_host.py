@@ -1,0 +1,108 @@
+"""Host-side checks of liblbm (no GPU needed): the library loads, exports
+every function ``include/lbm.h`` declares, its tiling equals the NumPy tiling
+oracle bit for bit, its lattice equals the oracle's, and host-side argument
+validation reports the documented error codes."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from oracle import tiles as otiles
+from paper_1703_08015_amd import inputs, lbm
+
+
+def test_library_exports_every_declared_symbol():
+    names = lbm.header_functions()
+    assert len(names) >= 20
+    L = lbm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_lattice_matches_oracle(q):
+    c, w, opp = lbm.lattice(q)
+    c2, w2, opp2 = dense.lattice(q)
+    assert np.array_equal(c, c2) and np.array_equal(w, w2) and np.array_equal(opp, opp2)
+
+
+def _masks():
+    yield "channel", inputs.channel_2d(64, 64, seed=0)[0], (16, 16, 1), (1, 0, 0)
+    yield "channel_ragged", inputs.channel_2d(48, 37, porosity=0.7, seed=3)[0], (16, 16, 1), (1, 0, 0)
+    yield "spheres", inputs.spheres_3d(32, 0.3, seed=1)[0], (4, 4, 4), (1, 1, 1)
+    yield "spheres_ragged", inputs.spheres_3d((21, 18, 13), 0.5, rmin=2, rmax=5, seed=2,
+                                             periodic=(0, 0, 0))[0], (4, 4, 4), (0, 0, 0)
+    yield "spheres_tall", inputs.spheres_3d((16, 12, 24), 0.4, rmin=2, rmax=5, seed=4)[0], (4, 4, 8), (1, 1, 1)
+    yield "vessel", inputs.vessel_tree(64, 0.08, r_root=5, r_leaf=2, seed=5)[0], (4, 4, 4), (1, 1, 1)
+
+
+@pytest.mark.parametrize("name,mask,tile,periodic", list(_masks()), ids=lambda v: v if isinstance(v, str) else "")
+def test_tiles_bitexact_vs_oracle(name, mask, tile, periodic):
+    t = lbm.Tiles(mask, tile, periodic)
+    e = t.export()
+    o = otiles.tile(mask, tile, periodic)
+    for k in ("tile_map", "tile_coord", "nbr", "fluid"):
+        assert np.array_equal(e[k], o[k]), k
+    i = t.info
+    assert i["n_ftiles"] == o["n_ftiles"] and i["n_fluid"] == o["n_fluid"] and i["n_tiles"] == o["n_tiles"]
+    assert i["phi"] == o["phi"] and math.isclose(i["phi_t"], o["phi_t"], rel_tol=1e-15)
+    assert tuple(i["grid"]) == tuple(o["grid"])
+
+
+def test_tiles_concat_offsets_rows():
+    a = inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0]
+    b = inputs.spheres_3d((8, 12, 16), 0.5, rmin=2, rmax=4, seed=2)[0]
+    ta, tb = lbm.Tiles(a), lbm.Tiles(b)
+    tc = lbm.Tiles.concat([ta, tb])
+    ea, eb, ec = ta.export(), tb.export(), tc.export()
+    na = ta.info["n_ftiles"]
+    assert tc.info["n_samples"] == 2 and tc.info["n_ftiles"] == na + tb.info["n_ftiles"]
+    assert np.array_equal(ec["nbr"][:27 * na], ea["nbr"])
+    assert np.array_equal(ec["nbr"][27 * na:], np.where(eb["nbr"] < 0, -1, eb["nbr"] + na))
+    assert np.array_equal(ec["fluid"], np.concatenate([ea["fluid"], eb["fluid"]]))
+    assert np.array_equal(ec["tile_map"], np.concatenate([ea["tile_map"],
+                                                          np.where(eb["tile_map"] < 0, -1, eb["tile_map"] + na)]))
+
+
+def test_tiling_errors():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Tiles(np.zeros((4, 4, 6), bool), (4, 4, 4), (1, 0, 0))
+    assert e.value.code == lbm.LBM_ERR_SHAPE
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Tiles(np.zeros((4, 4, 8), bool), (8, 8, 8), (1, 1, 1))
+    assert e.value.code == lbm.LBM_ERR_UNSUPPORTED
+    t = lbm.Tiles(np.ones((8, 8, 8), bool))
+    assert t.info["n_ftiles"] == 0 and t.info["n_fluid"] == 0
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), lbm.LBM_ERR_ARG),
+    (dict(tau=0.2), lbm.LBM_ERR_ARG),
+    (dict(tau=float("nan")), lbm.LBM_ERR_ARG),
+    (dict(tau=-math.inf), lbm.LBM_ERR_ARG),
+    (dict(rho0=0.0), lbm.LBM_ERR_ARG),
+    (dict(g=(float("inf"), 0, 0)), lbm.LBM_ERR_ARG),
+    (dict(storage=7), lbm.LBM_ERR_ARG),
+    (dict(f16_scale_log2=40), lbm.LBM_ERR_ARG),
+    (dict(lattice=9), lbm.LBM_ERR_UNSUPPORTED),
+    (dict(tiles_per_block=3), lbm.LBM_ERR_UNSUPPORTED),
+])
+def test_param_validation(kw, code):
+    t = lbm.Tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0])
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.workspace_bytes(t, **kw)
+    assert e.value.code == code
+
+
+def test_workspace_size_counts_fluid_nodes_only():
+    m = inputs.spheres_3d(32, 0.3, seed=1)[0]
+    t = lbm.Tiles(m)
+    for storage, sd in (("f64", 8), ("f32", 4), ("f16", 2)):
+        n = lbm.workspace_bytes(t, storage=storage, tau=0.7)
+        pdf = 2 * 19 * sd * t.info["n_fluid"]
+        # two copies of the fluid nodes' PDFs (each tile region padded to 128 bytes), the FP64
+        # residual reference velocity (24 bytes per fluid node) and under 200 bytes of tables per tile
+        nft = t.info["n_ftiles"]
+        assert pdf < n < pdf + 24 * t.info["n_fluid"] + (2 * 128 + 200) * nft + 8192
+    assert lbm.workspace_bytes(t, tau=math.inf) > 0
