@@ -58,9 +58,11 @@ def traffic_for(kernel_name, workload_key):
     rec = table.get(kernel_name, {}).get(workload_key)
     if not rec:
         return None
-    with open(os.path.join(ROOT, "paper_1703_08015_amd", "csrc", "kernels.hip"), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    if rec.get("kernels_hip_sha256") != sha:
+    src = b""
+    for rel in rec.get("source_files", []):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            src += fh.read()
+    if not src or rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -81,6 +83,29 @@ def cpu_baseline(mask, args):
                       "%.1f s" % (args.cpu_steps, args.n, nf, dt)}
 
 
+def copy_reference(torch, gib, reps=20):
+    """Achievable HBM bandwidth of a plain elementwise device copy (dst = src * 1)
+    of known size; the same kernel calibrates the rocprofv3 byte counters."""
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": round(ms, 4),
+            "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,9 +119,14 @@ def main():
     ap.add_argument("--tau", type=float, default=0.7)
     ap.add_argument("--g", type=float, default=1e-6)
     ap.add_argument("--tiles-per-block", type=int, default=0)
+    ap.add_argument("--order", default="morton", choices=["morton", "rowmajor"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "scalar"])
+    ap.add_argument("--store", default="auto", choices=["auto", "regular", "nontemporal"])
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-gib", type=float, default=1.0,
+                    help="size of the device copy reference (read + write each this many GiB); 0 = skip")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -109,11 +139,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    copy_ref = copy_reference(torch, args.copy_gib) if args.copy_gib > 0 else None
     mask, phi, desc = workload(args)
     tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
     info = tiles.info
     solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
-                        tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2)
+                        tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
+                        tile_order=args.order, step_kernel=args.kernel, store_policy=args.store)
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()
@@ -141,7 +173,10 @@ def main():
     alg_bytes = nf * 2 * q * sd  # Eq. (10) per non-solid node, per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     kernel = "k_step<D3Q19,4x4x4,%s>" % args.storage
-    wkey = "%s_%d_%s" % (args.geometry, args.n, args.storage)
+    wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
+                                        "scalar" if args.kernel == "auto" else args.kernel, args.order,
+                                        "nt" if args.store in ("auto", "nontemporal") else "regular",
+                                        args.tiles_per_block or 4)
     traffic = traffic_for(kernel, wkey)
     out = {
         "metric": METRIC,
@@ -161,6 +196,7 @@ def main():
             "n_fluid": nf, "n_ftiles": info["n_ftiles"], "n_tiles": info["n_tiles"],
             "phi": round(info["phi"], 4), "phi_t": round(info["phi_t"], 4),
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
+            "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -170,6 +206,9 @@ def main():
         },
         "bu_eq43": round(mlups * 1e6 * 2 * q * sd / (HBM_PEAK_GBS * 1e9), 4),
     }
+    if copy_ref:
+        out["copy_reference"] = copy_ref
+        out["roofline"]["frac_of_copy"] = round(achieved / copy_ref["gbs"], 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mask, args)
     print(json.dumps(out), flush=True)

@@ -83,7 +83,29 @@ typedef struct {
   double rho0;             /* reference density: cold start and offset storage */
   int32_t f16_scale_log2;  /* s of LBM_F16_OFFSET (0..24) */
   int32_t tiles_per_block; /* waves per workgroup for the D3Q19 step: 1, 2, 4 or 8 (0 = 4) */
+  int32_t tile_order;      /* LBM_ORDER_*: order in which tiles are stored and processed */
+  int32_t step_kernel;     /* LBM_KERNEL_*: which step kernel runs */
+  int32_t store_policy;    /* LBM_STORE_*: cache policy of the step's PDF stores */
+  int32_t reserved;        /* set to 0 */
 } lbm_params;
+
+/* Cache policy of the PDF stores of the step: a stored value is next read one
+ * step later, after the whole working set has streamed through the caches, so
+ * the default writes it non-temporally and leaves L2 to the halo reads. */
+#define LBM_STORE_AUTO 0
+#define LBM_STORE_REGULAR 1
+#define LBM_STORE_NONTEMPORAL 2
+
+/* Tile order inside the solver (the exported tiling is always row-major).
+ * Morton order keeps neighbour tiles close in memory and in time. */
+#define LBM_ORDER_MORTON 0
+#define LBM_ORDER_ROWMAJOR 1
+
+/* Step kernel: AUTO picks the scalar-mask D3Q19 kernel for 4x4x4 tiles and
+ * the generic kernel (LDS-staged neighbour records) otherwise. */
+#define LBM_KERNEL_AUTO 0
+#define LBM_KERNEL_GENERIC 1
+#define LBM_KERNEL_SCALAR_MASK 2
 
 /* Velocity set and weights of a lattice (q = 9 or 19): c[3*q] (x, y, z per
  * direction), w[q], opp[q].  Standard D2Q9 / D3Q19 sets; the paper's Fig. 1

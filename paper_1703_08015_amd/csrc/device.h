@@ -61,6 +61,7 @@ struct Store<LBM_F64> {
   static constexpr bool offset = false;
   __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
   __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
+  __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float) { __builtin_nontemporal_store(v, p + i); }
 };
 
 template <>
@@ -70,6 +71,7 @@ struct Store<LBM_F32_OFFSET> {
   static constexpr bool offset = true;
   __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
   __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
+  __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float) { __builtin_nontemporal_store(v, p + i); }
 };
 
 template <>
@@ -81,6 +83,10 @@ struct Store<LBM_F16_OFFSET> {
   __device__ static __forceinline__ R load(const T *p, int64_t i, float inv) { return __half2float(p[i]) * inv; }
   __device__ static __forceinline__ void store(T *p, int64_t i, R v, float scale) {
     p[i] = __float2half_rn(v * scale);
+  }
+  __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float scale) {
+    const __half h = __float2half_rn(v * scale);
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, h), reinterpret_cast<uint16_t *>(p) + i);
   }
 };
 
@@ -105,6 +111,26 @@ struct SampleRec {
   int64_t n_fluid;  // fluid nodes of this sample
   int32_t shape[3]; // nx, ny, nz
   int32_t pad;
+};
+
+// Compact record of a tile for the scalar-mask D3Q19 kernel: region offset,
+// fluid-node count and fluid mask in one 16-byte scalar load.  Index n_ftiles
+// is an all-solid sentinel that empty neighbours point at.
+struct NbRec {
+  uint32_t off;
+  uint32_t n;
+  uint64_t mask;
+  int32_t sample;
+  int32_t pad;
+};
+
+// Per-sample collision constants of the D3Q19 step (host-prepared):
+// a_i = 3w + 9(1 - w/2) c_i.g and b_i = 3(1 - w/2) c_i.g, w = 1/tau.
+struct CollideCoef {
+  double g[3];
+  double omega;
+  double a[19], b[19];
+  float af[19], bf[19];
 };
 
 // Arguments shared by the per-tile kernels.

@@ -9,6 +9,8 @@ namespace lbm {
 
 struct TileArgs;
 struct SampleRec;
+struct CollideCoef;
+struct NbRec;
 
 // Compile-time variant of the kernels: lattice, tile shape, storage form and
 // waves per workgroup of the step kernel.
@@ -24,6 +26,13 @@ int storage_bytes(int storage);
 
 hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileArgs &a, double omega,
                        hipStream_t s);
+// D3Q19 4x4x4 step with scalar-mask addressing (step19.hip); needs PDF entry
+// indices below 2^32.
+bool step19_supported(const Variant &v);
+// nrec: n_ftiles + 1 records (the last one all-solid); nrow: 20 per tile, the
+// 18 neighbour slots of the D3Q19 gather in kernel order (+2 padding).
+hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
+                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, hipStream_t s);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,
                        hipStream_t s);
 hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, double *rho, double *u,

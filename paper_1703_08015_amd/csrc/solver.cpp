@@ -4,6 +4,7 @@
 // enqueues the kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,13 +24,50 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every workspace array, plus the host tables to upload.
 struct Plan {
-  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, part, out, uref, total;
+  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, part, out, uref, total;
   int64_t entries = 0;  // PDF entries per copy (with region alignment padding)
+  // device tables in the solver's internal tile order
   std::vector<lbm::TileRec> rec_h;
-  std::vector<int32_t> pre_h;
+  std::vector<uint64_t> fluid_h;
+  std::vector<int32_t> pre_h, nbr_h, coord_h;
   std::vector<int64_t> nbase_h;
   std::vector<lbm::SampleRec> samples_h;
+  std::vector<lbm::CollideCoef> coef_h;
+  // scalar-mask D3Q19 kernel: compact records (+ all-solid sentinel) and rows
+  std::vector<lbm::NbRec> nrec_h;
+  std::vector<int32_t> nrow_h;
 };
+
+// Neighbour slots (3x3x3 index) of the D3Q19 gather, in the order the
+// scalar-mask kernel reads its compact neighbour row.
+constexpr int kGatherSlots[18] = {4, 22, 10, 16, 12, 14, 1, 3, 5, 7, 9, 11, 15, 17, 19, 21, 23, 25};
+
+// Morton (Z-order) key of a tile coordinate.
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+  };
+  return spread(x) | spread(y) << 1 | spread(z) << 2;
+}
+
+void fill_coef(lbm::CollideCoef &c, const double g[3], double omega) {
+  const double fo = 1.0 - 0.5 * omega;
+  for (int a = 0; a < 3; ++a) c.g[a] = g[a];
+  c.omega = omega;
+  for (int i = 0; i < 19; ++i) {
+    const double cg = lbm::D3Q19::C[i][0] * g[0] + lbm::D3Q19::C[i][1] * g[1] + lbm::D3Q19::C[i][2] * g[2];
+    c.a[i] = 3.0 * omega + 9.0 * fo * cg;
+    c.b[i] = 3.0 * fo * cg;
+    c.af[i] = (float)c.a[i];
+    c.bf[i] = (float)c.b[i];
+  }
+}
 
 int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
   if (!t || !p) return set_error(LBM_ERR_ARG, "NULL tiles or params");
@@ -42,6 +80,12 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
     if (!std::isfinite(p->g[a])) return set_error(LBM_ERR_ARG, "g[%d] is not finite", a);
   if (p->f16_scale_log2 < 0 || p->f16_scale_log2 > 24)
     return set_error(LBM_ERR_ARG, "f16_scale_log2 = %d outside 0..24", p->f16_scale_log2);
+  if (p->tile_order != LBM_ORDER_MORTON && p->tile_order != LBM_ORDER_ROWMAJOR)
+    return set_error(LBM_ERR_ARG, "tile_order = %d", p->tile_order);
+  if (p->step_kernel < LBM_KERNEL_AUTO || p->step_kernel > LBM_KERNEL_SCALAR_MASK)
+    return set_error(LBM_ERR_ARG, "step_kernel = %d", p->step_kernel);
+  if (p->store_policy < LBM_STORE_AUTO || p->store_policy > LBM_STORE_NONTEMPORAL)
+    return set_error(LBM_ERR_ARG, "store_policy = %d", p->store_policy);
   int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
   if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
   v->q = p->lattice;
@@ -60,24 +104,64 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   const int q = v.q, sd = lbm::storage_bytes(v.storage), W = t->words;
   const int64_t A = 128 / sd;  // entries per 128-byte line
   const int64_t nft = t->n_ftiles;
+  const double omega = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
   try {
+    // internal order: per sample, Morton order of tile coordinates (or row-major)
+    std::vector<int64_t> perm((size_t)nft), inv((size_t)nft);
+    for (int64_t k = 0; k < nft; ++k) perm[(size_t)k] = k;
+    if (p->tile_order == LBM_ORDER_MORTON) {
+      std::vector<uint64_t> key((size_t)nft);
+      for (int64_t k = 0; k < nft; ++k)
+        key[(size_t)k] = morton3((uint32_t)t->coord[(size_t)(3 * k)], (uint32_t)t->coord[(size_t)(3 * k + 1)],
+                                 (uint32_t)t->coord[(size_t)(3 * k + 2)]);
+      for (const lbm::Sample &S : t->samples)
+        std::stable_sort(perm.begin() + S.tile0, perm.begin() + S.tile0 + S.n_ftiles,
+                         [&](int64_t x, int64_t y) { return key[(size_t)x] < key[(size_t)y]; });
+    }
+    for (int64_t k = 0; k < nft; ++k) inv[(size_t)perm[(size_t)k]] = k;
+
     P.rec_h.resize((size_t)nft);
+    P.fluid_h.resize((size_t)(nft * W));
     P.pre_h.resize((size_t)(nft * W));
+    P.nbr_h.resize((size_t)(nft * 27));
+    P.coord_h.resize((size_t)(nft * 3));
     P.nbase_h.resize((size_t)nft);
     int64_t off = 0, nb = 0;
     for (int64_t k = 0; k < nft; ++k) {
+      const int64_t c = perm[(size_t)k];  // canonical index of internal tile k
       int n = 0;
       for (int w = 0; w < W; ++w) {
+        const uint64_t m = t->fluid[(size_t)(c * W + w)];
+        P.fluid_h[(size_t)(k * W + w)] = m;
         P.pre_h[(size_t)(k * W + w)] = n;
-        n += __builtin_popcountll(t->fluid[(size_t)(k * W + w)]);
+        n += __builtin_popcountll(m);
       }
-      P.rec_h[(size_t)k] = lbm::TileRec{off, n, t->sample_of[(size_t)k]};
+      for (int j = 0; j < 27; ++j) {
+        const int32_t o = t->nbr[(size_t)(c * 27 + j)];
+        P.nbr_h[(size_t)(k * 27 + j)] = o < 0 ? -1 : (int32_t)inv[(size_t)o];
+      }
+      for (int a = 0; a < 3; ++a) P.coord_h[(size_t)(k * 3 + a)] = t->coord[(size_t)(c * 3 + a)];
+      P.rec_h[(size_t)k] = lbm::TileRec{off, n, t->sample_of[(size_t)c]};
       P.nbase_h[(size_t)k] = nb;
       off += ((int64_t)q * n + A - 1) / A * A;
       nb += n;
     }
     P.entries = off;
+    if (q == 19 && W == 1) {
+      P.nrec_h.resize((size_t)nft + 1);
+      P.nrow_h.assign((size_t)(nft * 20), (int32_t)nft);
+      for (int64_t k = 0; k < nft; ++k) {
+        const lbm::TileRec &r = P.rec_h[(size_t)k];
+        P.nrec_h[(size_t)k] = lbm::NbRec{(uint32_t)r.off, (uint32_t)r.n, P.fluid_h[(size_t)k], r.sample, 0};
+        for (int j = 0; j < 18; ++j) {
+          const int32_t o = P.nbr_h[(size_t)(k * 27 + kGatherSlots[j])];
+          P.nrow_h[(size_t)(k * 20 + j)] = o < 0 ? (int32_t)nft : o;
+        }
+      }
+      P.nrec_h[(size_t)nft] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
+    }
     P.samples_h.resize(t->samples.size());
+    P.coef_h.resize(t->samples.size());
     for (size_t s = 0; s < t->samples.size(); ++s) {
       const lbm::Sample &S = t->samples[s];
       lbm::SampleRec &R = P.samples_h[s];
@@ -92,6 +176,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
       R.n_ftiles = S.n_ftiles;
       R.nbase0 = S.n_ftiles ? P.nbase_h[(size_t)S.tile0] : 0;
       R.n_fluid = S.n_fluid;
+      fill_coef(P.coef_h[s], p->g, omega);
     }
   } catch (const std::bad_alloc &) {
     return set_error(LBM_ERR_NOMEM, "out of host memory planning the workspace");
@@ -112,6 +197,9 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.coord = take((size_t)(nft * 3) * sizeof(int32_t));
   P.nbase = take((size_t)nft * sizeof(int64_t));
   P.samples = take(t->samples.size() * sizeof(lbm::SampleRec));
+  P.coef = take(t->samples.size() * sizeof(lbm::CollideCoef));
+  P.nrec = take(P.nrec_h.size() * sizeof(lbm::NbRec));
+  P.nrow = take(P.nrow_h.size() * sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
   P.out = take(t->samples.size() * 4 * sizeof(double));
   P.uref = take((size_t)(3 * (t->n_fluid > 0 ? t->n_fluid : 1)) * sizeof(double));
@@ -136,6 +224,11 @@ struct lbm_solver {
   int64_t dense_nodes = 0;
   std::vector<lbm::SampleRec> samples_h;
   lbm::SampleRec *samples_d = nullptr;
+  std::vector<lbm::CollideCoef> coef_h;
+  lbm::CollideCoef *coef_d = nullptr;
+  const lbm::NbRec *nrec_d = nullptr;
+  const int32_t *nrow_d = nullptr;
+  bool scalar_mask = false;  // which step kernel runs
   double *part = nullptr, *out = nullptr, *uref = nullptr;
   std::vector<double> out_h;
 };
@@ -206,6 +299,17 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->dense_nodes = t->n_nodes;
   s->samples_h = P.samples_h;
   s->samples_d = reinterpret_cast<lbm::SampleRec *>(base + P.samples);
+  s->coef_h = P.coef_h;
+  s->coef_d = reinterpret_cast<lbm::CollideCoef *>(base + P.coef);
+  s->nrec_d = reinterpret_cast<const lbm::NbRec *>(base + P.nrec);
+  s->nrow_d = reinterpret_cast<const int32_t *>(base + P.nrow);
+  const bool fits32 = P.entries < (int64_t(1) << 32);
+  if (p->step_kernel == LBM_KERNEL_SCALAR_MASK && !(lbm::step19_supported(v) && fits32)) {
+    delete s;
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the scalar-mask kernel needs D3Q19, 4x4x4 tiles and "
+                                          "fewer than 2^32 PDF entries per copy");
+  }
+  s->scalar_mask = p->step_kernel != LBM_KERNEL_GENERIC && lbm::step19_supported(v) && fits32;
   s->part = reinterpret_cast<double *>(base + P.part);
   s->out = reinterpret_cast<double *>(base + P.out);
   s->uref = reinterpret_cast<double *>(base + P.uref);
@@ -232,10 +336,13 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   hipError_t e = hipSuccess;
   const int64_t nft = t->n_ftiles, W = t->words;
   if (e == hipSuccess) e = up(P.rec, P.rec_h.data(), (size_t)nft * sizeof(lbm::TileRec));
-  if (e == hipSuccess) e = up(P.fluid, t->fluid.data(), (size_t)(nft * W) * sizeof(uint64_t));
+  if (e == hipSuccess) e = up(P.fluid, P.fluid_h.data(), (size_t)(nft * W) * sizeof(uint64_t));
   if (e == hipSuccess) e = up(P.pre, P.pre_h.data(), (size_t)(nft * W) * sizeof(int32_t));
-  if (e == hipSuccess) e = up(P.nbr, t->nbr.data(), (size_t)(nft * 27) * sizeof(int32_t));
-  if (e == hipSuccess) e = up(P.coord, t->coord.data(), (size_t)(nft * 3) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.nbr, P.nbr_h.data(), (size_t)(nft * 27) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.coord, P.coord_h.data(), (size_t)(nft * 3) * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.coef, P.coef_h.data(), P.coef_h.size() * sizeof(lbm::CollideCoef));
+  if (e == hipSuccess) e = up(P.nrec, P.nrec_h.data(), P.nrec_h.size() * sizeof(lbm::NbRec));
+  if (e == hipSuccess) e = up(P.nrow, P.nrow_h.data(), P.nrow_h.size() * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.nbase, P.nbase_h.data(), (size_t)nft * sizeof(int64_t));
   if (e == hipSuccess) e = up(P.samples, P.samples_h.data(), P.samples_h.size() * sizeof(lbm::SampleRec));
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host tables may be freed after return
@@ -259,9 +366,13 @@ extern "C" int lbm_set_sample_force(lbm_solver *s, const double *g) {
   if (!s || !g) return set_error(LBM_ERR_ARG, "lbm_set_sample_force: NULL argument");
   for (int k = 0; k < 3 * s->n_samples; ++k)
     if (!std::isfinite(g[k])) return set_error(LBM_ERR_ARG, "lbm_set_sample_force: g[%d] not finite", k);
-  for (int k = 0; k < s->n_samples; ++k)
+  for (int k = 0; k < s->n_samples; ++k) {
     for (int a = 0; a < 3; ++a) s->samples_h[(size_t)k].g[a] = g[3 * k + a];
+    fill_coef(s->coef_h[(size_t)k], &g[3 * k], s->omega);
+  }
   HIP_TRY(hipMemcpyAsync(s->samples_d, s->samples_h.data(), s->samples_h.size() * sizeof(lbm::SampleRec),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->coef_d, s->coef_h.data(), s->coef_h.size() * sizeof(lbm::CollideCoef),
                          hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return LBM_OK;
@@ -283,7 +394,11 @@ extern "C" int lbm_step(lbm_solver *s, int32_t n) {
   if (n < 0) return set_error(LBM_ERR_ARG, "lbm_step: n = %d", n);
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_step: call lbm_init or lbm_pdfs_import first");
   for (int32_t k = 0; k < n; ++k) {
-    HIP_TRY(lbm::launch_step(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->omega, s->stream));
+    if (s->scalar_mask)
+      HIP_TRY(lbm::launch_step19(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->nrec_d, s->nrow_d,
+                                 s->coef_d, s->p.store_policy != LBM_STORE_REGULAR, s->stream));
+    else
+      HIP_TRY(lbm::launch_step(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->omega, s->stream));
     s->cur ^= 1;
     ++s->steps;
   }

@@ -1,0 +1,220 @@
+// D3Q19 fused step on 4x4x4 tiles, one wavefront per tile, with all tile
+// bookkeeping on the scalar unit.
+//
+// Gather (two-copy method, Sec. 3, Fig. 5): lane l = x + 4y + 16z pulls f_i
+// from the node l - c_i.  For a direction i the lanes fall into at most four
+// regions by which axes the source wraps across: the tile itself, the face
+// neighbours and the edge neighbour (D3Q19 has no corner directions).  In a
+// region whose tile has fluid mask M, the source lane is s = l - d for a
+// constant shift d, so shifting M by d on the scalar unit turns
+//   "is the source non-solid"   into bit l of the shifted mask, and
+//   "rank of the source"        into v_mbcnt of the shifted mask (number of
+//                                set bits below lane l), plus a scalar
+//                                correction for bits shifted out below 0.
+// Two v_mbcnt give a region's entry index; regions and the half-way
+// bounce-back (Sec. 3.2: propagation only between non-solid nodes) are merged
+// with v_cndmask on scalar lane masks.  Neighbour records (region offset,
+// node count, fluid mask) come through scalar loads; nothing is staged in LDS
+// and there is no barrier.
+//
+// Collision (Eqs. 2, 3, 5, 7 with Guo forcing) is regrouped so that each
+// direction costs four fused multiply-adds:
+//   out_i = (1-w) f_i + w_i [P + rho (b_i + cu_i (a_i + h cu_i))]
+// with cu_i = c_i.u, h = 9w/2, a_i = 3w + 9(1-w/2) c_i.g, b_i = 3(1-w/2) c_i.g
+// (per-sample constants prepared on the host) and, per node,
+// P = w rho (1 - 3/2 u.u) - 3(1-w/2) rho u.g for the full form and
+// P = w (drho - 3/2 rho u.u) - 3(1-w/2) rho u.g for the offset forms.
+#include "device.h"
+#include "kernels.h"
+
+namespace lbm {
+namespace {
+
+// Lanes of a 4x4x4 tile whose source x - c wraps into a neighbour exactly
+// along the axes flagged by (wx, wy, wz).
+constexpr uint64_t region(int cx, int cy, int cz, int wx, int wy, int wz) {
+  uint64_t m = 0;
+  for (int l = 0; l < 64; ++l) {
+    const int x = l & 3, y = (l >> 2) & 3, z = l >> 4;
+    const bool ax = (cx > 0 && x == 0) || (cx < 0 && x == 3);
+    const bool ay = (cy > 0 && y == 0) || (cy < 0 && y == 3);
+    const bool az = (cz > 0 && z == 0) || (cz < 0 && z == 3);
+    if (ax == (wx != 0) && ay == (wy != 0) && az == (wz != 0)) m |= 1ull << l;
+  }
+  return m;
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t shifted(uint64_t m) {
+  if constexpr (D >= 0)
+    return m << D;
+  else
+    return m >> (-D);
+}
+
+// set bits of m below -D (those a right shift by -D drops), 0 for D >= 0
+template <int D>
+__device__ __forceinline__ uint32_t dropped(uint64_t m) {
+  if constexpr (D >= 0)
+    return 0u;
+  else
+    return (uint32_t)__popcll(m & ((1ull << (-D)) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t x, uint32_t acc) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(x >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)x, acc));
+}
+
+// lanes set in the scalar mask take if_set, the others if_clear
+__device__ __forceinline__ uint32_t select_lanes(uint64_t lanes, uint32_t if_set, uint32_t if_clear) {
+  uint32_t r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(lanes));
+  return r;
+}
+
+// The 18 neighbour slots a D3Q19 tile pulls from (6 faces, 12 edges; the
+// 3x3x3 index k = (dx+1) + 3(dy+1) + 9(dz+1)), in the order of the compact
+// neighbour row uploaded for this kernel.
+constexpr int kSlots[18] = {4, 22, 10, 16, 12, 14, 1, 3, 5, 7, 9, 11, 15, 17, 19, 21, 23, 25};
+constexpr int slot_of(int k) {
+  for (int j = 0; j < 18; ++j)
+    if (kSlots[j] == k) return j;
+  return -1;
+}
+
+template <int S, int WPB, bool NT>
+__global__ void __launch_bounds__(64 * WPB)
+    k_step19(const void *__restrict__ src_, void *__restrict__ dst_, TileArgs a, const NbRec *__restrict__ nrec,
+             const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
+  using L = D3Q19;
+  using St = Store<S>;
+  using T = typename St::T;
+  using R = typename St::R;
+  const T *__restrict__ src = static_cast<const T *>(src_);
+  T *__restrict__ dst = static_cast<T *>(dst_);
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if (tile >= a.n_waves) return;
+  // own record and the 18 neighbour records (empty neighbours point at an
+  // all-solid sentinel record, so every load is unconditional)
+  const NbRec own = nrec[tile];
+  NbRec nb[18];
+  static_for<18>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    nb[j] = nrec[nrow[tile * 20 + j]];
+  });
+  const uint64_t M = own.mask;
+  if (!((M >> lane) & 1ull)) return;
+  const uint32_t ooff = own.off, on = own.n;
+  const uint32_t rank = mbcnt(M, 0u);
+
+  R f[19];
+  static_for<19>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    if constexpr (i == 0) {
+      f[0] = St::load(src, (int64_t)(ooff + rank), a.f16_inv);
+    } else {
+      constexpr int d0 = cx + 4 * cy + 16 * cz;
+      constexpr uint64_t R0 = region(cx, cy, cz, 0, 0, 0);
+      const uint64_t X0 = shifted<d0>(M);
+      uint64_t from_fluid = X0 & R0;
+      uint32_t e = mbcnt(X0, ooff + (uint32_t)i * on + dropped<d0>(M));
+      static_for<8>([&](auto Wc) {
+        constexpr int w = decltype(Wc)::value;
+        constexpr int wx = w & 1, wy = (w >> 1) & 1, wz = (w >> 2) & 1;
+        if constexpr (w != 0 && (!wx || cx) && (!wy || cy) && (!wz || cz)) {
+          constexpr uint64_t Rr = region(cx, cy, cz, wx, wy, wz);
+          constexpr int dr = d0 - (wx ? 4 * cx : 0) - (wy ? 16 * cy : 0) - (wz ? 64 * cz : 0);
+          constexpr int k = 13 + (wx ? -cx : 0) + 3 * (wy ? -cy : 0) + 9 * (wz ? -cz : 0);
+          const NbRec &r = nb[slot_of(k)];
+          const uint64_t Xr = shifted<dr>(r.mask);
+          from_fluid |= Xr & Rr;
+          e = select_lanes(Rr, mbcnt(Xr, r.off + (uint32_t)i * r.n + dropped<dr>(r.mask)), e);
+        }
+      });
+      // half-way bounce-back: a solid or missing source returns the node's own opposite value
+      e = select_lanes(from_fluid, e, ooff + (uint32_t)L::Opp[i] * on + rank);
+      f[i] = St::load(src, (int64_t)e, a.f16_inv);
+    }
+  });
+
+  const CollideCoef &cc = coef[own.sample];
+  R sum = 0, jx = 0, jy = 0, jz = 0;
+  static_for<19>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    sum += f[i];
+    if constexpr (cx > 0) jx += f[i];
+    if constexpr (cx < 0) jx -= f[i];
+    if constexpr (cy > 0) jy += f[i];
+    if constexpr (cy < 0) jy -= f[i];
+    if constexpr (cz > 0) jz += f[i];
+    if constexpr (cz < 0) jz -= f[i];
+  });
+  const R gx = (R)cc.g[0], gy = (R)cc.g[1], gz = (R)cc.g[2];
+  const R om = (R)cc.omega, om1 = R(1) - om, fo = R(1) - R(0.5) * om, h = R(4.5) * om;
+  const R rho = St::offset ? (R)a.rho0 + sum : sum;
+  const R inv = R(1) / rho;
+  const R ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R ug = ux * gx + uy * gy + uz * gz;
+  const R P = (St::offset ? om * (sum - R(1.5) * rho * uu) : om * rho * (R(1) - R(1.5) * uu)) -
+              R(3) * fo * rho * ug;
+  const R wr1 = R(L::Wt[1]) * rho, wr2 = R(L::Wt[7]) * rho;
+  const R wp1 = R(L::Wt[1]) * P, wp2 = R(L::Wt[7]) * P;
+
+  static_for<19>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    R out;
+    if constexpr (i == 0) {
+      out = om1 * f[0] + R(L::Wt[0]) * P;
+    } else {
+      const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+      const R ai = St::offset ? (R)cc.af[i] : (R)cc.a[i];
+      const R bi = St::offset ? (R)cc.bf[i] : (R)cc.b[i];
+      const R t2 = cu * (ai + h * cu) + bi;
+      constexpr bool face = (cx != 0) + (cy != 0) + (cz != 0) == 1;
+      out = om1 * f[i] + ((face ? wr1 : wr2) * t2 + (face ? wp1 : wp2));
+    }
+    T *blk = dst + (ooff + (uint32_t)i * on);
+    if constexpr (NT)
+      St::store_nt(blk, (int64_t)rank, out, a.f16_scale);
+    else
+      St::store(blk, (int64_t)rank, out, a.f16_scale);
+  });
+}
+
+}  // namespace
+
+bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
+
+hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
+                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, hipStream_t s) {
+  if (a.n_waves == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, coef);
+    return hipGetLastError();
+  };
+#define LBM_STEP19_NT(S, W) return nontemporal ? go(k_step19<S, W, true>) : go(k_step19<S, W, false>);
+#define LBM_STEP19_WPB(S)                  \
+  switch (v.wpb) {                         \
+    case 1: LBM_STEP19_NT(S, 1)            \
+    case 2: LBM_STEP19_NT(S, 2)            \
+    case 4: LBM_STEP19_NT(S, 4)            \
+    default: LBM_STEP19_NT(S, 8)           \
+  }
+  switch (v.storage) {
+    case LBM_F64: LBM_STEP19_WPB(LBM_F64)
+    case LBM_F32_OFFSET: LBM_STEP19_WPB(LBM_F32_OFFSET)
+    default: LBM_STEP19_WPB(LBM_F16_OFFSET)
+  }
+#undef LBM_STEP19_WPB
+#undef LBM_STEP19_NT
+}
+
+}  // namespace lbm

@@ -25,6 +25,9 @@ LBM_ERR_STATE = -6
 LBM_ERR_NOMEM = -7
 
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+ORDER = {"morton": 0, "rowmajor": 1}
+KERNEL = {"auto": 0, "generic": 1, "scalar": 2}
+STORE_POLICY = {"auto": 0, "regular": 1, "nontemporal": 2}
 
 
 class LbmError(RuntimeError):
@@ -48,7 +51,8 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
         ("g", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("f16_scale_log2", ctypes.c_int32),
-        ("tiles_per_block", ctypes.c_int32),
+        ("tiles_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32), ("step_kernel", ctypes.c_int32),
+        ("store_policy", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -182,7 +186,7 @@ class Tiles:
 
 
 def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
-                tiles_per_block=0):
+                tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto"):
     p = Params()
     p.lattice = lattice
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -192,6 +196,9 @@ def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0,
     p.rho0 = float(rho0)
     p.f16_scale_log2 = int(f16_scale_log2)
     p.tiles_per_block = int(tiles_per_block)
+    p.tile_order = ORDER[tile_order] if isinstance(tile_order, str) else int(tile_order)
+    p.step_kernel = KERNEL[step_kernel] if isinstance(step_kernel, str) else int(step_kernel)
+    p.store_policy = STORE_POLICY[store_policy] if isinstance(store_policy, str) else int(store_policy)
     return p
 
 
@@ -206,13 +213,15 @@ class Solver:
     """A solver on one tiling; device memory and stream come from torch."""
 
     def __init__(self, tiles, lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
-                 tiles_per_block=0, device="cuda", stream=None):
+                 tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", device="cuda",
+                 stream=None):
         import torch
 
         self.torch = torch
         self.tiles = tiles
         self.q = lattice
-        self.params = make_params(lattice, storage, tau, g, rho0, f16_scale_log2, tiles_per_block)
+        self.params = make_params(lattice, storage, tau, g, rho0, f16_scale_log2, tiles_per_block, tile_order,
+                                  step_kernel, store_policy)
         self.device = torch.device(device)
         n = ctypes.c_size_t()
         _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(self.params), ctypes.byref(n)),

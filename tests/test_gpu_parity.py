@@ -36,10 +36,10 @@ def _tiles(mask, q, tile=None, periodic=(1, 1, 1)):
 
 
 def _gpu_run(torch, mask, q, tau, g, steps, periodic, f0=None, rho=None, u=None, storage="f64", tile=None,
-             tpb=0, f16_scale_log2=20):
+             tpb=0, f16_scale_log2=20, kernel="auto", order="morton"):
     t = _tiles(mask, q, tile, periodic)
     s = lbm.Solver(t, lattice=q, storage=storage, tau=tau, g=g, tiles_per_block=tpb,
-                   f16_scale_log2=f16_scale_log2)
+                   f16_scale_log2=f16_scale_log2, step_kernel=kernel, tile_order=order)
     if f0 is not None:
         s.pdfs_import(torch.from_numpy(f0).cuda())
     else:
@@ -61,23 +61,28 @@ def _geoms(q):
         yield "ragged", inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=2, periodic=(1, 0, 0))[0], (1, 0, 0)
 
 
-@pytest.mark.parametrize("q", [9, 19])
-def test_permutation_mode_bitexact(torch, q):
+KERNELS = [(9, "generic", "rowmajor"), (9, "generic", "morton"), (19, "generic", "rowmajor"),
+           (19, "generic", "morton"), (19, "scalar", "morton"), (19, "scalar", "rowmajor")]
+
+
+@pytest.mark.parametrize("q,kernel,order", KERNELS)
+def test_permutation_mode_bitexact(torch, q, kernel, order):
     """tau = +inf, g = 0: the step only moves values, so GPU == oracle exactly."""
     for name, mask, per in _geoms(q):
-        _log("permutation", q, name, mask.shape)
+        _log("permutation", q, kernel, order, name, mask.shape)
         f0 = inputs.random_pdfs(q, mask, seed=21)
-        f, _, _, _ = _gpu_run(torch, mask, q, math.inf, (0, 0, 0), 7, per, f0=f0)
+        f, _, _, _ = _gpu_run(torch, mask, q, math.inf, (0, 0, 0), 7, per, f0=f0, kernel=kernel, order=order)
         want = dense.step(q, mask, f0, math.inf, [0, 0, 0], 7, periodic=per)
         assert np.array_equal(f, want), name
 
 
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
 @pytest.mark.parametrize("tpb", [1, 2, 8])
-def test_permutation_mode_bitexact_launch_shapes(torch, tpb):
+def test_permutation_mode_bitexact_launch_shapes(torch, tpb, kernel):
     """Every workgroup size of the D3Q19 step visits every tile exactly once."""
     mask = inputs.spheres_3d((28, 20, 16), 0.5, rmin=2, rmax=5, seed=5)[0]
     f0 = inputs.random_pdfs(19, mask, seed=22)
-    f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 3, (1, 1, 1), f0=f0, tpb=tpb)
+    f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 3, (1, 1, 1), f0=f0, tpb=tpb, kernel=kernel)
     assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 3, periodic=7))
 
 
@@ -105,8 +110,9 @@ def test_fp64_1000_steps_channel_2d(torch):
     assert _rel(u, uw) <= 1e-9 and np.max(np.abs(r - rw)) <= 1e-13
 
 
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
 @pytest.mark.parametrize("case", ["spheres_periodic", "ragged_random_state"])
-def test_fp64_1000_steps_3d(torch, case):
+def test_fp64_1000_steps_3d(torch, case, kernel):
     """D3Q19 porous crops: from rest with g (tau 0.7), and from a random state."""
     if case == "spheres_periodic":
         mask = inputs.spheres_3d(32, 0.3, seed=8)[0]
@@ -115,7 +121,7 @@ def test_fp64_1000_steps_3d(torch, case):
         mask = inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=9, periodic=(1, 0, 0))[0]
         per, g = (1, 0, 0), (2e-5, -1e-5, 3e-6)
         rho, u = inputs.random_macro(mask, seed=10)
-    f, r, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, per, rho=rho, u=u)
+    f, r, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, per, rho=rho, u=u, kernel=kernel)
     f0 = dense.init(19, mask, rho=rho, u=u)
     want = dense.step(19, mask, f0, 0.7, g, 1000, periodic=per, nthreads=8)
     fl = ~mask
@@ -216,8 +222,9 @@ def test_step_before_init_is_an_error(torch):
     assert e.value.code == lbm.LBM_ERR_STATE
 
 
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
 @pytest.mark.parametrize("storage,scale", [("f32", 0), ("f16", 12)])
-def test_offset_storage_permutation_bitexact(torch, storage, scale):
+def test_offset_storage_permutation_bitexact(torch, storage, scale, kernel):
     """Pure streaming moves stored offsets unchanged; with PDFs whose offsets
     are representable in the storage type, GPU == oracle exactly."""
     q = 19
@@ -232,18 +239,20 @@ def test_offset_storage_permutation_bitexact(torch, storage, scale):
     f0 = w[:, None, None, None] + off
     f0[:, mask] = 0.0
     f, _, _, _ = _gpu_run(torch, mask, q, math.inf, (0, 0, 0), 6, (1, 0, 0), f0=f0, storage=storage,
-                          f16_scale_log2=scale)
+                          f16_scale_log2=scale, kernel=kernel)
     want = dense.step(q, mask, f0, math.inf, [0, 0, 0], 6, periodic=(1, 0, 0))
     assert np.array_equal(f, want)
 
 
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
 @pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16", 2e-2)])
-def test_offset_storage_error_vs_fp64(torch, storage, tol):
+def test_offset_storage_error_vs_fp64(torch, storage, tol, kernel):
     """FP32 / FP16-offset storage with FP32 arithmetic: velocity error against
     the FP64 oracle after 1000 steps (D3Q19 periodic porous crop)."""
     mask = inputs.spheres_3d(32, 0.3, seed=8)[0]
     g = (1e-6, 0.0, 0.0)
-    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 1, 1), storage=storage, f16_scale_log2=22)
+    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 1, 1), storage=storage, f16_scale_log2=22,
+                          kernel=kernel)
     want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=7, nthreads=8)
     _, uw = dense.moments(19, mask, want, g)
     fl = ~mask

@@ -87,6 +87,8 @@ def test_tiling_errors():
     (dict(f16_scale_log2=40), lbm.LBM_ERR_ARG),
     (dict(lattice=9), lbm.LBM_ERR_UNSUPPORTED),
     (dict(tiles_per_block=3), lbm.LBM_ERR_UNSUPPORTED),
+    (dict(tile_order=5), lbm.LBM_ERR_ARG),
+    (dict(step_kernel=9), lbm.LBM_ERR_ARG),
 ])
 def test_param_validation(kw, code):
     t = lbm.Tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0])
