@@ -86,7 +86,10 @@ typedef struct {
   int32_t tile_order;      /* LBM_ORDER_*: order in which tiles are stored and processed */
   int32_t step_kernel;     /* LBM_KERNEL_*: which step kernel runs */
   int32_t store_policy;    /* LBM_STORE_*: cache policy of the step's PDF stores */
-  int32_t reserved;        /* set to 0 */
+  int32_t persistent;      /* 1: the D3Q19 4x4x4 step runs as one persistent grid striding over the
+                              active tile list; 0: one wavefront per tile */
+  int32_t graph_steps;     /* K > 0: lbm_step replays captured HIP graphs of K steps; 0: plain launches */
+  int32_t reserved[3];     /* set to 0 */
 } lbm_params;
 
 /* Cache policy of the PDF stores of the step: a stored value is next read one
@@ -161,6 +164,13 @@ int lbm_set_stream(lbm_solver *s, void *stream);
 
 /* Per-sample body acceleration g[3*n_samples] (host), for batches. */
 int lbm_set_sample_force(lbm_solver *s, const double *g);
+
+/* Batches: restrict the steps to the samples whose flag is nonzero
+ * (active[n_samples], host).  A deactivated sample keeps its state (both PDF
+ * copies hold it), so it can be read or reactivated later; moments,
+ * reductions and exports still cover every sample.  Needs the scalar-mask
+ * D3Q19 kernel (LBM_ERR_UNSUPPORTED otherwise).  Synchronises the stream. */
+int lbm_set_active(lbm_solver *s, const uint8_t *active);
 
 /* Initial state, Eq. (3): on every non-solid node the stored post-collision
  * PDFs become f_eq(rho, u).  rho: device dense FP64 (NULL = rho0 everywhere);

@@ -31,8 +31,12 @@ hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileA
 bool step19_supported(const Variant &v);
 // nrec: n_ftiles + 1 records (the last one all-solid); nrow: 20 per tile, the
 // 18 neighbour slots of the D3Q19 gather in kernel order (+2 padding).
+// mode 0: wavefront w -> tile w; 1: -> list[w] for w < *count; 2: persistent
+// grid of blocks_persistent workgroups striding over list[0 .. *count).
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, hipStream_t s);
+                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s);
+hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,
                        hipStream_t s);
 hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, double *rho, double *u,
@@ -45,9 +49,11 @@ hipError_t launch_reduce_partial(const Variant &v, const void *src, const TileAr
 // ... and 2 per wave (|u - u_ref|^2, |u|^2), updating u_ref ([3][n_fluid])
 hipError_t launch_residual_partial(const Variant &v, const void *src, const TileArgs &a, double *uref,
                                    double *part, int accumulate, hipStream_t s);
-// fixed-order sum of per-wave partials over each sample's waves
+// fixed-order sum of per-wave partials over each sample's waves; chunk is
+// scratch of reduce_chunks() * ncomp doubles per sample
+int reduce_chunks();
 hipError_t launch_reduce_final(const double *part, int ncomp, const SampleRec *samples, int n_samples,
-                               int words, double *out, hipStream_t s);
+                               int words, double *chunk, double *out, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
 }  // namespace lbm

@@ -357,15 +357,23 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// One 256-thread block per sample: thread t sums partials t, t+256, ... in
-// order, then a fixed shared-memory tree.
+// Fixed-order sum of per-wave partials, in two stages.  Stage 1: block
+// (c, s) sums chunk c of sample s's waves -- thread t takes partials t,
+// t+256, ... of the chunk in order, then a fixed shared-memory tree.  Stage 2:
+// one 64-thread block per sample sums the kReduceChunks chunk totals with a
+// fixed tree.  The launch shape is fixed, so results repeat bit for bit.
+constexpr int kReduceChunks = 64;
+
 __global__ void __launch_bounds__(256)
-    k_reduce_final(const double *part, int ncomp, const SampleRec *samples, int words, double *out) {
+    k_reduce_chunks(const double *part, int ncomp, const SampleRec *samples, int words, double *chunk_out) {
   __shared__ double sh[256 * 4];
-  const SampleRec &s = samples[blockIdx.x];
-  const int64_t w0 = s.tile0 * words, w1 = (s.tile0 + s.n_ftiles) * words;
+  const SampleRec &s = samples[blockIdx.y];
+  const int64_t w0 = s.tile0 * words, n = s.n_ftiles * words;
+  const int64_t per = (n + kReduceChunks - 1) / kReduceChunks;
+  const int64_t c0 = w0 + per * blockIdx.x;
+  const int64_t c1 = (c0 + per < w0 + n) ? c0 + per : w0 + n;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t w = w0 + threadIdx.x; w < w1; w += 256)
+  for (int64_t w = c0 + threadIdx.x; w < c1; w += 256)
     for (int k = 0; k < ncomp; ++k) acc[k] += part[ncomp * w + k];
   for (int k = 0; k < ncomp; ++k) sh[k * 256 + threadIdx.x] = acc[k];
   __syncthreads();
@@ -374,7 +382,21 @@ __global__ void __launch_bounds__(256)
       for (int k = 0; k < ncomp; ++k) sh[k * 256 + threadIdx.x] += sh[k * 256 + threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x < (unsigned)ncomp) out[ncomp * blockIdx.x + threadIdx.x] = sh[threadIdx.x * 256];
+  if (threadIdx.x < (unsigned)ncomp)
+    chunk_out[((int64_t)blockIdx.y * kReduceChunks + blockIdx.x) * ncomp + threadIdx.x] = sh[threadIdx.x * 256];
+}
+
+__global__ void __launch_bounds__(64) k_reduce_final(const double *chunk, int ncomp, double *out) {
+  __shared__ double sh[64 * 4];
+  for (int k = 0; k < ncomp; ++k)
+    sh[k * 64 + threadIdx.x] = chunk[((int64_t)blockIdx.x * kReduceChunks + threadIdx.x) * ncomp + k];
+  __syncthreads();
+  for (int o = 32; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < ncomp; ++k) sh[k * 64 + threadIdx.x] += sh[k * 64 + threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)ncomp) out[ncomp * blockIdx.x + threadIdx.x] = sh[threadIdx.x * 64];
 }
 
 __global__ void k_fill(double *p, int64_t n, double v) {
@@ -501,10 +523,16 @@ hipError_t launch_residual_partial(const Variant &v, const void *src, const Tile
   });
 }
 
+int reduce_chunks() { return kReduceChunks; }
+
 hipError_t launch_reduce_final(const double *part, int ncomp, const SampleRec *samples, int n_samples, int words,
-                               double *out, hipStream_t s) {
+                               double *chunk, double *out, hipStream_t s) {
   if (n_samples <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_final, dim3(n_samples), dim3(256), 0, s, part, ncomp, samples, words, out);
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(kReduceChunks, n_samples), dim3(256), 0, s, part, ncomp, samples, words,
+                     chunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_samples), dim3(64), 0, s, chunk, ncomp, out);
   return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every workspace array, plus the host tables to upload.
 struct Plan {
-  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, part, out, uref, total;
+  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, list, count, part, chunk, out, uref,
+      total;
   int64_t entries = 0;  // PDF entries per copy (with region alignment padding)
   // device tables in the solver's internal tile order
   std::vector<lbm::TileRec> rec_h;
@@ -86,6 +87,9 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
     return set_error(LBM_ERR_ARG, "step_kernel = %d", p->step_kernel);
   if (p->store_policy < LBM_STORE_AUTO || p->store_policy > LBM_STORE_NONTEMPORAL)
     return set_error(LBM_ERR_ARG, "store_policy = %d", p->store_policy);
+  if (p->persistent != 0 && p->persistent != 1) return set_error(LBM_ERR_ARG, "persistent = %d", p->persistent);
+  if (p->graph_steps < 0 || p->graph_steps > 100000)
+    return set_error(LBM_ERR_ARG, "graph_steps = %d", p->graph_steps);
   int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
   if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
   v->q = p->lattice;
@@ -200,7 +204,10 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.coef = take(t->samples.size() * sizeof(lbm::CollideCoef));
   P.nrec = take(P.nrec_h.size() * sizeof(lbm::NbRec));
   P.nrow = take(P.nrow_h.size() * sizeof(int32_t));
+  P.list = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
+  P.count = take(sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
+  P.chunk = take(t->samples.size() * (size_t)lbm::reduce_chunks() * 4 * sizeof(double));
   P.out = take(t->samples.size() * 4 * sizeof(double));
   P.uref = take((size_t)(3 * (t->n_fluid > 0 ? t->n_fluid : 1)) * sizeof(double));
   P.total = o;
@@ -228,8 +235,21 @@ struct lbm_solver {
   lbm::CollideCoef *coef_d = nullptr;
   const lbm::NbRec *nrec_d = nullptr;
   const int32_t *nrow_d = nullptr;
+  // active tile list (batches) and the launch mode of the scalar-mask step
+  int32_t *list_d = nullptr, *count_d = nullptr;
+  std::vector<int32_t> list_h;
+  int32_t count_h = 0;
+  std::vector<uint8_t> active_h;
+  bool all_active = true;
+  int64_t persistent_blocks = 0;
+  // per sample: [first, last) PDF entry of its tiles' regions
+  std::vector<int64_t> entry0, entry1;
+  int storage_bytes = 8;
+  // captured graphs of graph_steps steps, one per starting copy
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool scalar_mask = false;  // which step kernel runs
-  double *part = nullptr, *out = nullptr, *uref = nullptr;
+  double *part = nullptr, *chunk = nullptr, *out = nullptr, *uref = nullptr;
   std::vector<double> out_h;
 };
 
@@ -303,6 +323,29 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->coef_d = reinterpret_cast<lbm::CollideCoef *>(base + P.coef);
   s->nrec_d = reinterpret_cast<const lbm::NbRec *>(base + P.nrec);
   s->nrow_d = reinterpret_cast<const int32_t *>(base + P.nrow);
+  s->list_d = reinterpret_cast<int32_t *>(base + P.list);
+  s->count_d = reinterpret_cast<int32_t *>(base + P.count);
+  s->storage_bytes = lbm::storage_bytes(v.storage);
+  try {
+    s->list_h.resize((size_t)t->n_ftiles);
+    for (int64_t k = 0; k < t->n_ftiles; ++k) s->list_h[(size_t)k] = (int32_t)k;
+    s->count_h = (int32_t)t->n_ftiles;
+    s->active_h.assign(t->samples.size(), 1);
+    for (const lbm::Sample &S : t->samples) {
+      if (S.n_ftiles == 0) {
+        s->entry0.push_back(0);
+        s->entry1.push_back(0);
+        continue;
+      }
+      const lbm::TileRec &a0 = P.rec_h[(size_t)S.tile0], &a1 = P.rec_h[(size_t)(S.tile0 + S.n_ftiles - 1)];
+      const int64_t A = 128 / s->storage_bytes;
+      s->entry0.push_back(a0.off);
+      s->entry1.push_back(a1.off + ((int64_t)v.q * a1.n + A - 1) / A * A);
+    }
+  } catch (const std::bad_alloc &) {
+    delete s;
+    return set_error(LBM_ERR_NOMEM, "lbm_create: out of host memory");
+  }
   const bool fits32 = P.entries < (int64_t(1) << 32);
   if (p->step_kernel == LBM_KERNEL_SCALAR_MASK && !(lbm::step19_supported(v) && fits32)) {
     delete s;
@@ -310,7 +353,12 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
                                           "fewer than 2^32 PDF entries per copy");
   }
   s->scalar_mask = p->step_kernel != LBM_KERNEL_GENERIC && lbm::step19_supported(v) && fits32;
+  if (p->persistent && !s->scalar_mask) {
+    delete s;
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the persistent step needs the scalar-mask D3Q19 kernel");
+  }
   s->part = reinterpret_cast<double *>(base + P.part);
+  s->chunk = reinterpret_cast<double *>(base + P.chunk);
   s->out = reinterpret_cast<double *>(base + P.out);
   s->uref = reinterpret_cast<double *>(base + P.uref);
   s->out_h.assign((size_t)s->n_samples * 4, 0.0);
@@ -343,6 +391,9 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if (e == hipSuccess) e = up(P.coef, P.coef_h.data(), P.coef_h.size() * sizeof(lbm::CollideCoef));
   if (e == hipSuccess) e = up(P.nrec, P.nrec_h.data(), P.nrec_h.size() * sizeof(lbm::NbRec));
   if (e == hipSuccess) e = up(P.nrow, P.nrow_h.data(), P.nrow_h.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.list, s->list_h.data(), s->list_h.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.count, &s->count_h, sizeof(int32_t));
+  if (e == hipSuccess && s->scalar_mask && p->persistent) e = lbm::step19_persistent_blocks(v, &s->persistent_blocks);
   if (e == hipSuccess) e = up(P.nbase, P.nbase_h.data(), (size_t)nft * sizeof(int64_t));
   if (e == hipSuccess) e = up(P.samples, P.samples_h.data(), P.samples_h.size() * sizeof(lbm::SampleRec));
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host tables may be freed after return
@@ -354,11 +405,57 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   return LBM_OK;
 }
 
-extern "C" void lbm_destroy(lbm_solver *s) { delete s; }
+static void drop_graphs(lbm_solver *s) {
+  for (hipGraphExec_t &g : s->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+extern "C" void lbm_destroy(lbm_solver *s) {
+  if (!s) return;
+  drop_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
 
 extern "C" int lbm_set_stream(lbm_solver *s, void *stream) {
   if (!s) return set_error(LBM_ERR_ARG, "lbm_set_stream: NULL solver");
   s->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
+  if (!s || !active) return set_error(LBM_ERR_ARG, "lbm_set_active: NULL argument");
+  if (!s->scalar_mask)
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_set_active: needs the scalar-mask D3Q19 kernel (4x4x4 tiles)");
+  // samples that stop here: make both PDF copies hold their current state
+  for (int k = 0; k < s->n_samples; ++k) {
+    if (s->active_h[(size_t)k] && !active[k] && s->initialized && s->entry1[(size_t)k] > s->entry0[(size_t)k]) {
+      const size_t off = (size_t)s->entry0[(size_t)k] * s->storage_bytes;
+      const size_t len = (size_t)(s->entry1[(size_t)k] - s->entry0[(size_t)k]) * s->storage_bytes;
+      HIP_TRY(hipMemcpyAsync(static_cast<char *>(s->buf[s->cur ^ 1]) + off, static_cast<char *>(s->buf[s->cur]) + off,
+                             len, hipMemcpyDeviceToDevice, s->stream));
+    }
+  }
+  int32_t n = 0;
+  bool all = true;
+  for (int k = 0; k < s->n_samples; ++k) {
+    s->active_h[(size_t)k] = active[k] ? 1 : 0;
+    all &= active[k] != 0;
+    if (!active[k]) continue;
+    const lbm::SampleRec &S = s->samples_h[(size_t)k];
+    for (int64_t t = S.tile0; t < S.tile0 + S.n_ftiles; ++t) s->list_h[(size_t)n++] = (int32_t)t;
+  }
+  s->count_h = n;
+  HIP_TRY(hipMemcpyAsync(s->list_d, s->list_h.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->count_d, &s->count_h, sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  // the non-persistent step switches between direct and list-driven launches
+  // here, so its captured graphs no longer match
+  if (!s->p.persistent && s->all_active != all) drop_graphs(s);
+  s->all_active = all;
   return LBM_OK;
 }
 
@@ -389,16 +486,56 @@ extern "C" int lbm_init(lbm_solver *s, const double *rho, const double *u) {
   return LBM_OK;
 }
 
+// Enqueue one step from copy `from` on `st`.
+static hipError_t enqueue_step(lbm_solver *s, int from, hipStream_t st) {
+  if (s->scalar_mask) {
+    const int mode = s->p.persistent ? 2 : (s->all_active ? 0 : 1);
+    return lbm::launch_step19(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d, s->coef_d,
+                              s->p.store_policy != LBM_STORE_REGULAR, s->list_d, s->count_d, mode,
+                              s->persistent_blocks, st);
+  }
+  return lbm::launch_step(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->omega, st);
+}
+
+// Capture graph_steps steps starting from copy `from` (on a private stream:
+// the caller's stream may be the null stream, which cannot be captured).
+static int capture(lbm_solver *s, int from) {
+  if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int c = from;
+  for (int k = 0; k < s->p.graph_steps && e == hipSuccess; ++k) {
+    e = enqueue_step(s, c, s->cap_stream);
+    c ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[from], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return set_error(LBM_ERR_HIP, "lbm_step: graph capture failed: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
 extern "C" int lbm_step(lbm_solver *s, int32_t n) {
   if (!s) return set_error(LBM_ERR_ARG, "lbm_step: NULL solver");
   if (n < 0) return set_error(LBM_ERR_ARG, "lbm_step: n = %d", n);
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_step: call lbm_init or lbm_pdfs_import first");
+  const int K = s->p.graph_steps;
+  if (K > 0 && s->args.n_waves > 0) {
+    while (n >= K) {
+      if (!s->graph[s->cur]) {
+        const int rc = capture(s, s->cur);
+        if (rc) return rc;
+      }
+      HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+      s->cur ^= (K & 1);
+      s->steps += K;
+      n -= K;
+    }
+  }
   for (int32_t k = 0; k < n; ++k) {
-    if (s->scalar_mask)
-      HIP_TRY(lbm::launch_step19(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->nrec_d, s->nrow_d,
-                                 s->coef_d, s->p.store_policy != LBM_STORE_REGULAR, s->stream));
-    else
-      HIP_TRY(lbm::launch_step(s->var, s->buf[s->cur], s->buf[s->cur ^ 1], s->args, s->omega, s->stream));
+    HIP_TRY(enqueue_step(s, s->cur, s->stream));
     s->cur ^= 1;
     ++s->steps;
   }
@@ -420,7 +557,8 @@ extern "C" int lbm_reduce(lbm_solver *s, double *out_host) {
   if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_reduce: NULL argument");
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_reduce: solver not initialised");
   HIP_TRY(lbm::launch_reduce_partial(s->var, s->buf[s->cur], s->args, s->part, s->stream));
-  HIP_TRY(lbm::launch_reduce_final(s->part, 4, s->samples_d, s->n_samples, s->words, s->out, s->stream));
+  HIP_TRY(lbm::launch_reduce_final(s->part, 4, s->samples_d, s->n_samples, s->words, s->chunk, s->out,
+                                     s->stream));
   HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 4 * sizeof(double),
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -434,7 +572,8 @@ extern "C" int lbm_residual(lbm_solver *s, double *out_host) {
   if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_residual: NULL argument");
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_residual: solver not initialised");
   HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[s->cur], s->args, s->uref, s->part, 1, s->stream));
-  HIP_TRY(lbm::launch_reduce_final(s->part, 2, s->samples_d, s->n_samples, s->words, s->out, s->stream));
+  HIP_TRY(lbm::launch_reduce_final(s->part, 2, s->samples_d, s->n_samples, s->words, s->chunk, s->out,
+                                     s->stream));
   HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 2 * sizeof(double),
                          hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));

@@ -82,21 +82,20 @@ constexpr int slot_of(int k) {
   return -1;
 }
 
-template <int S, int WPB, bool NT>
-__global__ void __launch_bounds__(64 * WPB)
-    k_step19(const void *__restrict__ src_, void *__restrict__ dst_, TileArgs a, const NbRec *__restrict__ nrec,
-             const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
+// One 4x4x4 tile: gather, collide, store.  Lanes of solid nodes return
+// early; every value the wavefront branches on is uniform.
+template <int S, bool NT>
+__device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict__ src_, void *__restrict__ dst_,
+                                            const TileArgs &a, const NbRec *__restrict__ nrec,
+                                            const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
   using L = D3Q19;
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
   const T *__restrict__ src = static_cast<const T *>(src_);
   T *__restrict__ dst = static_cast<T *>(dst_);
-
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
-  if (tile >= a.n_waves) return;
+
   // own record and the 18 neighbour records (empty neighbours point at an
   // all-solid sentinel record, so every load is unconditional)
   const NbRec own = nrec[tile];
@@ -188,25 +187,64 @@ __global__ void __launch_bounds__(64 * WPB)
   });
 }
 
+// Which tiles a launch visits.
+enum { kDirect = 0, kList = 1, kPersistent = 2 };
+
+// kDirect: wavefront w updates tile w.  kList: wavefront w updates tile
+// list[w] if w < *count.  kPersistent: a fixed grid of G wavefronts strides
+// over list[0 .. *count).  The count lives in device memory, so a captured
+// graph stays valid when the active set changes.
+template <int S, int WPB, bool NT, int MODE>
+__global__ void __launch_bounds__(64 * WPB)
+    k_step19(const void *__restrict__ src, void *__restrict__ dst, TileArgs a, const NbRec *__restrict__ nrec,
+             const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
+             const int32_t *__restrict__ count) {
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  if constexpr (MODE == kDirect) {
+    if (gw >= a.n_waves) return;
+    step19_tile<S, NT>(gw, src, dst, a, nrec, nrow, coef);
+  } else if constexpr (MODE == kList) {
+    if (gw >= (int64_t)*count) return;
+    step19_tile<S, NT>(list[gw], src, dst, a, nrec, nrow, coef);
+  } else {
+    const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
+    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT>(list[k], src, dst, a, nrec, nrow, coef);
+  }
+}
+
 }  // namespace
 
 bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
 
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, hipStream_t s) {
+                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
+  const unsigned blocks =
+      mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, coef);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, coef, list, count);
     return hipGetLastError();
   };
-#define LBM_STEP19_NT(S, W) return nontemporal ? go(k_step19<S, W, true>) : go(k_step19<S, W, false>);
-#define LBM_STEP19_WPB(S)                  \
-  switch (v.wpb) {                         \
-    case 1: LBM_STEP19_NT(S, 1)            \
-    case 2: LBM_STEP19_NT(S, 2)            \
-    case 4: LBM_STEP19_NT(S, 4)            \
-    default: LBM_STEP19_NT(S, 8)           \
+#define LBM_STEP19_MODE(S, W, N)                          \
+  switch (mode) {                                         \
+    case kDirect: return go(k_step19<S, W, N, kDirect>);  \
+    case kList: return go(k_step19<S, W, N, kList>);      \
+    default: return go(k_step19<S, W, N, kPersistent>);   \
+  }
+#define LBM_STEP19_NT(S, W)                  \
+  if (nontemporal) {                         \
+    LBM_STEP19_MODE(S, W, true)              \
+  } else {                                   \
+    LBM_STEP19_MODE(S, W, false)             \
+  }
+#define LBM_STEP19_WPB(S)   \
+  switch (v.wpb) {          \
+    case 1: LBM_STEP19_NT(S, 1) \
+    case 2: LBM_STEP19_NT(S, 2) \
+    case 4: LBM_STEP19_NT(S, 4) \
+    default: LBM_STEP19_NT(S, 8) \
   }
   switch (v.storage) {
     case LBM_F64: LBM_STEP19_WPB(LBM_F64)
@@ -215,6 +253,28 @@ hipError_t launch_step19(const Variant &v, const void *src, void *dst, const Til
   }
 #undef LBM_STEP19_WPB
 #undef LBM_STEP19_NT
+#undef LBM_STEP19_MODE
+}
+
+// Workgroups of the persistent step that fit on the device at once.
+hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  auto occ = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * v.wpb, 0); };
+#define LBM_OCC(S, W) e = (e == hipSuccess) ? occ(k_step19<S, W, true, kPersistent>) : e;
+  const int w = v.wpb;
+  if (v.storage == LBM_F64) {
+    if (w == 1) { LBM_OCC(LBM_F64, 1) } else if (w == 2) { LBM_OCC(LBM_F64, 2) } else if (w == 4) { LBM_OCC(LBM_F64, 4) } else { LBM_OCC(LBM_F64, 8) }
+  } else if (v.storage == LBM_F32_OFFSET) {
+    if (w == 1) { LBM_OCC(LBM_F32_OFFSET, 1) } else if (w == 2) { LBM_OCC(LBM_F32_OFFSET, 2) } else if (w == 4) { LBM_OCC(LBM_F32_OFFSET, 4) } else { LBM_OCC(LBM_F32_OFFSET, 8) }
+  } else {
+    if (w == 1) { LBM_OCC(LBM_F16_OFFSET, 1) } else if (w == 2) { LBM_OCC(LBM_F16_OFFSET, 2) } else if (w == 4) { LBM_OCC(LBM_F16_OFFSET, 4) } else { LBM_OCC(LBM_F16_OFFSET, 8) }
+  }
+#undef LBM_OCC
+  if (e != hipSuccess) return e;
+  *blocks = (int64_t)cus * (per > 0 ? per : 1);
+  return hipSuccess;
 }
 
 }  // namespace lbm

@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
         ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("tau", ctypes.c_double),
         ("g", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("f16_scale_log2", ctypes.c_int32),
         ("tiles_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32), ("step_kernel", ctypes.c_int32),
-        ("store_policy", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("store_policy", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -88,6 +89,7 @@ def lib():
             "lbm_destroy": (None, [P]),
             "lbm_set_stream": (ctypes.c_int, [P, P]),
             "lbm_set_sample_force": (ctypes.c_int, [P, P]),
+            "lbm_set_active": (ctypes.c_int, [P, P]),
             "lbm_init": (ctypes.c_int, [P, P, P]),
             "lbm_step": (ctypes.c_int, [P, I32]),
             "lbm_moments": (ctypes.c_int, [P, P, P]),
@@ -186,7 +188,8 @@ class Tiles:
 
 
 def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
-                tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto"):
+                tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", persistent=0,
+                graph_steps=0):
     p = Params()
     p.lattice = lattice
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -199,6 +202,8 @@ def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0,
     p.tile_order = ORDER[tile_order] if isinstance(tile_order, str) else int(tile_order)
     p.step_kernel = KERNEL[step_kernel] if isinstance(step_kernel, str) else int(step_kernel)
     p.store_policy = STORE_POLICY[store_policy] if isinstance(store_policy, str) else int(store_policy)
+    p.persistent = int(bool(persistent))
+    p.graph_steps = int(graph_steps)
     return p
 
 
@@ -213,15 +218,15 @@ class Solver:
     """A solver on one tiling; device memory and stream come from torch."""
 
     def __init__(self, tiles, lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
-                 tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", device="cuda",
-                 stream=None):
+                 tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", persistent=0,
+                 graph_steps=0, device="cuda", stream=None):
         import torch
 
         self.torch = torch
         self.tiles = tiles
         self.q = lattice
         self.params = make_params(lattice, storage, tau, g, rho0, f16_scale_log2, tiles_per_block, tile_order,
-                                  step_kernel, store_policy)
+                                  step_kernel, store_policy, persistent, graph_steps)
         self.device = torch.device(device)
         n = ctypes.c_size_t()
         _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(self.params), ctypes.byref(n)),
@@ -300,6 +305,36 @@ class Solver:
         if g.size != 3 * self.n_samples:
             raise ValueError("need 3 values per sample")
         _check(lib().lbm_set_sample_force(self._h, _np_ptr(g)), "lbm_set_sample_force")
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(np.asarray(active).astype(np.uint8).reshape(-1))
+        if a.size != self.n_samples:
+            raise ValueError("need one flag per sample")
+        _check(lib().lbm_set_active(self._h, _np_ptr(a)), "lbm_set_active")
+
+    def run_to_steady(self, tol=1e-6, check_every=100, max_steps=1_000_000, batch_deactivate=True):
+        """Step until every sample's residual (velocity change over
+        ``check_every`` steps, relative) is below ``tol``.  For batches,
+        converged samples are taken out of the active tile list.  Returns
+        (steps taken per sample, final residuals)."""
+        n = self.n_samples
+        done = np.zeros(n, bool)
+        steps_at = np.full(n, -1, np.int64)
+        res = np.full(n, np.inf)
+        self.residual()  # reference velocity
+        taken = 0
+        while taken < max_steps and not done.all():
+            self.step(check_every)
+            taken += check_every
+            res = self.residual()
+            newly = (~done) & (res < tol)
+            if newly.any():
+                steps_at[newly] = taken
+                done |= newly
+                if batch_deactivate and n > 1 and not done.all():
+                    self.set_active(~done)
+        steps_at[~done] = -1
+        return steps_at, res
 
     @property
     def step_count(self):

@@ -108,3 +108,16 @@ def test_workspace_size_counts_fluid_nodes_only():
         nft = t.info["n_ftiles"]
         assert pdf < n < pdf + 24 * t.info["n_fluid"] + (2 * 128 + 200) * nft + 8192
     assert lbm.workspace_bytes(t, tau=math.inf) > 0
+
+
+def test_autotune_candidates_and_key():
+    from paper_1703_08015_amd import autotune
+    c19 = autotune.candidates(19)
+    assert any(c["tile"] == (4, 4, 8) for c in c19) and any(c["persistent"] for c in c19)
+    assert all(c["tile"] == (4, 4, 4) for c in autotune.candidates(19, batched=True))
+    m = np.zeros((8, 8, 8), bool)
+    k1 = autotune.geometry_key([m], (1, 1, 1), 19, "f64", 0.7)
+    m2 = m.copy()
+    m2[0, 0, 0] = True
+    assert k1 != autotune.geometry_key([m2], (1, 1, 1), 19, "f64", 0.7)
+    assert k1 != autotune.geometry_key([m], (1, 1, 1), 19, "f32", 0.7)
