@@ -106,6 +106,128 @@ def copy_reference(torch, gib, reps=20):
             "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}
 
 
+def _progress(tag):
+    def f(steps, done, worst):
+        print("[%s] %d steps, %d converged, worst residual %.3e" % (tag, steps, done, worst), file=sys.stderr,
+              flush=True)
+    return f
+
+
+def _rel_l2(a, b):
+    return float(((a - b) ** 2).sum().sqrt() / (b ** 2).sum().sqrt())
+
+
+def mode_steady(args, torch, lbm):
+    """Time to steady state (residual < tol over check-interval steps) of the
+    workload for FP64 and FP32 storage, and the FP32 steady velocity error
+    against the FP64 one."""
+    mask, phi, desc = workload(args)
+    tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
+    out = {"metric": "time to steady state (residual < %g)" % args.tol, "unit": "s", "higher_is_better": False,
+           "data": "synthetic", "config": {"workload": desc, "n_fluid": tiles.info["n_fluid"],
+                                           "check_every": args.check_every}, "runs": {}}
+    fields = {}
+    for st in ("f64", "f32"):
+        s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0), graph_steps=args.check_every,
+                       f16_scale_log2=args.f16_scale_log2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.init()
+        steps, res = s.run_to_steady(tol=args.tol, check_every=args.check_every, max_steps=args.max_steps,
+                                     progress=_progress("steady " + st))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fields[st] = s.moments()
+        out["runs"][st] = {"steps": int(steps[0]), "seconds": round(wall, 3), "residual": float(res[0]),
+                           "mlups": round(tiles.info["n_fluid"] * max(int(steps[0]), 0) / wall / 1e6, 1)}
+        del s
+    fl = torch.from_numpy(~mask).cuda()
+    u64, u32 = fields["f64"][1][:, fl], fields["f32"][1][:, fl]
+    out["f32_vs_f64_u_rel_l2"] = _rel_l2(u32, u64)
+    out["f32_vs_f64_rho_max_abs"] = float((fields["f32"][0][fl] - fields["f64"][0][fl]).abs().max())
+    out["value"] = out["runs"]["f64"]["seconds"]
+    out["f32_speedup"] = round(out["runs"]["f64"]["seconds"] / out["runs"]["f32"]["seconds"], 3)
+    return out
+
+
+def mode_vessel(args, torch, lbm):
+    """Vessel-tree geometry: FP64 / FP32-offset / FP16-offset runs of a fixed
+    number of steps; rho and u error of the offset forms against FP64."""
+    from paper_1703_08015_amd import inputs
+    mask, phi = inputs.vessel_tree(args.n, 0.08, seed=args.seed)
+    tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
+    desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, fluid "
+            "fraction %.4f, seed %d), tau %.2f, g %.0e along x, %d steps from rest" % (args.n, phi, args.seed, args.tau,
+                                                                                   args.g, args.vessel_steps))
+    out = {"metric": "offset-storage error vs FP64 and MLUPS", "unit": "MLUPS", "higher_is_better": True,
+           "data": "synthetic", "config": {"workload": desc, "n_fluid": tiles.info["n_fluid"],
+                                           "n_ftiles": tiles.info["n_ftiles"], "phi_t": round(tiles.info["phi_t"], 4),
+                                           "f16_scale_log2": args.f16_scale_log2}, "runs": {}}
+    fl = torch.from_numpy(~mask).cuda()
+    ref = None
+    for st in ("f64", "f32", "f16"):
+        s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0),
+                       f16_scale_log2=args.f16_scale_log2)
+        s.init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.vessel_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r, u = s.moments()
+        run = {"mlups": round(tiles.info["n_fluid"] * args.vessel_steps / wall / 1e6, 1),
+               "algorithmic_gbs": round(tiles.info["n_fluid"] * 38 * SD[st] * args.vessel_steps / wall / 1e9, 1)}
+        if ref is None:
+            ref = (r[fl].clone(), u[:, fl].clone())
+        else:
+            run["u_rel_l2_vs_f64"] = _rel_l2(u[:, fl], ref[1])
+            run["rho_max_abs_vs_f64"] = float((r[fl] - ref[0]).abs().max())
+        out["runs"][st] = run
+        del s, r, u
+    out["value"] = out["runs"]["f64"]["mlups"]
+    return out
+
+
+def batch_masks(count, seed):
+    from paper_1703_08015_amd import inputs
+    specs = inputs.batch_specs(count, seed=seed)
+    masks = [inputs.porous_cube(sp)[0] for sp in specs]
+    return specs, masks
+
+
+def mode_batch(args, torch, lbm):
+    """Batch of porous cubes (uneven sizes) in one concatenated tile list,
+    run to steady state with converged samples dropped from the step."""
+    t0 = time.perf_counter()
+    specs, masks = batch_masks(args.batch, args.seed + 1000)
+    tiles = lbm.Tiles.concat([lbm.Tiles(m) for m in masks])
+    t_geom = time.perf_counter() - t0
+    s = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, persistent=1, graph_steps=args.check_every,
+                   f16_scale_log2=args.f16_scale_log2)
+    s.set_sample_force(np.array([sp["g"] for sp in specs]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.init()
+    steps, res = s.run_to_steady(tol=args.tol, check_every=args.check_every, max_steps=args.max_steps,
+                                 progress=_progress("batch"))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    fluid = np.array([int((~m).sum()) for m in masks])
+    done = steps > 0
+    updates = int((fluid * np.where(done, steps, args.max_steps)).sum())
+    desc = ("%d periodic porous cubes, edge uniform over 32..96 step 4, overlapping spheres r 4-12 to porosity "
+            "U[0.2, 0.8], |g| = 1e-6 in a uniform direction, tau %.2f, %s storage, residual < %g every %d steps"
+            % (args.batch, args.tau, args.storage, args.tol, args.check_every))
+    return {"metric": "batched time to steady state", "value": round(wall, 3), "unit": "s", "higher_is_better": False,
+            "data": "synthetic", "dtype": args.storage,
+            "config": {"workload": desc, "n_samples": len(masks), "n_nodes": tiles.info["n_nodes"],
+                       "n_fluid": tiles.info["n_fluid"], "n_ftiles": tiles.info["n_ftiles"]},
+            "converged": int(done.sum()), "steps_min": int(steps[done].min()) if done.any() else None,
+            "steps_median": int(np.median(steps[done])) if done.any() else None,
+            "steps_max": int(steps[done].max()) if done.any() else None,
+            "node_updates": updates, "mlups": round(updates / wall / 1e6, 1), "geometry_seconds": round(t_geom, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +247,12 @@ def main():
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--max-steps", type=int, default=200000)
+    ap.add_argument("--vessel-steps", type=int, default=5000)
+    ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the device copy reference (read + write each this many GiB); 0 = skip")
     args = ap.parse_args()
@@ -139,6 +267,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode != "step":
+        if args.mode == "vessel" and args.n == 256:
+            args.n = 448
+        if args.mode == "batch":
+            args.tau = 0.8 if args.tau == 0.7 else args.tau
+            args.storage = "f32" if args.storage == "f64" else args.storage
+        res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch}[args.mode](args, torch, lbm)
+        res["n_gpus"] = 1
+        print(json.dumps(res), flush=True)
+        return
     copy_ref = copy_reference(torch, args.copy_gib) if args.copy_gib > 0 else None
     mask, phi, desc = workload(args)
     tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))

@@ -312,12 +312,16 @@ class Solver:
             raise ValueError("need one flag per sample")
         _check(lib().lbm_set_active(self._h, _np_ptr(a)), "lbm_set_active")
 
-    def run_to_steady(self, tol=1e-6, check_every=100, max_steps=1_000_000, batch_deactivate=True):
+    def run_to_steady(self, tol=1e-6, check_every=100, max_steps=1_000_000, batch_deactivate=True, progress=None):
         """Step until every sample's residual (velocity change over
         ``check_every`` steps, relative) is below ``tol``.  For batches,
         converged samples are taken out of the active tile list.  Returns
-        (steps taken per sample, final residuals)."""
+        (steps taken per sample, final residuals).  ``progress``: a callable
+        given (steps, number converged, max residual of the rest) about every
+        20 s."""
+        import time
         n = self.n_samples
+        last = time.perf_counter()
         done = np.zeros(n, bool)
         steps_at = np.full(n, -1, np.int64)
         res = np.full(n, np.inf)
@@ -333,6 +337,9 @@ class Solver:
                 done |= newly
                 if batch_deactivate and n > 1 and not done.all():
                     self.set_active(~done)
+            if progress is not None and time.perf_counter() - last > 20:
+                last = time.perf_counter()
+                progress(taken, int(done.sum()), float(res[~done].max()) if (~done).any() else 0.0)
         steps_at[~done] = -1
         return steps_at, res
 
