@@ -1,0 +1,122 @@
+/*
+ * lbm_nn.h -- C ABI of the learned warm start's layer kernels (liblbm.so).
+ *
+ * A small 3D convolutional U-Net maps a solid mask and a force direction to
+ * the steady (rho, u) of the lattice Boltzmann problem; f_eq(rho, u) then
+ * initialises the solver (lbm_init), which still produces the answer.  These
+ * calls are the network's building blocks; the network itself is assembled by
+ * the caller.  (The method's paper has no learned component; its solver and
+ * steady state are what the network imitates.)
+ *
+ * Conventions
+ *   - Activations are BF16, one sample at a time, channels last:
+ *     element (x, y, z, c) of an (nx, ny, nz) grid with row stride ld (>= the
+ *     channel count, a multiple of 8) is at c + ld*(x + nx*(y + ny*z)).  Channel
+ *     counts are multiples of 8; x, y and ld-strided rows are 16-byte aligned.
+ *   - A layer is a gather-GEMM: for every GEMM row m (a voxel of `rows`) and
+ *     output channel n,
+ *         y[dst(m)][n] = act( sum_t sum_c x[src(m, t)][c] * w[n][t*cin + c] + bias[n] )
+ *     src: LBM_NN_CONV3 (27 taps t = (dz+1)*9 + (dy+1)*3 + (dx+1), circular
+ *     neighbour m + (dx, dy, dz)); LBM_NN_IDENT (one tap, src = m);
+ *     LBM_NN_GATHER2 (8 taps t = az*4 + ay*2 + ax, src = 2m + a on a grid twice
+ *     as fine).  dst: LBM_NN_IDENT, or LBM_NN_SCATTER2 (for tap t only,
+ *     dst = 2m + a on a grid twice as fine: a 2x2x2 stride-2 transposed conv).
+ *   - Weights w are BF16 [cout][taps*cin]; bias FP32 [cout] or NULL.
+ *     Products run on BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+ *     accumulation.
+ *   - Everything is asynchronous on the given HIP stream (NULL = default);
+ *     the caller owns all buffers.  Return: LBM_OK or an LBM_ERR_* code of lbm.h.
+ */
+#ifndef LBM_NN_H
+#define LBM_NN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_NN_IDENT 0
+#define LBM_NN_CONV3 1
+#define LBM_NN_GATHER2 2
+#define LBM_NN_SCATTER2 3
+
+typedef struct {
+  int32_t src_mode;     /* LBM_NN_IDENT, LBM_NN_CONV3 or LBM_NN_GATHER2 */
+  int32_t dst_mode;     /* LBM_NN_IDENT or LBM_NN_SCATTER2 */
+  int32_t rows[3];      /* GEMM row grid (nx, ny, nz) */
+  int32_t taps;         /* 27 (CONV3), 1 (IDENT), 8 (GATHER2 or SCATTER2) */
+  int32_t cin, cout;    /* multiples of 8 (cout: any >= 1 for FP32 outputs) */
+  const void *x;        /* BF16 input rows */
+  int32_t ldx;
+  const void *w;        /* BF16 [cout][taps*cin] */
+  const float *bias;    /* FP32 [cout] or NULL */
+  void *y;              /* output rows: BF16, or FP32 if y_fp32 */
+  int32_t ldy;
+  int32_t y_fp32;
+  int32_t relu;         /* apply max(0, .) */
+  int32_t reserved;
+} lbm_nn_gemm;
+
+/* y = act(gather-GEMM(x, w) + bias).  For LBM_NN_SCATTER2 every output voxel
+ * of the fine grid is written once over the 8 taps. */
+int lbm_nn_forward(const lbm_nn_gemm *g, void *stream);
+
+/* Weight gradient of the same layer: dw[n][t*cin + c] += sum_m x[src(m,t)][c]
+ * * dy[dst(m)][n], with g->y the BF16 gradient dy (row stride ldy) and dw an
+ * FP32 [cout][taps*cin] accumulator (not cleared); g->w and g->bias unused.
+ * If db is not NULL it accumulates sum_m dy[dst(m)][n] (taps 0 / per tap for
+ * SCATTER2). */
+int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream);
+
+/* Weights of the backward-data pass of a layer, so that lbm_nn_forward with
+ * them computes dx from dy: CONV3: wt[c][t*cout + n] = w[n][(26-t)*cin + c];
+ * SCATTER2 (transposed conv): wt[c][t*cout + n] = w[n][t*cin + c] (used with
+ * src LBM_NN_GATHER2); IDENT: wt[c][n] = w[n][c].  BF16 in, BF16 out. */
+int lbm_nn_backward_weights(int32_t mode, int32_t taps, int32_t cin, int32_t cout, const void *w, void *wt,
+                            void *stream);
+
+/* 2x2x2 max pooling of x (fine grid 2*grid, stride ldx) into y (grid, ldy);
+ * arg (uint8 per output element, c fastest over `channels`) records the
+ * winning corner.  Backward: dx (fine grid, ldx) receives dy at each window's
+ * winning corner and 0 elsewhere; with accumulate the values are added to dx
+ * instead (for a tensor that also feeds a skip connection). */
+int lbm_nn_maxpool2(const int32_t grid[3], int32_t channels, const void *x, int32_t ldx, void *y, int32_t ldy,
+                    uint8_t *arg, void *stream);
+int lbm_nn_maxpool2_backward(const int32_t grid[3], int32_t channels, const void *dy, int32_t ldy,
+                             const uint8_t *arg, void *dx, int32_t ldx, int32_t accumulate, void *stream);
+
+/* dy[i] = y[i] > 0 ? dy[i] : 0 over n rows of `channels` (strides ldy). */
+int lbm_nn_relu_backward(int64_t n, int32_t channels, const void *y, int32_t ld_y, void *dy, int32_t ld_dy,
+                         void *stream);
+
+/* Masked mean-squared error: loss_acc[0] += sum over rows with mask == 0 of
+ * sum_c (pred - target)^2 (FP32 [rows][channels]); dpred (BF16 rows of stride
+ * ldd, channels written, the rest zeroed) = scale * 2 (pred - target) on those
+ * rows, 0 elsewhere. */
+int lbm_nn_mse(int64_t n, int32_t channels, const float *pred, const float *target, const uint8_t *mask,
+               float scale, void *dpred, int32_t ldd, float *loss_acc, void *stream);
+
+/* Adam on FP32 master weights p with moments m, v, gradient g (all n), then
+ * p16 = bf16(p).  step >= 1 is the update count (bias correction). */
+int lbm_nn_adam(int64_t n, float *p, float *m, float *v, const float *g, void *p16, float lr, float beta1,
+                float beta2, float eps, int32_t step, void *stream);
+
+/* Network input: x (BF16 [nodes][8]) = (solid, gx, gy, gz on fluid nodes, 0...)
+ * from a uint8 solid mask and a unit force direction. */
+int lbm_nn_encode_input(int64_t n, const uint8_t *solid, const float dir[3], void *x, void *stream);
+
+/* Network output (FP32 [nodes][4]: scaled (rho - rho0, u)) to dense FP64
+ * fields for lbm_init: rho = rho0 + s*p0, u = s*p[1..3] on fluid nodes, 0 on
+ * solid ones.  If renorm, rho is shifted on fluid nodes so that its sum is
+ * rho0 times the fluid count (mass of the cold start); scratch: 2 device
+ * doubles. */
+int lbm_nn_decode_output(int64_t n, const float *pred, const uint8_t *solid, double rho0, double scale, int32_t renorm,
+                         double *rho, double *u, double *scratch, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_NN_H */

@@ -1,0 +1,592 @@
+// Layer kernels of the warm-start U-Net (C ABI in lbm_nn.h), gfx950.
+//
+// All convolutions are gather-GEMMs on BF16 MFMA (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation): GEMM rows are voxels, the reduction runs over
+// (tap, input channel) and columns are output channels.  Lane l of a
+// wavefront holds A[l%16][8(l/16)..+7], B[8(l/16)..+7][l%16] and the result
+// C[4(l/16)..+3][l%16]; with channels-last activations the A operand of a row
+// is one 16-byte load of 8 consecutive channels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+#include "lbm_nn.h"
+
+namespace lbm {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct Grid {
+  int nx, ny, nz;
+};
+
+struct GemmArgs {
+  Grid rows, in_grid, out_grid;
+  int taps, cin, cout, ldx, ldy;
+  int64_t M;  // GEMM rows
+  const bf16 *x;
+  const bf16 *w;
+  const float *bias;
+  void *y;
+};
+
+__device__ __forceinline__ int64_t vidx(int x, int y, int z, const Grid &g) {
+  return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+}
+
+// input voxel of GEMM row m for tap t
+template <int SRC>
+__device__ __forceinline__ int64_t src_voxel(int64_t m, int t, const Grid &rows, const Grid &in) {
+  if constexpr (SRC == LBM_NN_IDENT) {
+    return m;
+  } else {
+    const int x = (int)(m % rows.nx), y = (int)((m / rows.nx) % rows.ny), z = (int)(m / ((int64_t)rows.nx * rows.ny));
+    if constexpr (SRC == LBM_NN_CONV3) {
+      int sx = x + t % 3 - 1, sy = y + (t / 3) % 3 - 1, sz = z + t / 9 - 1;
+      sx += sx < 0 ? in.nx : (sx >= in.nx ? -in.nx : 0);
+      sy += sy < 0 ? in.ny : (sy >= in.ny ? -in.ny : 0);
+      sz += sz < 0 ? in.nz : (sz >= in.nz ? -in.nz : 0);
+      return vidx(sx, sy, sz, in);
+    } else {  // GATHER2
+      return vidx(2 * x + (t & 1), 2 * y + ((t >> 1) & 1), 2 * z + (t >> 2), in);
+    }
+  }
+}
+
+template <int DST>
+__device__ __forceinline__ int64_t dst_voxel(int64_t m, int t, const Grid &rows, const Grid &out) {
+  if constexpr (DST == LBM_NN_IDENT) {
+    return m;
+  } else {
+    const int x = (int)(m % rows.nx), y = (int)((m / rows.nx) % rows.ny), z = (int)(m / ((int64_t)rows.nx * rows.ny));
+    return vidx(2 * x + (t & 1), 2 * y + ((t >> 1) & 1), 2 * z + (t >> 2), out);
+  }
+}
+
+// ---- forward gather-GEMM: 4 wavefronts x 16 rows, NW column fragments ------
+template <int SRC, int DST, int NW, bool F32, bool RELU>
+__global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, kb = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * 64 + wv * 16;
+  const int n0 = blockIdx.y * 16 * NW;
+  const int tfix = blockIdx.z;  // the tap of a SCATTER2 launch
+  const int64_t m = m0 + r;
+  const bool mv = m < a.M;
+  f32x4 acc[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ktot = a.taps * a.cin;
+  const int t0 = DST == LBM_NN_SCATTER2 ? tfix : 0;
+  const int t1 = DST == LBM_NN_SCATTER2 ? tfix + 1 : a.taps;
+  for (int t = t0; t < t1; ++t) {
+    const bf16 *xrow = a.x + (mv ? src_voxel<SRC>(m, t, a.rows, a.in_grid) : 0) * a.ldx;
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+      const int c = c0 + 8 * kb;
+      bf16x8 av = {};
+      if (mv && c < a.cin) av = *reinterpret_cast<const bf16x8 *>(xrow + c);
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int n = n0 + 16 * j + r;
+        bf16x8 bv = {};
+        if (n < a.cout && c < a.cin) bv = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)n * ktot + t * a.cin + c);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int n = n0 + 16 * j + r;
+    if (n >= a.cout) continue;
+    const float b = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t mo = m0 + 4 * kb + i;
+      if (mo >= a.M) continue;
+      float v = acc[j][i] + b;
+      if (RELU) v = fmaxf(v, 0.f);
+      const int64_t d = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid) * a.ldy + n;
+      if (F32)
+        static_cast<float *>(a.y)[d] = v;
+      else
+        static_cast<bf16 *>(a.y)[d] = (bf16)v;
+    }
+  }
+}
+
+// ---- weight gradient: voxels are the reduction; LDS transposes the tiles ----
+// Block: tap t, 16*CF input channels, 16*NF output channels, a voxel chunk.
+// Each wavefront stages 32 voxels of x and dy as [channel][voxel] in LDS and
+// runs CF x NF MFMAs; the four wavefronts' sums meet in LDS, then one FP32
+// atomic add per weight.
+constexpr int kWgradPad = 8;  // bf16 of padding per LDS row
+
+template <int SRC, int DST, int CF, int NF>
+__global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks) {
+  __shared__ __attribute__((aligned(16))) bf16 sx[4][16 * CF][32 + kWgradPad];
+  __shared__ __attribute__((aligned(16))) bf16 sy[4][16 * NF][32 + kWgradPad];
+  __shared__ float red[4][16 * CF][16 * NF + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, kb = lane >> 4;
+  const int t = blockIdx.y % a.taps, cb = blockIdx.y / a.taps, nb = blockIdx.z;
+  const int cbase = cb * 16 * CF, nbase = nb * 16 * NF;
+  const int64_t v0 = (int64_t)blockIdx.x * chunk;
+  int64_t v1 = v0 + chunk;
+  if (v1 > a.M) v1 = a.M;
+  f32x4 acc[CF][NF];
+#pragma unroll
+  for (int i = 0; i < CF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t vb = v0; vb < v1; vb += 128) {
+    // stage: lane handles voxel vb + 32*wv + (lane & 31), channel groups by lane >> 5
+    const int64_t m = vb + 32 * wv + (lane & 31);
+    const bool mv = m < v1;
+    const int vl = lane & 31;
+    const bf16 *xr = a.x + (mv ? src_voxel<SRC>(m, t, a.rows, a.in_grid) : 0) * a.ldx;
+    const bf16 *yr = static_cast<const bf16 *>(a.y) + (mv ? dst_voxel<DST>(m, t, a.rows, a.out_grid) : 0) * a.ldy;
+    for (int gch = lane >> 5; gch < 2 * CF; gch += 2) {
+      const int c = cbase + 8 * gch;
+      bf16x8 v = {};
+      if (mv && c < a.cin) v = *reinterpret_cast<const bf16x8 *>(xr + c);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sx[wv][8 * gch + q][vl] = v[q];
+    }
+    for (int gch = lane >> 5; gch < 2 * NF; gch += 2) {
+      const int n = nbase + 8 * gch;
+      bf16x8 v = {};
+      if (mv && n < a.cout) v = *reinterpret_cast<const bf16x8 *>(yr + n);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sy[wv][8 * gch + q][vl] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CF; ++i) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sx[wv][16 * i + r][8 * kb]);
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sy[wv][16 * j + r][8 * kb]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds C[c = 16i + 4kb + q][n = 16j + r]
+#pragma unroll
+  for (int i = 0; i < CF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[wv][16 * i + 4 * kb + q][16 * j + r] = acc[i][j][q];
+  __syncthreads();
+  const int ktot = a.taps * a.cin;
+  for (int e = threadIdx.x; e < 256 * CF * NF; e += 256) {
+    const int cl = e / (16 * NF), nl = e % (16 * NF);
+    const int c = cbase + cl, n = nbase + nl;
+    if (c >= a.cin || n >= a.cout) continue;
+    const float s = red[0][cl][nl] + red[1][cl][nl] + red[2][cl][nl] + red[3][cl][nl];
+    atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, s);
+  }
+}
+
+// bias gradient: db[n] += sum over rows of dy[dst(m)][n] (per tap for SCATTER2)
+template <int DST>
+__global__ void __launch_bounds__(256) k_bias_grad(GemmArgs a, float *db, int64_t chunk) {
+  const int n = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int part = threadIdx.x >> 6;
+  __shared__ float red[4][64];
+  float s = 0.f;
+  if (n < a.cout) {
+    const int taps = DST == LBM_NN_SCATTER2 ? a.taps : 1;
+    const int64_t v0 = (int64_t)blockIdx.x * chunk;
+    const int64_t v1 = v0 + chunk < a.M ? v0 + chunk : a.M;
+    for (int t = 0; t < taps; ++t)
+      for (int64_t m = v0 + part; m < v1; m += 4)
+        s += (float)static_cast<const bf16 *>(a.y)[dst_voxel<DST>(m, t, a.rows, a.out_grid) * a.ldy + n];
+  }
+  red[part][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (part == 0 && n < a.cout) atomicAdd(db + n, red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                                     red[3][threadIdx.x]);
+}
+
+__global__ void k_backward_weights(int mode, int taps, int cin, int cout, const bf16 *w, bf16 *wt) {
+  const int64_t total = (int64_t)taps * cin * cout;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    // e indexes wt[c][t*cout + n]
+    const int c = (int)(e / ((int64_t)taps * cout));
+    const int rem = (int)(e % ((int64_t)taps * cout));
+    const int t = rem / cout, n = rem % cout;
+    const int ts = mode == LBM_NN_CONV3 ? (taps - 1 - t) : t;
+    wt[e] = w[(int64_t)n * taps * cin + (int64_t)ts * cin + c];
+  }
+}
+
+__global__ void k_maxpool(Grid g, int channels, const bf16 *x, int ldx, bf16 *y, int ldy, uint8_t *arg) {
+  const int64_t total = (int64_t)g.nx * g.ny * g.nz * channels;
+  const Grid f{2 * g.nx, 2 * g.ny, 2 * g.nz};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % channels);
+    const int64_t v = e / channels;
+    const int xx = (int)(v % g.nx), yy = (int)((v / g.nx) % g.ny), zz = (int)(v / ((int64_t)g.nx * g.ny));
+    float best = -INFINITY;
+    int who = 0;
+    for (int k = 0; k < 8; ++k) {
+      const float val = (float)x[vidx(2 * xx + (k & 1), 2 * yy + ((k >> 1) & 1), 2 * zz + (k >> 2), f) * ldx + c];
+      if (val > best) {
+        best = val;
+        who = k;
+      }
+    }
+    y[v * ldy + c] = (bf16)best;
+    arg[e] = (uint8_t)who;
+  }
+}
+
+__global__ void k_maxpool_backward(Grid g, int channels, const bf16 *dy, int ldy, const uint8_t *arg, bf16 *dx,
+                                   int ldx, int accumulate) {
+  // one thread per fine-grid element: each belongs to exactly one window
+  const Grid f{2 * g.nx, 2 * g.ny, 2 * g.nz};
+  const int64_t total = (int64_t)f.nx * f.ny * f.nz * channels;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % channels);
+    const int64_t v = e / channels;
+    const int xx = (int)(v % f.nx), yy = (int)((v / f.nx) % f.ny), zz = (int)(v / ((int64_t)f.nx * f.ny));
+    const int k = (xx & 1) | ((yy & 1) << 1) | ((zz & 1) << 2);
+    const int64_t cv = vidx(xx >> 1, yy >> 1, zz >> 1, g);
+    const float routed = arg[cv * channels + c] == k ? (float)dy[cv * ldy + c] : 0.f;
+    dx[v * ldx + c] = (bf16)(accumulate ? (float)dx[v * ldx + c] + routed : routed);
+  }
+}
+
+__global__ void k_relu_backward(int64_t n, int channels, const bf16 *y, int ldy, bf16 *dy, int lddy) {
+  const int64_t total = n * channels;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / channels;
+    const int c = (int)(e % channels);
+    if (!((float)y[row * ldy + c] > 0.f)) dy[row * lddy + c] = (bf16)0.f;
+  }
+}
+
+__global__ void k_mse(int64_t n, int channels, const float *pred, const float *target, const uint8_t *mask, float scale,
+                      bf16 *dpred, int ldd, float *loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n; row += (int64_t)gridDim.x * blockDim.x) {
+    const bool on = mask[row] == 0;
+    for (int c = 0; c < ldd; ++c) {
+      float g = 0.f;
+      if (c < channels && on) {
+        const float d = pred[row * channels + c] - target[row * channels + c];
+        s += d * d;
+        g = scale * 2.f * d;
+      }
+      dpred[row * ldd + c] = (bf16)g;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+}
+
+__global__ void k_adam(int64_t n, float *p, float *m, float *v, const float *g, bf16 *p16, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    const float pp = p[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    p[e] = pp;
+    if (p16) p16[e] = (bf16)pp;
+  }
+}
+
+__global__ void k_encode(int64_t n, const uint8_t *solid, float dx, float dy, float dz, bf16 *x) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool s = solid[e] != 0;
+    bf16 *row = x + e * 8;
+    row[0] = (bf16)(s ? 1.f : 0.f);
+    row[1] = (bf16)(s ? 0.f : dx);
+    row[2] = (bf16)(s ? 0.f : dy);
+    row[3] = (bf16)(s ? 0.f : dz);
+    for (int c = 4; c < 8; ++c) row[c] = (bf16)0.f;
+  }
+}
+
+__global__ void k_decode(int64_t n, const float *pred, const uint8_t *solid, double rho0, double scale, double *rho,
+                         double *u, double *acc) {
+  double s = 0.0, cnt = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool sd = solid[e] != 0;
+    const double r = sd ? 0.0 : rho0 + scale * (double)pred[4 * e];
+    rho[e] = r;
+    for (int k = 0; k < 3; ++k) u[k * n + e] = sd ? 0.0 : scale * (double)pred[4 * e + 1 + k];
+    if (!sd) {
+      s += r;
+      cnt += 1.0;
+    }
+  }
+  if (acc) {
+    atomicAdd(acc, s);
+    atomicAdd(acc + 1, cnt);
+  }
+}
+
+__global__ void k_renorm(int64_t n, const uint8_t *solid, double rho0, const double *acc, double *rho) {
+  const double shift = acc[1] > 0.0 ? rho0 - acc[0] / acc[1] : 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    if (!solid[e]) rho[e] += shift;
+}
+
+__global__ void k_zero2(double *p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0.0;
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+GemmArgs to_args(const lbm_nn_gemm *g) {
+  GemmArgs a;
+  a.rows = Grid{g->rows[0], g->rows[1], g->rows[2]};
+  if (g->src_mode == LBM_NN_GATHER2)
+    a.in_grid = Grid{2 * g->rows[0], 2 * g->rows[1], 2 * g->rows[2]};
+  else
+    a.in_grid = a.rows;
+  if (g->dst_mode == LBM_NN_SCATTER2)
+    a.out_grid = Grid{2 * g->rows[0], 2 * g->rows[1], 2 * g->rows[2]};
+  else
+    a.out_grid = a.rows;
+  a.taps = g->taps;
+  a.cin = g->cin;
+  a.cout = g->cout;
+  a.ldx = g->ldx;
+  a.ldy = g->ldy;
+  a.M = (int64_t)g->rows[0] * g->rows[1] * g->rows[2];
+  a.x = static_cast<const bf16 *>(g->x);
+  a.w = static_cast<const bf16 *>(g->w);
+  a.bias = g->bias;
+  a.y = g->y;
+  return a;
+}
+
+int check_gemm(const lbm_nn_gemm *g, bool wgrad) {
+  if (!g || !g->x || !g->y || (!wgrad && !g->w)) return set_error(LBM_ERR_ARG, "lbm_nn: NULL tensor");
+  for (int k = 0; k < 3; ++k)
+    if (g->rows[k] <= 0) return set_error(LBM_ERR_SHAPE, "lbm_nn: rows[%d] = %d", k, g->rows[k]);
+  const bool src_ok = g->src_mode == LBM_NN_IDENT || g->src_mode == LBM_NN_CONV3 || g->src_mode == LBM_NN_GATHER2;
+  const bool dst_ok = g->dst_mode == LBM_NN_IDENT || g->dst_mode == LBM_NN_SCATTER2;
+  if (!src_ok || !dst_ok) return set_error(LBM_ERR_ARG, "lbm_nn: modes %d/%d", g->src_mode, g->dst_mode);
+  const int want_taps = g->src_mode == LBM_NN_CONV3 ? 27 : (g->src_mode == LBM_NN_GATHER2 ? 8 : 1);
+  if (g->dst_mode == LBM_NN_SCATTER2 ? (g->taps != 8 || g->src_mode != LBM_NN_IDENT) : g->taps != want_taps)
+    return set_error(LBM_ERR_ARG, "lbm_nn: %d taps for modes %d/%d", g->taps, g->src_mode, g->dst_mode);
+  if (g->cin <= 0 || g->cin % 8 || g->ldx < g->cin || g->ldx % 8)
+    return set_error(LBM_ERR_SHAPE, "lbm_nn: cin %d / ldx %d must be multiples of 8", g->cin, g->ldx);
+  if (g->cout <= 0 || g->ldy < g->cout) return set_error(LBM_ERR_SHAPE, "lbm_nn: cout %d / ldy %d", g->cout, g->ldy);
+  if ((!g->y_fp32 || wgrad) && (g->cout % 8 || g->ldy % 8))
+    return set_error(LBM_ERR_SHAPE, "lbm_nn: BF16 rows need cout and ldy multiples of 8");
+  if ((uintptr_t)g->x % 16 || (g->w && (uintptr_t)g->w % 16) || (uintptr_t)g->y % 16)
+    return set_error(LBM_ERR_ARG, "lbm_nn: tensors must be 16-byte aligned");
+  return LBM_OK;
+}
+
+#define NN_TRY(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return set_error(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+template <int SRC, int DST, bool F32, bool RELU>
+hipError_t launch_fwd(const GemmArgs &a, int scatter_taps, hipStream_t s) {
+  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
+  const unsigned gx = (unsigned)((a.M + 63) / 64), gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
+  const dim3 grid(gx, gy, scatter_taps);
+  switch (nw) {
+    case 1: hipLaunchKernelGGL((k_forward<SRC, DST, 1, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_forward<SRC, DST, 2, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_forward<SRC, DST, 3, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_forward<SRC, DST, 4, F32, RELU>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int SRC, int DST>
+hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, int st, hipStream_t s) {
+  if (f32) return relu ? launch_fwd<SRC, DST, true, true>(a, st, s) : launch_fwd<SRC, DST, true, false>(a, st, s);
+  return relu ? launch_fwd<SRC, DST, false, true>(a, st, s) : launch_fwd<SRC, DST, false, false>(a, st, s);
+}
+
+template <int SRC, int DST, int CF, int NF>
+hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, hipStream_t s) {
+  const int cblocks = (a.cin + 16 * CF - 1) / (16 * CF), nblocks = (a.cout + 16 * NF - 1) / (16 * NF);
+  const int64_t other = (int64_t)a.taps * cblocks * nblocks;
+  int64_t chunks = (2048 + other - 1) / other;
+  const int64_t max_chunks = (a.M + 127) / 128;
+  if (chunks > max_chunks) chunks = max_chunks;
+  if (chunks < 1) chunks = 1;
+  int64_t chunk = (a.M + chunks - 1) / chunks;
+  chunk = (chunk + 127) / 128 * 128;
+  chunks = (a.M + chunk - 1) / chunk;
+  hipLaunchKernelGGL((k_wgrad<SRC, DST, CF, NF>), dim3((unsigned)chunks, (unsigned)(a.taps * cblocks), (unsigned)nblocks),
+                     dim3(256), 0, s, a, dw, chunk, cblocks);
+  return hipGetLastError();
+}
+
+template <int SRC, int DST>
+hipError_t launch_wgrad(const GemmArgs &a, float *dw, hipStream_t s) {
+  const int cf = a.cin <= 16 ? 1 : 2, nf = a.cout <= 16 ? 1 : 2;
+  if (cf == 1 && nf == 1) return launch_wgrad_cf<SRC, DST, 1, 1>(a, dw, s);
+  if (cf == 1) return launch_wgrad_cf<SRC, DST, 1, 2>(a, dw, s);
+  if (nf == 1) return launch_wgrad_cf<SRC, DST, 2, 1>(a, dw, s);
+  return launch_wgrad_cf<SRC, DST, 2, 2>(a, dw, s);
+}
+
+}  // namespace
+}  // namespace nn
+}  // namespace lbm
+
+using namespace lbm::nn;
+using lbm::set_error;
+
+extern "C" int lbm_nn_forward(const lbm_nn_gemm *g, void *stream) {
+  int rc = check_gemm(g, false);
+  if (rc) return rc;
+  const GemmArgs a = to_args(g);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f32 = g->y_fp32 != 0, relu = g->relu != 0;
+  if (g->dst_mode == LBM_NN_SCATTER2) {
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, f32, relu, 8, s)));
+  } else if (g->src_mode == LBM_NN_CONV3) {
+    NN_TRY((fwd_act<LBM_NN_CONV3, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+  } else if (g->src_mode == LBM_NN_GATHER2) {
+    NN_TRY((fwd_act<LBM_NN_GATHER2, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+  } else {
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream) {
+  int rc = check_gemm(g, true);
+  if (rc) return rc;
+  if (!dw) return set_error(LBM_ERR_ARG, "lbm_nn_wgrad: NULL dw");
+  const GemmArgs a = to_args(g);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (g->dst_mode == LBM_NN_SCATTER2) {
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, s)));
+  } else if (g->src_mode == LBM_NN_CONV3) {
+    NN_TRY((launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s)));
+  } else if (g->src_mode == LBM_NN_GATHER2) {
+    NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, s)));
+  } else {
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, s)));
+  }
+  if (db) {
+    int64_t chunk = 4096;
+    const unsigned gx = (unsigned)((a.M + chunk - 1) / chunk), gy = (unsigned)((a.cout + 63) / 64);
+    if (g->dst_mode == LBM_NN_SCATTER2)
+      hipLaunchKernelGGL(k_bias_grad<LBM_NN_SCATTER2>, dim3(gx, gy), dim3(256), 0, s, a, db, chunk);
+    else
+      hipLaunchKernelGGL(k_bias_grad<LBM_NN_IDENT>, dim3(gx, gy), dim3(256), 0, s, a, db, chunk);
+    NN_TRY(hipGetLastError());
+  }
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_backward_weights(int32_t mode, int32_t taps, int32_t cin, int32_t cout, const void *w, void *wt,
+                                       void *stream) {
+  if (!w || !wt || taps <= 0 || cin <= 0 || cout <= 0) return set_error(LBM_ERR_ARG, "lbm_nn_backward_weights: args");
+  if (mode == LBM_NN_CONV3 && taps != 27) return set_error(LBM_ERR_ARG, "lbm_nn_backward_weights: CONV3 needs 27 taps");
+  const int64_t n = (int64_t)taps * cin * cout;
+  hipLaunchKernelGGL(k_backward_weights, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), mode, taps,
+                     cin, cout, static_cast<const bf16 *>(w), static_cast<bf16 *>(wt));
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_maxpool2(const int32_t grid[3], int32_t channels, const void *x, int32_t ldx, void *y,
+                               int32_t ldy, uint8_t *arg, void *stream) {
+  if (!grid || !x || !y || !arg || channels <= 0 || ldx < channels || ldy < channels)
+    return set_error(LBM_ERR_ARG, "lbm_nn_maxpool2: args");
+  const Grid g{grid[0], grid[1], grid[2]};
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz * channels;
+  hipLaunchKernelGGL(k_maxpool, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), g, channels,
+                     static_cast<const bf16 *>(x), ldx, static_cast<bf16 *>(y), ldy, arg);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_maxpool2_backward(const int32_t grid[3], int32_t channels, const void *dy, int32_t ldy,
+                                        const uint8_t *arg, void *dx, int32_t ldx, int32_t accumulate, void *stream) {
+  if (!grid || !dy || !dx || !arg || channels <= 0 || ldx < channels || ldy < channels)
+    return set_error(LBM_ERR_ARG, "lbm_nn_maxpool2_backward: args");
+  const Grid g{grid[0], grid[1], grid[2]};
+  const int64_t n = (int64_t)8 * g.nx * g.ny * g.nz * channels;
+  hipLaunchKernelGGL(k_maxpool_backward, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), g,
+                     channels, static_cast<const bf16 *>(dy), ldy, arg, static_cast<bf16 *>(dx), ldx, accumulate);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_relu_backward(int64_t n, int32_t channels, const void *y, int32_t ld_y, void *dy, int32_t ld_dy,
+                                    void *stream) {
+  if (!y || !dy || n < 0 || channels <= 0) return set_error(LBM_ERR_ARG, "lbm_nn_relu_backward: args");
+  hipLaunchKernelGGL(k_relu_backward, dim3(grid_for(n * channels)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
+                     channels, static_cast<const bf16 *>(y), ld_y, static_cast<bf16 *>(dy), ld_dy);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_mse(int64_t n, int32_t channels, const float *pred, const float *target, const uint8_t *mask,
+                          float scale, void *dpred, int32_t ldd, float *loss_acc, void *stream) {
+  if (!pred || !target || !mask || !dpred || !loss_acc || channels <= 0 || ldd < channels)
+    return set_error(LBM_ERR_ARG, "lbm_nn_mse: args");
+  hipLaunchKernelGGL(k_mse, dim3(grid_for(n) < 2048 ? grid_for(n) : 2048), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), n, channels, pred, target, mask, scale,
+                     static_cast<bf16 *>(dpred), ldd, loss_acc);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_adam(int64_t n, float *p, float *m, float *v, const float *g, void *p16, float lr, float beta1,
+                           float beta2, float eps, int32_t step, void *stream) {
+  if (!p || !m || !v || !g || n < 0 || step < 1) return set_error(LBM_ERR_ARG, "lbm_nn_adam: args");
+  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, p, m, v, g,
+                     static_cast<bf16 *>(p16), lr, beta1, beta2, eps, c1, c2);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_encode_input(int64_t n, const uint8_t *solid, const float dir[3], void *x, void *stream) {
+  if (!solid || !dir || !x || n < 0) return set_error(LBM_ERR_ARG, "lbm_nn_encode_input: args");
+  hipLaunchKernelGGL(k_encode, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, solid, dir[0],
+                     dir[1], dir[2], static_cast<bf16 *>(x));
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_decode_output(int64_t n, const float *pred, const uint8_t *solid, double rho0, double scale,
+                                    int32_t renorm, double *rho, double *u, double *scratch, void *stream) {
+  if (!pred || !solid || !rho || !u || n < 0 || (renorm && !scratch))
+    return set_error(LBM_ERR_ARG, "lbm_nn_decode_output: args");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (renorm) hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, scratch);
+  hipLaunchKernelGGL(k_decode, dim3(grid_for(n)), dim3(256), 0, s, n, pred, solid, rho0, scale, rho, u,
+                     renorm ? scratch : nullptr);
+  if (renorm) hipLaunchKernelGGL(k_renorm, dim3(grid_for(n)), dim3(256), 0, s, n, solid, rho0, scratch, rho);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}

@@ -1,0 +1,251 @@
+"""3D convolutional U-Net for the learned warm start, assembled from the
+liblbm layer kernels (BF16 MFMA convolutions with FP32 accumulation).
+
+Input per voxel: (solid, force direction on fluid voxels) padded to 8
+channels.  Output per voxel: 4 values, the steady (rho - rho0, u) divided by
+a scale; by the linearity of slow (Stokes) flow in the force, the target is
+(rho - rho0, u) * nu / |g| / out_scale.
+
+Levels l = 0..L-1 carry base * 2^l channels.  Encoder level l: two 3x3x3
+circular convolutions with ReLU; the second writes into the first half of a
+concatenation buffer (the skip).  Between levels: 2x2x2 max pooling.  Bottom
+level: two convolutions.  Decoder level l: a 2x2x2 stride-2 transposed
+convolution into the second half of the concatenation buffer, then two
+convolutions with ReLU.  Head: 1x1x1 convolution to 4 channels (FP32).
+Grid edges must be multiples of 2^(L-1).
+"""
+import math
+
+from . import nn
+
+
+class Param:
+    """FP32 master weights, Adam moments, FP32 gradient and the BF16 copy."""
+
+    def __init__(self, torch, shape, fan_in, device, gen, zero=False, bias=False):
+        if zero:
+            w = torch.zeros(shape, dtype=torch.float32)
+        elif bias:
+            w = torch.zeros(shape, dtype=torch.float32)
+        else:
+            w = torch.randn(shape, generator=gen, dtype=torch.float32) * math.sqrt(2.0 / fan_in)
+        self.p = w.to(device)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.g = torch.zeros_like(self.p)
+        self.b16 = self.p.to(torch.bfloat16) if not bias else None
+
+
+class UNet:
+    def __init__(self, levels=4, base=24, in_ch=8, out_ch=4, seed=0, device="cuda", out_scale=1.0):
+        import torch
+        self.torch = torch
+        self.L = levels
+        self.C = [base * 2 ** l for l in range(levels)]
+        self.in_ch, self.out_ch = in_ch, out_ch
+        self.out_pad = 8  # head gradient rows are 8 BF16 wide (channels 4..7 stay zero)
+        self.device = torch.device(device)
+        self.out_scale = out_scale
+        gen = torch.Generator().manual_seed(seed)
+        P = lambda shape, fan, **kw: Param(torch, shape, fan, self.device, gen, **kw)
+        self.enc = []
+        cin = in_ch
+        for l in range(levels):
+            c = self.C[l]
+            self.enc.append([(P((c, 27, cin), 27 * cin), P((c,), 1, bias=True)),
+                             (P((c, 27, c), 27 * c), P((c,), 1, bias=True))])
+            cin = c
+        self.up, self.dec = [], []
+        for l in range(levels - 2, -1, -1):
+            c, cd = self.C[l], self.C[l + 1]
+            self.up.append((P((c, 8, cd), cd), P((c,), 1, bias=True)))
+            self.dec.append([(P((c, 27, 2 * c), 27 * 2 * c), P((c,), 1, bias=True)),
+                             (P((c, 27, c), 27 * c), P((c,), 1, bias=True))])
+        hw = P((self.out_pad, 1, self.C[0]), self.C[0])
+        hw.p[out_ch:] = 0.0  # unused rows
+        hw.b16 = hw.p.to(torch.bfloat16)
+        self.head = (hw, P((self.out_pad,), 1, bias=True))
+        self.params = [p for lvl in self.enc for pair in lvl for p in pair]
+        self.params += [p for pair in self.up for p in pair]
+        self.params += [p for lvl in self.dec for pair in lvl for p in pair]
+        self.params += list(self.head)
+        self.step_count = 0
+        self._cache = None
+
+    def n_params(self):
+        return int(sum(p.p.numel() for p in self.params) - (self.out_pad - self.out_ch) * (self.C[0] + 1))
+
+    # ---- activations -------------------------------------------------------
+    def _alloc(self, shape):
+        t = self.torch
+        nz, ny, nx = shape
+        L = self.L
+        if nx % 2 ** (L - 1) or ny % 2 ** (L - 1) or nz % 2 ** (L - 1):
+            raise ValueError("grid %s not divisible by %d" % (shape, 2 ** (L - 1)))
+        A = {}
+        grids = [(nz >> l, ny >> l, nx >> l) for l in range(L)]
+        bf = dict(dtype=t.bfloat16, device=self.device)
+        for l in range(L):
+            g = grids[l]
+            c = self.C[l]
+            A["e1", l] = t.empty(g + (c,), **bf)
+            width = 2 * c if l < L - 1 else c  # concat buffer [skip | up] except at the bottom
+            A["cat", l] = t.empty(g + (width,), **bf)
+            if l < L - 1:
+                A["d1", l] = t.empty(g + (c,), **bf)
+                A["d2", l] = t.empty(g + (c,), **bf)
+            if l > 0:
+                A["pool", l] = t.empty(g + (self.C[l - 1],), **bf)
+                A["arg", l] = t.empty(g + (self.C[l - 1],), dtype=t.uint8, device=self.device)
+        A["out"] = t.empty(grids[0] + (self.out_ch,), dtype=t.float32, device=self.device)
+        return A, grids
+
+    @staticmethod
+    def _rows(g):
+        return (g[2], g[1], g[0])  # (nx, ny, nz)
+
+    # ---- forward -------------------------------------------------------------
+    def forward(self, x):
+        """x: BF16 (nz, ny, nx, in_ch).  Returns FP32 (nz, ny, nx, 4)."""
+        shape = tuple(x.shape[:3])
+        if self._cache is None or self._cache[0] != shape:
+            self._cache = (shape,) + self._alloc(shape)
+        _, A, grids = self._cache
+        self._x = x
+        L, C = self.L, self.C
+        src, srcld, srcc = x, self.in_ch, self.in_ch
+        for l in range(L):
+            rows = self._rows(grids[l])
+            (w1, b1), (w2, b2) = self.enc[l]
+            if l > 0:
+                nn.maxpool2(rows, C[l - 1], A["cat", l - 1], 2 * C[l - 1], A["pool", l], C[l - 1], A["arg", l])
+                src, srcld, srcc = A["pool", l], C[l - 1], C[l - 1]
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, srcc, C[l], src, srcld, w1.b16, A["e1", l], C[l], bias=b1.p,
+                       relu=True)
+            width = A["cat", l].shape[-1]
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["e1", l], C[l], w2.b16, A["cat", l], width,
+                       bias=b2.p, relu=True)
+        below = A["cat", L - 1]
+        for k, l in enumerate(range(L - 2, -1, -1)):
+            rows_c, rows = self._rows(grids[l + 1]), self._rows(grids[l])
+            uw, ub = self.up[k]
+            (w1, b1), (w2, b2) = self.dec[k]
+            ldb = below.shape[-1]
+            nn.forward(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], below, ldb, uw.b16, A["cat", l], 2 * C[l],
+                       bias=ub.p, y_offset=C[l])
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1.b16, A["d1", l], C[l],
+                       bias=b1.p, relu=True)
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["d1", l], C[l], w2.b16, A["d2", l], C[l],
+                       bias=b2.p, relu=True)
+            below = A["d2", l]
+        hw, hb = self.head
+        nn.forward(nn.IDENT, nn.IDENT, self._rows(grids[0]), 1, C[0], self.out_ch, below, C[0], hw.b16, A["out"],
+                   self.out_ch, bias=hb.p, y_fp32=True)
+        return A["out"]
+
+    # ---- backward ------------------------------------------------------------
+    def _conv_backward(self, rows, cin, cout, x, ldx, w, b, y, ldy, dy, lddy, dx, lddx, relu=True, need_dx=True,
+                       dy_offset=0, y_offset=0, x_offset=0):
+        n = rows[0] * rows[1] * rows[2]
+        if relu:
+            nn.relu_backward(n, cout, y, ldy, dy, lddy, y_offset=y_offset, dy_offset=dy_offset)
+        nn.wgrad(nn.CONV3, nn.IDENT, rows, 27, cin, cout, x, ldx, dy, lddy, w.g, b.g, x_offset=x_offset,
+                 dy_offset=dy_offset)
+        if need_dx:
+            wt = self._wt(w, nn.CONV3, 27, cin, cout)
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, x_offset=dy_offset)
+
+    def _wt(self, w, mode, taps, cin, cout):
+        t = self.torch
+        key = ("wt", id(w))
+        buf = self._wt_cache.get(key)
+        if buf is None:
+            buf = t.empty((cin, taps, cout), dtype=t.bfloat16, device=self.device)
+            self._wt_cache[key] = buf
+        nn.backward_weights(mode, taps, cin, cout, w.b16, buf)
+        return buf
+
+    def backward(self, dout):
+        """dout: BF16 (nz, ny, nx, 8) gradient of the loss wrt the head output
+        (channels 4..7 zero).  Accumulates parameter gradients."""
+        t = self.torch
+        _, A, grids = self._cache
+        L, C = self.L, self.C
+        if not hasattr(self, "_wt_cache"):
+            self._wt_cache = {}
+        G = self._grads(A, grids)
+        hw, hb = self.head
+        rows0 = self._rows(grids[0])
+        below = A["d2", 0] if L > 1 else A["cat", 0]
+        ldbelow = C[0] if L > 1 else A["cat", 0].shape[-1]
+        nn.wgrad(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g)
+        wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
+        d_below = G["d2", 0] if L > 1 else G["cat", 0]
+        nn.forward(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow)
+        # decoder, top level first (reverse of the forward order)
+        for k, l in enumerate(range(0, L - 1)):
+            idx = L - 2 - l  # position of level l in self.up / self.dec
+            rows, rows_c = self._rows(grids[l]), self._rows(grids[l + 1])
+            uw, ub = self.up[idx]
+            (w1, b1), (w2, b2) = self.dec[idx]
+            self._conv_backward(rows, C[l], C[l], A["d1", l], C[l], w2, b2, A["d2", l], C[l], G["d2", l], C[l],
+                                G["d1", l], C[l])
+            self._conv_backward(rows, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1, b1, A["d1", l], C[l], G["d1", l],
+                                C[l], G["cat", l], 2 * C[l])
+            # transposed conv: input = level l+1 output (d2 of l+1, or the bottom cat buffer)
+            if l + 1 == L - 1:
+                xin, ldxin, dxin = A["cat", L - 1], A["cat", L - 1].shape[-1], G["cat", L - 1]
+            else:
+                xin, ldxin, dxin = A["d2", l + 1], C[l + 1], G["d2", l + 1]
+            nn.wgrad(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], xin, ldxin, G["cat", l], 2 * C[l], uw.g, ub.g,
+                     dy_offset=C[l])
+            wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
+            nn.forward(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
+                       x_offset=C[l])
+        # encoder, bottom level first
+        for l in range(L - 1, -1, -1):
+            rows = self._rows(grids[l])
+            (w1, b1), (w2, b2) = self.enc[l]
+            width = A["cat", l].shape[-1]
+            self._conv_backward(rows, C[l], C[l], A["e1", l], C[l], w2, b2, A["cat", l], width, G["cat", l], width,
+                                G["e1", l], C[l])
+            if l > 0:
+                self._conv_backward(rows, C[l - 1], C[l], A["pool", l], C[l - 1], w1, b1, A["e1", l], C[l],
+                                    G["e1", l], C[l], G["pool", l], C[l - 1])
+                # pooled gradient joins the skip gradient already in the first half of cat[l-1]
+                nn.maxpool2_backward(rows, C[l - 1], G["pool", l], C[l - 1], A["arg", l], G["cat", l - 1],
+                                     2 * C[l - 1], accumulate=True)
+            else:
+                self._conv_backward(rows, self.in_ch, C[0], self._x, self.in_ch, w1, b1, A["e1", 0], C[0], G["e1", 0],
+                                    C[0], None, 0, need_dx=False)
+
+    def _grads(self, A, grids):
+        t = self.torch
+        if getattr(self, "_gcache", None) is None or self._gcache[0] != self._cache[0]:
+            G = {}
+            for k, v in A.items():
+                if isinstance(k, tuple) and k[0] in ("e1", "cat", "d1", "d2", "pool"):
+                    G[k] = t.empty_like(v)
+            self._gcache = (self._cache[0], G)
+        return self._gcache[1]
+
+    def zero_grad(self):
+        for p in self.params:
+            p.g.zero_()
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        for p in self.params:
+            nn.adam(p.p, p.m, p.v, p.g, p.b16, lr, self.step_count, beta1, beta2, eps)
+
+    # ---- state -------------------------------------------------------------------
+    def state_dict(self):
+        return {"levels": self.L, "base": self.C[0], "out_scale": self.out_scale,
+                "params": [p.p.cpu() for p in self.params]}
+
+    def load_state_dict(self, sd):
+        for p, v in zip(self.params, sd["params"]):
+            p.p.copy_(v.to(self.device))
+            if p.b16 is not None:
+                p.b16.copy_(p.p.to(self.torch.bfloat16))
+        self.out_scale = sd["out_scale"]

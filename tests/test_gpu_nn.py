@@ -1,0 +1,300 @@
+"""GPU layer kernels of the warm-start network against the FP64 NumPy
+oracle.  Inputs and weights are rounded to BF16 first, so the differences
+left are FP32 accumulation order and the BF16 rounding of outputs."""
+import numpy as np
+import pytest
+
+from oracle import nn as onn
+from paper_1703_08015_amd import nn
+
+pytestmark = pytest.mark.gpu
+rng = np.random.default_rng(7)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def bf(a):
+    """Round to the nearest BF16 value (ties to even), as float64."""
+    a32 = np.asarray(a, np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def dev(torch, a, dtype=None):
+    dtype = dtype or torch.bfloat16
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def close(got, want, rel=1.5e-2):
+    scale = max(np.max(np.abs(want)), 1e-30)
+    err = np.max(np.abs(got - want)) / scale
+    assert err <= rel, err
+
+
+GRID = (4, 5, 6)  # (nz, ny, nx): 120 voxels, not a multiple of the 64-row tile
+
+
+def rows_of(shape):
+    return (shape[2], shape[1], shape[0])
+
+
+@pytest.mark.parametrize("cin,cout,relu", [(8, 24, True), (24, 48, False), (48, 24, True), (16, 8, False)])
+def test_conv3_forward_backward(torch, cin, cout, relu):
+    x = bf(rng.normal(size=GRID + (cin,)))
+    w = bf(rng.normal(size=(cout, 27, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    y = torch.empty(GRID + (cout,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.CONV3, nn.IDENT, rows_of(GRID), 27, cin, cout, dev(torch, x), cin, dev(torch, w), y, cout,
+               bias=dev(torch, b, torch.float32), relu=relu)
+    want = onn.conv3(x, w, b)
+    if relu:
+        want = onn.relu(want)
+    close(host(y), want)
+    # backward data and weights for an output gradient dy
+    dy = bf(rng.normal(size=GRID + (cout,)))
+    wt = torch.empty((cin, 27, cout), dtype=torch.bfloat16, device="cuda")
+    nn.backward_weights(nn.CONV3, 27, cin, cout, dev(torch, w), wt)
+    dx = torch.empty(GRID + (cin,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.CONV3, nn.IDENT, rows_of(GRID), 27, cout, cin, dev(torch, dy), cout, wt, dx, cin)
+    gx, gw, gb = onn.conv3_backward(x, w, dy)
+    close(host(dx), gx)
+    dw = torch.zeros((cout, 27, cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.CONV3, nn.IDENT, rows_of(GRID), 27, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw, db)
+    close(host(dw), gw, 2e-5)
+    close(host(db), gb, 2e-5)
+
+
+def test_conv3_wgrad_large_grid_split(torch):
+    """Voxel counts far above one workgroup's chunk exercise the split reduction."""
+    g = (24, 20, 16)
+    x = bf(rng.normal(size=g + (24,)))
+    dy = bf(rng.normal(size=g + (24,)))
+    dw = torch.zeros((24, 27, 24), dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.CONV3, nn.IDENT, rows_of(g), 27, 24, 24, dev(torch, x), 24, dev(torch, dy), 24, dw)
+    _, gw, _ = onn.conv3_backward(x, np.zeros((24, 27, 24)), dy)
+    close(host(dw), gw, 2e-5)
+
+
+@pytest.mark.parametrize("cin,cout", [(48, 24), (16, 8)])
+def test_up2_forward_backward(torch, cin, cout):
+    coarse = (2, 3, 2)
+    fine = tuple(2 * v for v in coarse)
+    x = bf(rng.normal(size=coarse + (cin,)))
+    w = bf(rng.normal(size=(cout, 8, cin)) * 0.2)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    # output written into the second half of a concatenation buffer
+    cat = torch.zeros(fine + (2 * cout,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.IDENT, nn.SCATTER2, rows_of(coarse), 8, cin, cout, dev(torch, x), cin, dev(torch, w), cat, 2 * cout,
+               bias=dev(torch, b, torch.float32), y_offset=cout)
+    close(host(cat)[..., cout:], onn.up2(x, w, b))
+    assert not host(cat)[..., :cout].any()
+    dyc = bf(rng.normal(size=fine + (2 * cout,)))
+    dy = dyc[..., cout:]
+    wt = torch.empty((cin, 8, cout), dtype=torch.bfloat16, device="cuda")
+    nn.backward_weights(nn.SCATTER2, 8, cin, cout, dev(torch, w), wt)
+    dx = torch.empty(coarse + (cin,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.GATHER2, nn.IDENT, rows_of(coarse), 8, cout, cin, dev(torch, dyc), 2 * cout, wt, dx, cin,
+               x_offset=cout)
+    gx, gw, gb = onn.up2_backward(x, w, dy)
+    close(host(dx), gx)
+    dw = torch.zeros((cout, 8, cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.IDENT, nn.SCATTER2, rows_of(coarse), 8, cin, cout, dev(torch, x), cin, dev(torch, dyc), 2 * cout, dw,
+             db, dy_offset=cout)
+    close(host(dw), gw, 2e-5)
+    close(host(db), gb, 2e-5)
+
+
+def test_head_dense_fp32_and_backward(torch):
+    x = bf(rng.normal(size=GRID + (24,)))
+    w = np.zeros((8, 1, 24))
+    w[:4] = bf(rng.normal(size=(4, 1, 24)))
+    b = np.zeros(8)
+    b[:4] = rng.normal(size=4).astype(np.float32)
+    out = torch.empty(GRID + (4,), dtype=torch.float32, device="cuda")
+    nn.forward(nn.IDENT, nn.IDENT, rows_of(GRID), 1, 24, 4, dev(torch, x), 24, dev(torch, w), out, 4,
+               bias=dev(torch, b, torch.float32), y_fp32=True)
+    close(host(out), onn.dense(x, w[:4, 0], b[:4]), 1e-5)
+    dy = np.zeros(GRID + (8,))
+    dy[..., :4] = bf(rng.normal(size=GRID + (4,)))
+    dw = torch.zeros((8, 1, 24), dtype=torch.float32, device="cuda")
+    db = torch.zeros(8, dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.IDENT, nn.IDENT, rows_of(GRID), 1, 24, 8, dev(torch, x), 24, dev(torch, dy), 8, dw, db)
+    gx, gw, gb = onn.dense_backward(x, w[:, 0], dy)
+    close(host(dw)[:, 0], gw, 2e-5)
+    close(host(db), gb, 2e-5)
+    wt = torch.empty((24, 1, 8), dtype=torch.bfloat16, device="cuda")
+    nn.backward_weights(nn.IDENT, 1, 24, 8, dev(torch, w), wt)
+    dx = torch.empty(GRID + (24,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.IDENT, nn.IDENT, rows_of(GRID), 1, 8, 24, dev(torch, dy), 8, wt, dx, 24)
+    close(host(dx), gx)
+
+
+def test_maxpool_relu_mse_adam(torch):
+    coarse = (2, 2, 3)
+    fine = tuple(2 * v for v in coarse)
+    x = bf(rng.normal(size=fine + (16,)))
+    y = torch.empty(coarse + (16,), dtype=torch.bfloat16, device="cuda")
+    arg = torch.empty(coarse + (16,), dtype=torch.uint8, device="cuda")
+    nn.maxpool2(rows_of(coarse), 16, dev(torch, x), 16, y, 16, arg)
+    wy, warg = onn.maxpool2(x)
+    assert np.array_equal(host(y), wy) and np.array_equal(arg.cpu().numpy(), warg)
+    dy = bf(rng.normal(size=coarse + (16,)))
+    base = bf(rng.normal(size=fine + (16,)))
+    dx = dev(torch, base)
+    nn.maxpool2_backward(rows_of(coarse), 16, dev(torch, dy), 16, arg, dx, 16, accumulate=True)
+    close(host(dx), base + onn.maxpool2_backward(warg, dy), 1e-2)
+    nn.maxpool2_backward(rows_of(coarse), 16, dev(torch, dy), 16, arg, dx, 16)
+    assert np.array_equal(host(dx), onn.maxpool2_backward(warg, dy))
+    # relu backward
+    yv = bf(rng.normal(size=(40, 8)))
+    g = bf(rng.normal(size=(40, 8)))
+    gd = dev(torch, g)
+    nn.relu_backward(40, 8, dev(torch, yv), 8, gd, 8)
+    assert np.array_equal(host(gd), onn.relu_backward(yv, g))
+    # masked MSE
+    pred = rng.normal(size=(50, 4)).astype(np.float32)
+    targ = rng.normal(size=(50, 4)).astype(np.float32)
+    solid = (rng.random(50) < 0.3).astype(np.uint8)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dp = torch.empty((50, 8), dtype=torch.bfloat16, device="cuda")
+    nn.mse(50, 4, dev(torch, pred, torch.float32), dev(torch, targ, torch.float32), dev(torch, solid, torch.uint8),
+           0.5, dp, 8, loss)
+    wl, wg = onn.masked_mse(pred.astype(np.float64), targ.astype(np.float64), solid.astype(bool))
+    assert np.isclose(float(loss.item()), wl, rtol=1e-5)
+    close(host(dp)[:, :4], 0.5 * wg, 1e-2)
+    assert not host(dp)[:, 4:].any()
+    # Adam (FP32) against the FP64 definition
+    p0 = rng.normal(size=300).astype(np.float32)
+    gr = rng.normal(size=300).astype(np.float32)
+    P, M, V = [dev(torch, a, torch.float32) for a in (p0, np.zeros(300), np.zeros(300))]
+    G = dev(torch, gr, torch.float32)
+    p16 = torch.empty(300, dtype=torch.bfloat16, device="cuda")
+    pp, mm, vv = p0.astype(np.float64), np.zeros(300), np.zeros(300)
+    for step in (1, 2, 3):
+        nn.adam(P, M, V, G, p16, 1e-2, step)
+        pp, mm, vv = onn.adam(pp, mm, vv, gr.astype(np.float64), 1e-2, 0.9, 0.999, 1e-8, step)
+    assert np.allclose(host(P), pp, rtol=1e-5, atol=1e-6)
+    assert np.array_equal(host(p16), bf(host(P)))
+
+
+def test_encode_decode(torch):
+    solid = (rng.random(GRID) < 0.4).astype(np.uint8)
+    x = torch.empty(GRID + (8,), dtype=torch.bfloat16, device="cuda")
+    d = np.array([0.6, -0.8, 0.0])
+    nn.encode_input(dev(torch, solid, torch.uint8), d, x)
+    hx = host(x)
+    assert np.array_equal(hx[..., 0], solid.astype(float))
+    assert np.allclose(hx[solid == 0][:, 1:4], bf(d)) and not hx[solid == 1][:, 1:].any()
+    pred = rng.normal(size=GRID + (4,)).astype(np.float32)
+    rho = torch.empty(GRID, dtype=torch.float64, device="cuda")
+    u = torch.empty((3,) + GRID, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(2, dtype=torch.float64, device="cuda")
+    nn.decode_output(dev(torch, pred, torch.float32), dev(torch, solid, torch.uint8), 1.0, 1e-3, rho, u, scratch)
+    r, uu = rho.cpu().numpy(), u.cpu().numpy()
+    fl = solid == 0
+    assert np.isclose(r[fl].sum(), fl.sum(), rtol=1e-12) and np.all(r[~fl] == 0)
+    want_u = np.moveaxis(pred[..., 1:].astype(np.float64) * 1e-3, -1, 0)
+    assert np.allclose(uu[:, fl], want_u[:, fl], rtol=1e-12) and not uu[:, ~fl].any()
+    raw = 1.0 + 1e-3 * pred[..., 0].astype(np.float64)
+    assert np.allclose(r[fl], raw[fl] - raw[fl].mean() + 1.0, rtol=1e-12)
+
+
+def _oracle_unet(net, x, dout):
+    """The same network from the FP64 oracle layers, rounding activations and
+    activation gradients to BF16 where the GPU stores them.  Returns the
+    output and the gradient of every parameter (in net.params order)."""
+    L, C = net.L, net.C
+    P = lambda p: p.p.cpu().numpy().astype(np.float64)
+    W = lambda p: bf(P(p))
+    A = {}
+    src = x
+    for l in range(L):
+        (w1, b1), (w2, b2) = net.enc[l]
+        if l > 0:
+            A["pool", l], A["arg", l] = onn.maxpool2(A["cat", l - 1])
+            src = A["pool", l]
+        A["in", l] = src
+        A["e1", l] = bf(onn.relu(onn.conv3(src, W(w1), P(b1))))
+        A["cat", l] = bf(onn.relu(onn.conv3(A["e1", l], W(w2), P(b2))))
+    below = A["cat", L - 1]
+    for k, l in enumerate(range(L - 2, -1, -1)):
+        uw, ub = net.up[k]
+        (w1, b1), (w2, b2) = net.dec[k]
+        A["below", l] = below
+        A["up", l] = bf(onn.up2(below, W(uw), P(ub)))
+        A["catfull", l] = np.concatenate([A["cat", l], A["up", l]], axis=-1)
+        A["d1", l] = bf(onn.relu(onn.conv3(A["catfull", l], W(w1), P(b1))))
+        A["d2", l] = bf(onn.relu(onn.conv3(A["d1", l], W(w2), P(b2))))
+        below = A["d2", l]
+    hw, hb = net.head
+    out = onn.dense(below, W(hw)[:, 0], P(hb))[..., :net.out_ch]
+    grads = {}
+    g_below, grads["hw"], grads["hb"] = onn.dense_backward(below, W(hw)[:, 0], dout)
+    g_below = bf(g_below)
+    gcat = {}
+    for l in range(0, L - 1):
+        idx = L - 2 - l
+        uw, ub = net.up[idx]
+        (w1, b1), (w2, b2) = net.dec[idx]
+        g = bf(onn.relu_backward(A["d2", l], g_below))
+        gx, grads["dec", idx, 1, "w"], grads["dec", idx, 1, "b"] = onn.conv3_backward(A["d1", l], W(w2), g)
+        g = bf(onn.relu_backward(A["d1", l], bf(gx)))
+        gx, grads["dec", idx, 0, "w"], grads["dec", idx, 0, "b"] = onn.conv3_backward(A["catfull", l], W(w1), g)
+        gx = bf(gx)
+        gcat[l] = gx[..., :C[l]]
+        gup = gx[..., C[l]:]
+        gb_, grads["up", idx, "w"], grads["up", idx, "b"] = onn.up2_backward(A["below", l], W(uw), gup)
+        g_below = bf(gb_)
+    gcat[L - 1] = g_below
+    for l in range(L - 1, -1, -1):
+        (w1, b1), (w2, b2) = net.enc[l]
+        g = bf(onn.relu_backward(A["cat", l], gcat[l]))
+        gx, grads["enc", l, 1, "w"], grads["enc", l, 1, "b"] = onn.conv3_backward(A["e1", l], W(w2), g)
+        g = bf(onn.relu_backward(A["e1", l], bf(gx)))
+        gx, grads["enc", l, 0, "w"], grads["enc", l, 0, "b"] = onn.conv3_backward(A["in", l], W(w1), g)
+        if l > 0:
+            gcat[l - 1] = bf(gcat[l - 1] + onn.maxpool2_backward(A["arg", l], bf(gx)))
+    order = []
+    for l in range(L):
+        for j in range(2):
+            order += [grads["enc", l, j, "w"], grads["enc", l, j, "b"]]
+    for k in range(L - 1):
+        order += [grads["up", k, "w"], grads["up", k, "b"]]
+    for k in range(L - 1):
+        for j in range(2):
+            order += [grads["dec", k, j, "w"], grads["dec", k, j, "b"]]
+    order += [grads["hw"][:, None, :], grads["hb"]]
+    return out, order
+
+
+def test_unet_forward_and_gradients_match_oracle(torch):
+    from paper_1703_08015_amd.unet import UNet
+    net = UNet(levels=3, base=8, seed=3)
+    g = (8, 8, 8)
+    x = np.zeros(g + (8,))
+    x[..., :4] = bf(rng.normal(size=g + (4,)))
+    out = net.forward(dev(torch, x))
+    dout = np.zeros(g + (8,))
+    dout[..., :4] = bf(rng.normal(size=g + (4,)))
+    net.zero_grad()
+    net.backward(dev(torch, dout))
+    torch.cuda.synchronize()
+    want_out, want_grads = _oracle_unet(net, x, dout)
+    close(host(out), want_out, 2e-2)
+    assert len(want_grads) == len(net.params)
+    for k, (p, wg) in enumerate(zip(net.params, want_grads)):
+        got = host(p.g)
+        assert got.shape == wg.shape, k
+        close(got, wg, 6e-2)
