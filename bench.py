@@ -228,6 +228,63 @@ def mode_batch(args, torch, lbm):
             "node_updates": updates, "mlups": round(updates / wall / 1e6, 1), "geometry_seconds": round(t_geom, 1)}
 
 
+def mode_warmstart(args, torch, lbm):
+    """Train the U-Net on steady states of the porous-cube batch (edges that
+    are multiples of 8), then compare warm and cold starts to the same
+    residual on held-out 128^3 porous samples."""
+    from paper_1703_08015_amd import inputs, warmstart
+    t0 = time.perf_counter()
+    specs = [sp for sp in inputs.batch_specs(args.batch, seed=args.seed + 1000) if sp["edge"] % 8 == 0]
+    masks = [inputs.porous_cube(sp)[0] for sp in specs]
+    data, steps, _ = warmstart.steady_dataset(torch, masks, [sp["g"] for sp in specs], tau=args.tau,
+                                              progress=_progress("data"))
+    t_data = time.perf_counter() - t0
+    out_scale = warmstart.make_targets(torch, data, args.tau)
+    net = warmstart.make_net(levels=4, base=24, seed=args.seed, out_scale=out_scale)
+    t1 = time.perf_counter()
+    hist = warmstart.train(torch, net, data, epochs=args.epochs, lr=args.lr,
+                           progress=lambda ep, l: print("[train] epoch %d loss %.4e" % (ep, l), file=sys.stderr,
+                                                        flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del data
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(args.seed + 5000)
+    tests = []
+    for k in range(args.test_samples):
+        phi = float(rng.uniform(0.3, 0.7))
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        m, _ = inputs.spheres_3d(128, phi, 4.0, 12.0, seed=args.seed + 5000 + k)
+        tests.append(warmstart.Sample(torch, m, (1e-6 * d).tolist()))
+    rows = []
+    for k, sm in enumerate(tests):
+        r = warmstart.evaluate(torch, net, [sm], args.tau)[0]
+        print("[eval] sample %d cold %d steps %.2fs warm %d steps %.2fs pred err %.3f agree %.1e%s"
+              % (k, r["cold_steps"], r["cold_s"], r["warm_steps"], r["warm_s"], r["prediction_u_rel_l2"],
+                 r["warm_vs_cold_u_rel_l2"], " (fell back)" if r["fell_back"] else ""), file=sys.stderr, flush=True)
+        rows.append(r)
+    cold_s = sum(r["cold_s"] for r in rows)
+    warm_s = sum(r["warm_s"] for r in rows)
+    return {"metric": "time to steady state, warm vs cold start", "unit": "s", "higher_is_better": False,
+            "value": round(warm_s, 3), "data": "synthetic", "dtype": "f32 (solver), bf16 (network)",
+            "config": {"workload": "%d held-out 128^3 periodic porous samples (spheres r 4-12, porosity U[0.3, 0.7], "
+                                   "|g| 1e-6 random direction), tau %.2f, FP32 LBM to residual %g" %
+                                   (args.test_samples, args.tau, args.tol),
+                       "network": "U-Net 4 levels, 24 base channels, %d parameters" % net.n_params(),
+                       "training": "%d porous cubes (edges 32..96, multiples of 8), %d epochs, Adam lr %g" %
+                                   (len(specs), args.epochs, args.lr)},
+            "cold_seconds": round(cold_s, 3), "warm_seconds_incl_inference": round(warm_s, 3),
+            "speedup": round(cold_s / warm_s, 3) if warm_s > 0 else None,
+            "cold_steps_mean": float(np.mean([r["cold_steps"] for r in rows])),
+            "warm_steps_mean": float(np.mean([r["warm_steps"] for r in rows])),
+            "prediction_u_rel_l2_mean": float(np.mean([r["prediction_u_rel_l2"] for r in rows])),
+            "warm_vs_cold_u_rel_l2_max": float(np.max([r["warm_vs_cold_u_rel_l2"] for r in rows])),
+            "fallbacks": int(sum(r["fell_back"] for r in rows)),
+            "train_loss_first_last": [hist[0], hist[-1]], "data_seconds": round(t_data, 1),
+            "train_seconds": round(t_train, 1), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +304,10 @@ def main():
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch"])
+    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart"])
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--test-samples", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--max-steps", type=int, default=200000)
@@ -270,10 +330,11 @@ def main():
     if args.mode != "step":
         if args.mode == "vessel" and args.n == 256:
             args.n = 448
-        if args.mode == "batch":
+        if args.mode in ("batch", "warmstart"):
             args.tau = 0.8 if args.tau == 0.7 else args.tau
             args.storage = "f32" if args.storage == "f64" else args.storage
-        res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch}[args.mode](args, torch, lbm)
+        res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch,
+               "warmstart": mode_warmstart}[args.mode](args, torch, lbm)
         res["n_gpus"] = 1
         print(json.dumps(res), flush=True)
         return

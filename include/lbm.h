@@ -212,6 +212,53 @@ int lbm_pdfs_import(lbm_solver *s, const double *dev_dense);
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_solver *s);
 
+/* ---- invariants of the discrete dynamics (starting states) ----------
+ * The step (Eqs. 2, 3, 5, 7 with Guo forcing; propagation only between
+ * non-solid nodes, Sec. 3.2) conserves the mass of every set of non-solid
+ * nodes joined by lattice links.  Collision keeps each node's momentum j
+ * (the force adds rho*g), and a population with c_ik != 0 either moves one
+ * node along axis k or bounces back with c_ik negated.  Both flip the sign
+ * of (-1)^{x_k} c_ik f_i, so for every set A that no link with c_k != 0
+ * leaves, S_k(A) = sum_A (-1)^{x_k} j_k obeys
+ * S_k(t+1) = -S_k(t) + g_k sum_A (-1)^{x_k} rho: a staggered momentum that
+ * is never damped.  A start from rest has S_k = 0 and rho0 per node; any
+ * other starting state reaches a long-time state that differs unless its
+ * invariants are set to those values first (lbm_project_invariants). */
+
+/* Connected components of the non-solid nodes of one lattice under the
+ * links of the D2Q9 (q = 9, shape[2] = 1) or D3Q19 (q = 19) set that join
+ * two non-solid nodes; axis = -1 keeps every link, axis = k in {0, 1, 2}
+ * (x, y, z; k < 2 for q = 9) only links with c_k != 0.  solid: host uint8
+ * [nz][ny][nx], nonzero = solid; shape = {nx, ny, nz}; periodic bits as in
+ * lbm_tiles_build (a non-periodic edge is a wall).  labels: host int32
+ * [nz][ny][nx], -1 on solid nodes, else the component number, numbered
+ * from 0 in order of first appearance, x fastest.  *count = number of
+ * components.  Host only, synchronous; LBM_ERR_ARG / LBM_ERR_UNSUPPORTED
+ * for bad arguments, LBM_ERR_NOMEM if host memory runs out. */
+int lbm_components(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic, int32_t axis,
+                   int32_t *labels, int32_t *count);
+
+/* Give a starting state (rho, u) for lbm_init the invariants of a start
+ * from rest.  With D = 2 (q = 9) or 3 (q = 19):
+ *   labels  device int32 [1 + D][nz][ny][nx]: lbm_components of the same
+ *           geometry for axis -1, then axis 0 .. D-1;
+ *   counts  host int32 [1 + D], the matching component counts;
+ *   rho, u  device dense FP64, rho [nz][ny][nx] and u [3][nz][ny][nx],
+ *           updated in place on non-solid nodes (solid entries untouched);
+ *   scratch device FP64, 2 * (counts[0] + ... + counts[D]) entries,
+ *           overwritten; must not overlap rho or u.
+ * First rho is scaled per lattice-connected component so that it holds
+ * rho0 per node; then, for each axis k < D and each component of the
+ * c_k != 0 links, u_k -= (-1)^{x_k} S_k / M with S_k = sum (-1)^{x_k} rho u_k
+ * and M = sum rho over the component, which makes S_k zero.  Parity uses the
+ * lattice coordinate; on a periodic axis of odd length S_k of a component
+ * that crosses the wrap is not conserved and the step only alters the guess.
+ * A component whose mass is zero or not finite yields non-finite values.
+ * Asynchronous on the given stream; LBM_ERR_ARG for bad arguments,
+ * LBM_ERR_HIP if a launch fails. */
+int lbm_project_invariants(int32_t q, const int32_t shape[3], const int32_t *labels, const int32_t *counts,
+                           double rho0, double *rho, double *u, double *scratch, void *stream);
+
 const char *lbm_strerror(int code);
 const char *lbm_last_error(void);
 

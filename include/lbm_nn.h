@@ -103,6 +103,15 @@ int lbm_nn_mse(int64_t n, int32_t channels, const float *pred, const float *targ
 int lbm_nn_adam(int64_t n, float *p, float *m, float *v, const float *g, void *p16, float lr, float beta1,
                 float beta2, float eps, int32_t step, void *stream);
 
+/* Slow (Stokes) flow is linear in the body force, so the network predicts one
+ * (rho - rho0, u) field per force axis and the force direction mixes them:
+ * p[n][k] = sum_j dir[j] * y[n][4j + k] for k < 4 (y FP32 [nodes][12], p FP32
+ * [nodes][4]).  Backward: dy[n][4j + k] = dir[j] * dp[n][k] (dp BF16 rows of
+ * stride ldp; dy BF16 rows of stride ldy >= 12, entries 12.. zeroed). */
+int lbm_nn_mix(int64_t n, const float *y, const float dir[3], float *p, void *stream);
+int lbm_nn_mix_backward(int64_t n, const void *dp, int32_t ldp, const float dir[3], void *dy, int32_t ldy,
+                        void *stream);
+
 /* Network input: x (BF16 [nodes][8]) = (solid, gx, gy, gz on fluid nodes, 0...)
  * from a uint8 solid mask and a unit force direction. */
 int lbm_nn_encode_input(int64_t n, const uint8_t *solid, const float dir[3], void *x, void *stream);

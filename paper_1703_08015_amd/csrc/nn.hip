@@ -312,6 +312,20 @@ __global__ void k_adam(int64_t n, float *p, float *m, float *v, const float *g, 
   }
 }
 
+__global__ void k_mix(int64_t n, const float *y, float d0, float d1, float d2, float *p) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    for (int k = 0; k < 4; ++k) p[4 * e + k] = d0 * y[12 * e + k] + d1 * y[12 * e + 4 + k] + d2 * y[12 * e + 8 + k];
+}
+
+__global__ void k_mix_backward(int64_t n, const bf16 *dp, int ldp, float d0, float d1, float d2, bf16 *dy, int ldy) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float d[3] = {d0, d1, d2};
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 4; ++k) dy[e * ldy + 4 * j + k] = (bf16)(d[j] * (float)dp[e * ldp + k]);
+    for (int c = 12; c < ldy; ++c) dy[e * ldy + c] = (bf16)0.f;
+  }
+}
+
 __global__ void k_encode(int64_t n, const uint8_t *solid, float dx, float dy, float dz, bf16 *x) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const bool s = solid[e] != 0;
@@ -566,6 +580,23 @@ extern "C" int lbm_nn_adam(int64_t n, float *p, float *m, float *v, const float 
   const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
   hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, p, m, v, g,
                      static_cast<bf16 *>(p16), lr, beta1, beta2, eps, c1, c2);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_mix(int64_t n, const float *y, const float dir[3], float *p, void *stream) {
+  if (!y || !dir || !p || n < 0) return set_error(LBM_ERR_ARG, "lbm_nn_mix: args");
+  hipLaunchKernelGGL(k_mix, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, y, dir[0], dir[1],
+                     dir[2], p);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_mix_backward(int64_t n, const void *dp, int32_t ldp, const float dir[3], void *dy, int32_t ldy,
+                                   void *stream) {
+  if (!dp || !dir || !dy || n < 0 || ldp < 4 || ldy < 12) return set_error(LBM_ERR_ARG, "lbm_nn_mix_backward: args");
+  hipLaunchKernelGGL(k_mix_backward, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
+                     static_cast<const bf16 *>(dp), ldp, dir[0], dir[1], dir[2], static_cast<bf16 *>(dy), ldy);
   NN_TRY(hipGetLastError());
   return LBM_OK;
 }

@@ -98,6 +98,8 @@ def lib():
             "lbm_pdfs_export": (ctypes.c_int, [P, P]),
             "lbm_pdfs_import": (ctypes.c_int, [P, P]),
             "lbm_step_count": (I64, [P]),
+            "lbm_components": (ctypes.c_int, [I32, P, P, U32, I32, P, P]),
+            "lbm_project_invariants": (ctypes.c_int, [I32, P, P, P, ctypes.c_double, P, P, P, P]),
             "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "lbm_last_error": (ctypes.c_char_p, []),
         }
@@ -132,6 +134,57 @@ def _periodic_bits(periodic):
     if isinstance(periodic, (int, np.integer)):
         return int(periodic)
     return int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
+
+
+def components(solid, lattice=19, axis=-1, periodic=(1, 1, 1)):
+    """Host labels (int32, -1 on solid) and count of the fluid components of
+    a (nz, ny, nx) mask under the lattice links (axis >= 0: links with
+    c_axis != 0 only); lbm_components."""
+    m = np.ascontiguousarray(np.asarray(solid).astype(np.uint8))
+    if m.ndim == 2:
+        m = m[None]
+    shape = np.array([m.shape[2], m.shape[1], m.shape[0]], np.int32)
+    labels = np.empty(m.shape, np.int32)
+    count = ctypes.c_int32()
+    _check(lib().lbm_components(int(lattice), _np_ptr(m), _np_ptr(shape), _periodic_bits(periodic), int(axis),
+                                _np_ptr(labels), ctypes.byref(count)), "lbm_components")
+    return labels, int(count.value)
+
+
+class Invariants:
+    """Component labels of one geometry on the GPU, for
+    lbm_project_invariants: mass components, then one labelling per axis."""
+
+    def __init__(self, solid, lattice=19, periodic=(1, 1, 1), device="cuda"):
+        import torch
+        m = np.asarray(solid)
+        if m.ndim == 2:
+            m = m[None]
+        self.lattice = int(lattice)
+        self.shape = tuple(m.shape)
+        dims = 2 if self.lattice == 9 else 3
+        labs, counts = [], []
+        for axis in range(-1, dims):
+            lab, n = components(m, self.lattice, axis, periodic)
+            labs.append(lab)
+            counts.append(n)
+        self.counts = np.array(counts, np.int32)
+        self.labels = torch.from_numpy(np.stack(labs)).to(device)
+        self.scratch = torch.empty(max(1, 2 * int(self.counts.sum())), dtype=torch.float64, device=device)
+
+    def project(self, rho, u, rho0=1.0, stream=None):
+        """In place on device FP64 rho (nz, ny, nx) and u (3, nz, ny, nx)."""
+        import torch
+        n = int(np.prod(self.shape))
+        if rho.dtype != torch.float64 or u.dtype != torch.float64 or not rho.is_contiguous() or \
+                not u.is_contiguous() or rho.numel() != n or u.numel() != 3 * n:
+            raise ValueError("rho and u must be contiguous FP64 of %d and %d elements" % (n, 3 * n))
+        shape = np.array([self.shape[2], self.shape[1], self.shape[0]], np.int32)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().lbm_project_invariants(self.lattice, _np_ptr(shape), ctypes.c_void_p(self.labels.data_ptr()),
+                                            _np_ptr(self.counts), float(rho0), ctypes.c_void_p(rho.data_ptr()),
+                                            ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self.scratch.data_ptr()),
+                                            ctypes.c_void_p(s.cuda_stream)), "lbm_project_invariants")
 
 
 class Tiles:

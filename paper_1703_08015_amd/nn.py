@@ -41,6 +41,8 @@ def _lib():
             "lbm_nn_mse": [I64, I32, P, P, P, F, P, I32, P, P],
             "lbm_nn_adam": [I64, P, P, P, P, P, F, F, F, F, I32, P],
             "lbm_nn_encode_input": [I64, P, P, P, P],
+            "lbm_nn_mix": [I64, P, P, P, P],
+            "lbm_nn_mix_backward": [I64, P, I32, P, P, I32, P],
             "lbm_nn_decode_output": [I64, P, P, D, D, I32, P, P, P, P],
         }
         for name, args in sig.items():
@@ -131,6 +133,17 @@ def mse(n, channels, pred, target, mask, scale, dpred, ldd, loss, stream=None):
 def adam(p, m, v, g, p16, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(_lib().lbm_nn_adam(p.numel(), _ptr(p), _ptr(m), _ptr(v), _ptr(g), _ptr(p16), float(lr), float(beta1),
                               float(beta2), float(eps), int(step), _stream(stream)), "lbm_nn_adam")
+
+
+def mix(y, direction, p, stream=None):
+    d = (ctypes.c_float * 3)(*[float(v) for v in direction])
+    _check(_lib().lbm_nn_mix(p.numel() // 4, _ptr(y), d, _ptr(p), _stream(stream)), "lbm_nn_mix")
+
+
+def mix_backward(dp, ldp, direction, dy, ldy, stream=None):
+    d = (ctypes.c_float * 3)(*[float(v) for v in direction])
+    _check(_lib().lbm_nn_mix_backward(dy.numel() // ldy, _ptr(dp), ldp, d, _ptr(dy), ldy, _stream(stream)),
+           "lbm_nn_mix_backward")
 
 
 def encode_input(solid, direction, x, stream=None):

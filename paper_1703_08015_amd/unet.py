@@ -43,7 +43,7 @@ class UNet:
         self.L = levels
         self.C = [base * 2 ** l for l in range(levels)]
         self.in_ch, self.out_ch = in_ch, out_ch
-        self.out_pad = 8  # head gradient rows are 8 BF16 wide (channels 4..7 stay zero)
+        self.out_pad = (out_ch + 7) // 8 * 8  # head gradient rows: BF16, a multiple of 8 wide
         self.device = torch.device(device)
         self.out_scale = out_scale
         gen = torch.Generator().manual_seed(seed)
@@ -71,6 +71,25 @@ class UNet:
         self.params += list(self.head)
         self.step_count = 0
         self._cache = None
+
+    # ---- force-linear head -----------------------------------------------------
+    def forward_mixed(self, x, direction):
+        """With out_ch = 12: per-axis fields mixed by the force direction into
+        FP32 (nz, ny, nx, 4)."""
+        y = self.forward(x)
+        t = self.torch
+        shape = tuple(x.shape[:3])
+        if getattr(self, "_mixbuf", None) is None or self._mixbuf.shape[:3] != shape:
+            self._mixbuf = t.empty(shape + (4,), dtype=t.float32, device=self.device)
+        nn.mix(y, direction, self._mixbuf)
+        return self._mixbuf
+
+    def backward_mixed(self, dp, ldp, direction):
+        t = self.torch
+        shape = tuple(dp.shape[:3])
+        dy = t.empty(shape + (self.out_pad,), dtype=t.bfloat16, device=self.device)
+        nn.mix_backward(dp, ldp, direction, dy, self.out_pad)
+        self.backward(dy)
 
     def n_params(self):
         return int(sum(p.p.numel() for p in self.params) - (self.out_pad - self.out_ch) * (self.C[0] + 1))
@@ -166,8 +185,8 @@ class UNet:
         return buf
 
     def backward(self, dout):
-        """dout: BF16 (nz, ny, nx, 8) gradient of the loss wrt the head output
-        (channels 4..7 zero).  Accumulates parameter gradients."""
+        """dout: BF16 (nz, ny, nx, out_pad) gradient of the loss wrt the head
+        output (channels out_ch.. zero).  Accumulates parameter gradients."""
         t = self.torch
         _, A, grids = self._cache
         L, C = self.L, self.C

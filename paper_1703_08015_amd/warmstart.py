@@ -1,0 +1,195 @@
+"""Learned warm start: steady states from the batched solver train the U-Net,
+whose (rho, u) prediction initialises the solver through f_eq (lbm_init).
+
+The prediction is first given the invariants of a start from rest
+(lbm_project_invariants): mass rho0 per node on every lattice-connected
+component and zero staggered momentum per axis component.  The discrete
+dynamics never change those, so without the projection a warm start settles
+into a different long-time state than the cold start.
+
+The solver still produces the answer: a warm run steps to the same residual
+tolerance as a cold start from rest, and falls back to a cold start if its
+residual turns non-finite or grows.
+"""
+import time
+
+import numpy as np
+
+from . import lbm, nn
+from .unet import UNet
+
+
+def nu_of(tau):
+    return (tau - 0.5) / 3.0
+
+
+class Sample:
+    """One geometry on the GPU: mask, force, and (after the solver) its
+    steady fields, channels last."""
+
+    def __init__(self, torch, mask, g, rho=None, u=None):
+        self.shape = tuple(mask.shape)
+        self.g = np.asarray(g, np.float64)
+        self.gmag = float(np.linalg.norm(self.g))
+        self.dir = self.g / self.gmag
+        self.solid = torch.from_numpy(np.ascontiguousarray(mask.astype(np.uint8))).cuda()
+        self.rho, self.u = rho, u  # torch FP64 (nz,ny,nx) and (3,nz,ny,nx)
+        self.target = None
+        self._mask = np.asarray(mask, bool)
+        self._inv = None
+
+    @property
+    def invariants(self):
+        """Component labels of the geometry on the GPU (built on first use)."""
+        if self._inv is None:
+            self._inv = lbm.Invariants(self._mask, 19)
+        return self._inv
+
+
+def steady_dataset(torch, masks, gs, tau=0.8, storage="f32", tol=1e-6, check_every=100, max_steps=200000,
+                   progress=None):
+    """Run all geometries as one batch to steady state; return Samples with
+    rho, u and the number of steps each needed."""
+    tiles = lbm.Tiles.concat([lbm.Tiles(m) for m in masks])
+    s = lbm.Solver(tiles, lattice=19, storage=storage, tau=tau, persistent=1, graph_steps=check_every)
+    s.set_sample_force(np.asarray(gs, np.float64))
+    s.init()
+    steps, res = s.run_to_steady(tol=tol, check_every=check_every, max_steps=max_steps, progress=progress)
+    rho, u = s.moments()
+    out = []
+    o = 0
+    for m, g in zip(masks, gs):
+        n = m.size
+        r = rho[o:o + n].view(m.shape)
+        uu = u[3 * o:3 * (o + n)].view((3,) + m.shape)
+        out.append(Sample(torch, m, g, r.clone(), uu.clone()))
+        o += n
+    del s
+    return out, steps, res
+
+
+def make_targets(torch, samples, tau, rho0=1.0, out_scale=None):
+    """Scaled targets (rho - rho0, u) * nu / |g| / out_scale as FP32
+    (nz, ny, nx, 4); out_scale defaults to the RMS of the scaled velocity."""
+    nu = nu_of(tau)
+    if out_scale is None:
+        acc, cnt = 0.0, 0
+        for sm in samples:
+            fl = sm.solid == 0
+            uu = sm.u[:, fl] * (nu / sm.gmag)
+            acc += float((uu ** 2).sum())
+            cnt += int(uu.numel())
+        out_scale = float(np.sqrt(acc / max(cnt, 1)))
+    for sm in samples:
+        k = nu / sm.gmag / out_scale
+        t = torch.empty(sm.shape + (4,), dtype=torch.float32, device="cuda")
+        t[..., 0] = ((sm.rho - rho0) * k).float()
+        t[..., 1:] = (sm.u * k).permute(1, 2, 3, 0).float()
+        t[sm.solid != 0] = 0.0
+        sm.target = t
+    return out_scale
+
+
+def encode(torch, sample):
+    """Geometry-only input (solid flag); the force direction enters through
+    the force-linear output head."""
+    x = torch.empty(sample.shape + (8,), dtype=torch.bfloat16, device="cuda")
+    nn.encode_input(sample.solid, (0.0, 0.0, 0.0), x)
+    return x
+
+
+def make_net(levels=4, base=24, seed=0, out_scale=1.0):
+    return UNet(levels=levels, base=base, out_ch=12, seed=seed, out_scale=out_scale)
+
+
+def train(torch, net, samples, epochs=10, lr=1e-3, seed=0, progress=None):
+    """Per-sample Adam steps on the masked MSE; returns the mean loss per epoch."""
+    rng = np.random.default_rng(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    history = []
+    for ep in range(epochs):
+        total, nodes = 0.0, 0
+        for idx in rng.permutation(len(samples)):
+            sm = samples[idx]
+            x = encode(torch, sm)
+            pred = net.forward_mixed(x, sm.dir)
+            nf = int((sm.solid == 0).sum())
+            dout = torch.empty(sm.shape + (8,), dtype=torch.bfloat16, device="cuda")
+            loss.zero_()
+            nn.mse(pred[..., 0].numel(), 4, pred, sm.target, sm.solid, 1.0 / max(nf, 1), dout, 8, loss)
+            net.zero_grad()
+            net.backward_mixed(dout, 8, sm.dir)
+            net.adam_step(lr)
+            total += float(loss.item())
+            nodes += nf
+        history.append(total / max(nodes, 1))
+        if progress:
+            progress(ep, history[-1])
+    return history
+
+
+def predict_fields(torch, net, sample, tau, rho0=1.0, project=True):
+    """Network (rho, u) for a geometry as dense FP64 fields, projected onto
+    the invariants of a start from rest (project=False: the raw decode)."""
+    x = encode(torch, sample)
+    pred = net.forward_mixed(x, sample.dir)
+    rho = torch.empty(sample.shape, dtype=torch.float64, device="cuda")
+    u = torch.empty((3,) + sample.shape, dtype=torch.float64, device="cuda")
+    nn.decode_output(pred, sample.solid, rho0, net.out_scale * sample.gmag / nu_of(tau), rho, u, renorm=False)
+    if project:
+        sample.invariants.project(rho, u, rho0)
+    return rho, u
+
+
+def solve(torch, sample, tau, init=None, storage="f32", tol=1e-6, check_every=100, max_steps=200000):
+    """Run one geometry to steady state from rest (init None) or from given
+    (rho, u); returns (steps, seconds, final u, fell_back)."""
+    tiles = lbm.Tiles(sample.solid.cpu().numpy().astype(bool))
+    s = lbm.Solver(tiles, lattice=19, storage=storage, tau=tau, g=tuple(sample.g), graph_steps=check_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fell_back = False
+    if init is None:
+        s.init()
+    else:
+        s.init(*init)
+        # guard: a prediction whose first residuals are non-finite or growing falls back to rest
+        s.step(check_every)
+        try:
+            r1 = s.residual()[0]
+            s.step(check_every)
+            r2 = s.residual()[0]
+            bad = not (np.isfinite(r1) and np.isfinite(r2)) or r2 > 2.0 * r1
+        except lbm.LbmError:
+            bad = True
+        if bad:
+            fell_back = True
+            s.init()
+    steps, res = s.run_to_steady(tol=tol, check_every=check_every, max_steps=max_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, u = s.moments()
+    taken = int(s.step_count)
+    del s
+    return taken if steps[0] > 0 else -1, wall, u, fell_back
+
+
+def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100, project=True):
+    """Warm vs cold time to steady state for each geometry (project=False
+    starts from the raw prediction, for comparison)."""
+    rows = []
+    for sm in samples:
+        cold_steps, cold_s, u_cold, _ = solve(torch, sm, tau, None, storage, tol, check_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        init = predict_fields(torch, net, sm, tau, project=project)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        fl = sm.solid == 0
+        pred_err = float(((init[1][:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
+        warm_steps, warm_s, u_warm, fb = solve(torch, sm, tau, init, storage, tol, check_every)
+        agree = float(((u_warm[:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
+        rows.append(dict(cold_steps=cold_steps, cold_s=cold_s, warm_steps=warm_steps, warm_s=warm_s + t_inf,
+                         inference_s=t_inf, prediction_u_rel_l2=pred_err, warm_vs_cold_u_rel_l2=agree,
+                         fell_back=fb))
+    return rows

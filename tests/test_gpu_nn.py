@@ -189,6 +189,23 @@ def test_maxpool_relu_mse_adam(torch):
     assert np.array_equal(host(p16), bf(host(P)))
 
 
+def test_force_mix(torch):
+    y = rng.normal(size=(30, 12)).astype(np.float32)
+    d = np.array([0.36, -0.48, 0.8])
+    p = torch.empty((30, 4), dtype=torch.float32, device="cuda")
+    nn.mix(dev(torch, y, torch.float32), d, p)
+    want = sum(d[j] * y[:, 4 * j:4 * j + 4].astype(np.float64) for j in range(3))
+    close(host(p), want, 1e-6)
+    dp = np.zeros((30, 8))
+    dp[:, :4] = bf(rng.normal(size=(30, 4)))
+    dy = torch.empty((30, 16), dtype=torch.bfloat16, device="cuda")
+    nn.mix_backward(dev(torch, dp), 8, d, dy, 16)
+    hdy = host(dy)
+    for j in range(3):
+        close(hdy[:, 4 * j:4 * j + 4], d[j] * dp[:, :4], 1e-2)
+    assert not hdy[:, 12:].any()
+
+
 def test_encode_decode(torch):
     solid = (rng.random(GRID) < 0.4).astype(np.uint8)
     x = torch.empty(GRID + (8,), dtype=torch.bfloat16, device="cuda")

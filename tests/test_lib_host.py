@@ -121,3 +121,41 @@ def test_autotune_candidates_and_key():
     m2[0, 0, 0] = True
     assert k1 != autotune.geometry_key([m2], (1, 1, 1), 19, "f64", 0.7)
     assert k1 != autotune.geometry_key([m], (1, 1, 1), 19, "f32", 0.7)
+
+
+def test_library_exports_every_nn_symbol():
+    from paper_1703_08015_amd import nn
+    names = nn.header_functions()
+    assert len(names) >= 10
+    L = lbm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_components_bitexact_vs_oracle():
+    from oracle import invariants
+    rng = np.random.default_rng(11)
+    cases = []
+    for _ in range(6):
+        shape = tuple(int(v) for v in rng.integers(2, 10, size=3))
+        cases.append((19, rng.random(shape) < rng.uniform(0.3, 0.7), int(rng.integers(0, 8))))
+        cases.append((9, rng.random((1,) + shape[1:]) < rng.uniform(0.3, 0.7), int(rng.integers(0, 4))))
+    m, _ = inputs.spheres_3d(32, 0.5, 2.0, 4.0, seed=2)
+    cases.append((19, m, 7))
+    for q, mask, periodic in cases:
+        for axis in range(-1, 2 if q == 9 else 3):
+            lab, n = lbm.components(mask, q, axis, periodic)
+            ref, nref = invariants.components(mask, q, axis, periodic)
+            assert n == nref and np.array_equal(lab, ref.astype(np.int32)), (q, mask.shape, periodic, axis)
+
+
+def test_components_errors():
+    m = np.zeros((4, 4, 4), bool)
+    for kw, code in [(dict(lattice=27), lbm.LBM_ERR_UNSUPPORTED), (dict(axis=3), lbm.LBM_ERR_ARG),
+                     (dict(axis=-2), lbm.LBM_ERR_ARG), (dict(lattice=9), lbm.LBM_ERR_ARG),
+                     (dict(periodic=8), lbm.LBM_ERR_ARG)]:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.components(m, **kw)
+        assert e.value.code == code, kw
+    lab, n = lbm.components(np.ones((3, 3, 3), bool))
+    assert n == 0 and np.all(lab == -1)

@@ -1,0 +1,192 @@
+"""Pins of the invariants oracle: component labels against a brute-force
+breadth-first search, the conservation laws against the dense FP64 step
+(mass per component; the staggered momentum identity per axis component,
+for random states with a body force), the projection's defining
+properties, and the end-to-end consequence: a start from the cold steady
+velocity reaches the cold long-time state only after projection."""
+from collections import deque
+
+import numpy as np
+import pytest
+
+from oracle import dense, invariants
+from paper_1703_08015_amd import inputs
+
+rng = np.random.default_rng(7)
+
+
+def _bfs_partition(mask, q, axis, periodic):
+    """Components by breadth-first search over lattice links (pure Python)."""
+    c, _, _ = dense.lattice(q)
+    nz, ny, nx = mask.shape
+    ext = (nx, ny, nz)
+    label = -np.ones(mask.shape, np.int64)
+    nxt = 0
+    for start in zip(*np.nonzero(~mask)):
+        if label[start] >= 0:
+            continue
+        label[start] = nxt
+        todo = deque([start])
+        while todo:
+            z, y, x = todo.popleft()
+            for ci in c:
+                if not ci.any() or (axis >= 0 and ci[axis] == 0):
+                    continue
+                t = [x + ci[0], y + ci[1], z + ci[2]]
+                ok = True
+                for a in range(3):
+                    if not 0 <= t[a] < ext[a]:
+                        if periodic >> a & 1:
+                            t[a] %= ext[a]
+                        else:
+                            ok = False
+                if not ok:
+                    continue
+                nb = (t[2], t[1], t[0])
+                if not mask[nb] and label[nb] < 0:
+                    label[nb] = nxt
+                    todo.append(nb)
+        nxt += 1
+    return label, nxt
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_components_match_breadth_first_search(q):
+    for trial in range(8):
+        shape = (1, int(rng.integers(3, 8)), int(rng.integers(3, 8))) if q == 9 else \
+            tuple(int(v) for v in rng.integers(2, 7, size=3))
+        mask = rng.random(shape) < rng.uniform(0.3, 0.7)
+        periodic = int(rng.integers(0, 4 if q == 9 else 8))
+        for axis in range(-1, 2 if q == 9 else 3):
+            lab, n = invariants.components(mask, q, axis, periodic)
+            ref, nref = _bfs_partition(mask, q, axis, periodic)
+            # BFS numbers components by the first node in scan order too
+            assert n == nref and np.array_equal(lab, ref), (trial, axis)
+
+
+def _porous(n, seed):
+    """Sphere packing plus a sealed 2x2x2 cavity: several components."""
+    m, _ = inputs.spheres_3d(n, 0.45, 1.5, 3.0, seed=seed)
+    m[2:6, 2:6, 2:6] = True
+    m[3:5, 3:5, 3:5] = False
+    return m
+
+
+def _porous_2d(ny, nx, seed):
+    return np.random.default_rng(seed).random((1, ny, nx)) < 0.55
+
+
+def _random_state(q, mask):
+    f = dense.init(q, mask) * (1.0 + 0.2 * rng.random((q,) + mask.shape))
+    return f * (~mask)
+
+
+def _stag(q, mask, f, labels, count, axis):
+    c, _, _ = dense.lattice(q)
+    j = np.tensordot(c[:, axis].astype(np.float64), f, axes=(0, 0))
+    rho = f.sum(axis=0)
+    u = np.where(mask, 0.0, j / np.where(mask, 1.0, rho))
+    uu = np.zeros((3,) + mask.shape)
+    uu[axis] = u
+    return invariants.staggered_momentum(mask, rho, uu, labels, count, axis)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_step_conserves_component_mass_and_staggered_momentum(q):
+    mask = _porous(12, 3) if q == 19 else _porous_2d(12, 14, 3)
+    g = np.array([2e-4, -3e-4, 1e-4 if q == 19 else 0.0])
+    f = _random_state(q, mask)
+    lab, n = invariants.components(mask, q)
+    assert n >= 2  # several components, so per-component mass means something
+    axes = [invariants.components(mask, q, k) for k in range(2 if q == 9 else 3)]
+    for _ in range(3):
+        f1 = dense.step(q, mask, f, 0.8, g, 1)
+        rho0, rho1 = f.sum(0), f1.sum(0)
+        m0 = np.bincount(lab[lab >= 0], weights=rho0[lab >= 0], minlength=n)
+        m1 = np.bincount(lab[lab >= 0], weights=rho1[lab >= 0], minlength=n)
+        tol = 1e-14 * rho0.sum()  # rounding of sums over the whole lattice
+        assert np.allclose(m1, m0, rtol=0, atol=tol)
+        for k, (labk, nk) in enumerate(axes):
+            s0, _ = _stag(q, mask, f, labk, nk, k)
+            s1, _ = _stag(q, mask, f1, labk, nk, k)
+            nz, ny, nx = mask.shape
+            coord = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")[2 - k]
+            sign = np.where(coord % 2 == 0, 1.0, -1.0)
+            on = labk >= 0
+            drive = g[k] * np.bincount(labk[on], weights=(sign * rho1)[on], minlength=nk)
+            assert np.allclose(s1, -s0 + drive, rtol=0, atol=tol), (k, np.abs(s1 + s0 - drive).max())
+        f = f1
+
+
+def test_staggered_sum_of_a_split_set_is_not_conserved():
+    """The identity needs whole components: half of one breaks it, so the
+    previous test would catch a labelling that splits components."""
+    mask = _porous(12, 3)
+    g = np.zeros(3)
+    f = _random_state(19, mask)
+    lab, n = invariants.components(mask, 19, 0)
+    big = np.argmax(np.bincount(lab[lab >= 0]))
+    nz, ny, nx = mask.shape
+    half = (lab == big) & (np.arange(nz)[:, None, None] < nz // 2)
+    part = np.where(half, 0, -1)
+    s0, _ = _stag(19, mask, f, part, 1, 0)
+    s1, _ = _stag(19, mask, dense.step(19, mask, f, 0.8, g, 1), part, 1, 0)
+    assert abs(s1[0] + s0[0]) > 1e-6
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_projection_sets_the_invariants_of_rest(q):
+    mask = _porous(10, 5) if q == 19 else _porous_2d(10, 12, 5)
+    rho = np.where(mask, 0.0, 1.0 + 0.01 * rng.normal(size=mask.shape))
+    u = np.where(mask[None], 0.0, 0.01 * rng.normal(size=(3,) + mask.shape))
+    if q == 9:
+        u[2] = 0.0
+    rp, up = invariants.project(mask, rho, u, q, rho0=1.1)
+    lab, n = invariants.components(mask, q)
+    on = lab >= 0
+    assert np.allclose(np.bincount(lab[on], weights=rp[on], minlength=n),
+                       1.1 * np.bincount(lab[on], minlength=n), rtol=1e-13)
+    for k in range(2 if q == 9 else 3):
+        labk, nk = invariants.components(mask, q, k)
+        s, _ = invariants.staggered_momentum(mask, rp, up, labk, nk, k)
+        assert np.abs(s).max() < 1e-15
+    assert np.all(rp[mask] == 0) and np.all(up[:, mask] == 0)
+    if q == 9:
+        assert np.all(up[2] == 0)
+    r2, u2 = invariants.project(mask, rp, up, q, rho0=1.1)
+    assert np.allclose(r2, rp, rtol=1e-14, atol=0) and np.allclose(u2, up, rtol=0, atol=1e-16)
+    # the cold start (rho0 = 1 at rest) is an exact fixed point
+    r0, u0 = invariants.project(mask, np.where(mask, 0.0, 1.0), np.zeros((3,) + mask.shape), q, rho0=1.0)
+    assert np.array_equal(r0, np.where(mask, 0.0, 1.0)) and not u0.any()
+
+
+def _run_to(mask, g, f, tol=1e-10):
+    prev = None
+    for it in range(400):
+        f = dense.step(19, mask, f, 0.8, g, 100, nthreads=4)
+        _, u = dense.moments(19, mask, f, g)
+        if prev is not None and np.linalg.norm(u - prev) < tol * np.linalg.norm(u):
+            return u
+        prev = u
+    raise AssertionError("no steady state")
+
+
+def test_projected_start_reaches_the_cold_long_time_state():
+    """A sphere packing with a node whose y links are all solid (its y
+    momentum is a one-node invariant): starting from the cold steady velocity
+    itself ends 8e-4 away from the cold state, starting from its projection
+    ends within 1e-7 of it."""
+    r = np.random.default_rng(0)
+    mask, _ = inputs.spheres_3d(16, float(r.uniform(0.4, 0.7)), 2.0, 4.0, seed=100)
+    d = r.normal(size=3)
+    g = 1e-6 * d / np.linalg.norm(d)
+    labk, nk = invariants.components(mask, 19, 1)
+    assert (np.bincount(labk[labk >= 0]) == 1).any()
+    u_cold = _run_to(mask, g, dense.init(19, mask))
+    rho1 = np.where(mask, 0.0, 1.0)
+    u_raw = _run_to(mask, g, dense.init(19, mask, rho=rho1, u=u_cold))
+    rp, up = invariants.project(mask, rho1, u_cold, 19)
+    u_proj = _run_to(mask, g, dense.init(19, mask, rho=rp, u=up))
+    rel = lambda a: np.linalg.norm(a - u_cold) / np.linalg.norm(u_cold)
+    assert rel(u_raw) > 1e-4
+    assert rel(u_proj) < 1e-7
