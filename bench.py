@@ -67,8 +67,21 @@ def traffic_for(kernel_name, workload_key):
     return rec.get("bytes_per_launch")
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mask, args):
-    """The FP64 oracle on the same geometry, all host cores, a few steps."""
+    """The FP64 oracle on the same geometry: all host cores for a bounded
+    number of steps (about 10-20 s of CPU work at the default 64), and one
+    thread for a few steps."""
     from oracle import dense
     dense.build()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -77,10 +90,15 @@ def cpu_baseline(mask, args):
     t0 = time.perf_counter()
     dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores)
     dt = time.perf_counter() - t0
+    one = max(1, args.cpu_steps // 16)
+    t1 = time.perf_counter()
+    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1)
+    dt1 = time.perf_counter() - t1
     nf = int((~mask).sum())
     return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": "%d steps of the full %d^3 geometry (%d non-solid nodes), FP64 dense C oracle, OpenMP, "
-                      "%.1f s" % (args.cpu_steps, args.n, nf, dt)}
+                      "%.1f s" % (args.cpu_steps, args.n, nf, dt),
+            "single_thread_mlups": nf * one / dt1 / 1e6, "single_thread_steps": one, "cpu_model": _cpu_model()}
 
 
 def copy_reference(torch, gib, reps=20):
@@ -302,7 +320,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "scalar"])
     ap.add_argument("--store", default="auto", choices=["auto", "regular", "nontemporal"])
     ap.add_argument("--f16-scale-log2", type=int, default=22)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart"])
     ap.add_argument("--epochs", type=int, default=10)
@@ -371,7 +389,8 @@ def main():
     mlups = nf * args.steps / wall / 1e6
     alg_bytes = nf * 2 * q * sd  # Eq. (10) per non-solid node, per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    kernel = "k_step<D3Q19,4x4x4,%s>" % args.storage
+    # D3Q19 on 4x4x4 tiles runs the scalar-mask kernel unless the generic one is asked for
+    kernel = "%s<D3Q19,4x4x4,%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage)
     wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
                                         "scalar" if args.kernel == "auto" else args.kernel, args.order,
                                         "nt" if args.store in ("auto", "nontemporal") else "regular",
@@ -401,6 +420,8 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            # measured overhead over the algorithmic bytes (the paper's Delta^B, Table 5)
+            "delta_b": round(traffic / alg_bytes - 1.0, 4) if traffic else None,
             "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": round(launch_ms, 5),
         },
         "bu_eq43": round(mlups * 1e6 * 2 * q * sd / (HBM_PEAK_GBS * 1e9), 4),

@@ -215,15 +215,16 @@ int64_t lbm_step_count(const lbm_solver *s);
 /* ---- invariants of the discrete dynamics (starting states) ----------
  * The step (Eqs. 2, 3, 5, 7 with Guo forcing; propagation only between
  * non-solid nodes, Sec. 3.2) conserves the mass of every set of non-solid
- * nodes joined by lattice links.  Collision keeps each node's momentum j
- * (the force adds rho*g), and a population with c_ik != 0 either moves one
- * node along axis k or bounces back with c_ik negated.  Both flip the sign
- * of (-1)^{x_k} c_ik f_i, so for every set A that no link with c_k != 0
- * leaves, S_k(A) = sum_A (-1)^{x_k} j_k obeys
- * S_k(t+1) = -S_k(t) + g_k sum_A (-1)^{x_k} rho: a staggered momentum that
- * is never damped.  A start from rest has S_k = 0 and rho0 per node; any
- * other starting state reaches a long-time state that differs unless its
- * invariants are set to those values first (lbm_project_invariants). */
+ * nodes joined by lattice links, and a family of staggered momenta: for
+ * every field beta with c.beta(x + c) = -c.beta(x) on each link between
+ * non-solid nodes, L = sum_x beta(x).j(x) (j = sum_i c_i f*_i) obeys
+ * L(t+1) = -L(t) + sum_x beta(x).g rho(x).  Collision keeps j at each node
+ * (the force adds rho*g); streaming and bounce-back both flip the sign of
+ * every term.  These are never damped.  beta_k = (-1)^{x_k} over a set
+ * joined by links with c_k != 0 is one such field; nodes that touch only
+ * diagonally add more.  A start from rest has L = 0 for all of them and
+ * rho0 per node; any other starting state reaches a long-time state that
+ * differs unless it is projected first (lbm_project_invariants). */
 
 /* Connected components of the non-solid nodes of one lattice under the
  * links of the D2Q9 (q = 9, shape[2] = 1) or D3Q19 (q = 19) set that join
@@ -239,25 +240,27 @@ int lbm_components(int32_t q, const uint8_t *solid, const int32_t shape[3], uint
                    int32_t *labels, int32_t *count);
 
 /* Give a starting state (rho, u) for lbm_init the invariants of a start
- * from rest.  With D = 2 (q = 9) or 3 (q = 19):
- *   labels  device int32 [1 + D][nz][ny][nx]: lbm_components of the same
- *           geometry for axis -1, then axis 0 .. D-1;
- *   counts  host int32 [1 + D], the matching component counts;
+ * from rest.
+ *   q, shape, periodic  the lattice, as for lbm_components;
+ *   labels  device int32 [nz][ny][nx]: lbm_components(axis = -1) of the
+ *           geometry (negative = solid), count components;
  *   rho, u  device dense FP64, rho [nz][ny][nx] and u [3][nz][ny][nx],
  *           updated in place on non-solid nodes (solid entries untouched);
- *   scratch device FP64, 2 * (counts[0] + ... + counts[D]) entries,
- *           overwritten; must not overlap rho or u.
- * First rho is scaled per lattice-connected component so that it holds
- * rho0 per node; then, for each axis k < D and each component of the
- * c_k != 0 links, u_k -= (-1)^{x_k} S_k / M with S_k = sum (-1)^{x_k} rho u_k
- * and M = sum rho over the component, which makes S_k zero.  Parity uses the
- * lattice coordinate; on a periodic axis of odd length S_k of a component
- * that crosses the wrap is not conserved and the step only alters the guess.
+ *   scratch device FP64, 2 * count + 6 * nx * ny * nz entries, overwritten;
+ *           must not overlap rho or u.
+ * First rho is scaled per component so that it holds rho0 per node.  Then,
+ * with the link operator
+ *   (T j)(x) = 3 sum_{i: x + c_i non-solid} w_i c_i [c_i.(j(x) + j(x + c_i))] / 2,
+ * whose range is orthogonal to every staggered invariant, `iterations`
+ * (1..1000) sweeps j <- j + T(rho u - j) from j = 0 replace rho u, and
+ * u = j / rho.  T is the identity on smooth fields away from walls, so a
+ * few sweeps keep a smooth prediction while removing every invariant.
  * A component whose mass is zero or not finite yields non-finite values.
  * Asynchronous on the given stream; LBM_ERR_ARG for bad arguments,
  * LBM_ERR_HIP if a launch fails. */
-int lbm_project_invariants(int32_t q, const int32_t shape[3], const int32_t *labels, const int32_t *counts,
-                           double rho0, double *rho, double *u, double *scratch, void *stream);
+int lbm_project_invariants(int32_t q, const int32_t shape[3], uint32_t periodic, const int32_t *labels,
+                           int32_t count, double rho0, int32_t iterations, double *rho, double *u, double *scratch,
+                           void *stream);
 
 const char *lbm_strerror(int code);
 const char *lbm_last_error(void);

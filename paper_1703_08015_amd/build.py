@@ -26,9 +26,17 @@ COMMON = [
 ]
 
 
+# Per-source flags.  step19.hip: machine-level loop-invariant code motion
+# hoists the step's ~60 constant lane masks out of the persistent kernel's
+# tile loop, where they stay live across iterations and spill the scalar
+# register file (about 270 SGPRs to VGPR lanes, twice the VALU work); the
+# kernels without a runtime loop compile identically either way.
+EXTRA = {"step19.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def _compile(src):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

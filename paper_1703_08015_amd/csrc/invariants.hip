@@ -1,17 +1,26 @@
-// Projection of a starting state onto the invariants of a start from rest:
-// mass per lattice-connected component and, per axis k, the staggered
-// momentum sum (-1)^{x_k} rho u_k per component of the c_k != 0 links.
+// Projection of a starting state onto the invariants of a start from rest.
 //
-// Four launches on the caller's stream: clear the per-component sums, sum
-// (rho, 1) per component, rescale rho, sum ((-1)^{x_k} rho u_k, rho) per
-// axis component, subtract the staggered mean.  Per-component sums use
-// wave-aggregated FP64 atomics: the lanes of a wave that share a label are
-// reduced with cross-lane shuffles and one lane adds the total, so a giant
-// component costs one atomic per wave rather than one per node.
+// Mass: rho is rescaled per lattice-connected component so that it holds
+// rho0 per node.  Staggered momentum: the invariants are the functionals
+// sum_x beta(x).j(x) with beta in the null space of the link operator
+// (A beta)_link = c.beta(x+c) + c.beta(x); the operator
+//   (T j)(x) = 3 sum_{i: x + c_i fluid} w_i c_i [c_i.(j(x) + j(x + c_i))] / 2
+// equals (3/2) A^T W A, so its range is orthogonal to all of them, and the
+// Richardson sweeps j <- j + T(rho u - j) from j = 0 give a momentum field
+// with none of them while approaching rho u (T is the identity on smooth
+// fields in the bulk, with eigenvalues in [0, 1]).
+//
+// Launches on the caller's stream: clear the per-component sums, sum
+// (rho, 1) per component, rescale rho, one stencil launch per sweep
+// (ping-pong buffers in the scratch), then u = j / rho.  Per-component sums
+// use wave-aggregated FP64 atomics: the lanes of a wave that share a label
+// are reduced with cross-lane shuffles and one lane adds the total, so a
+// giant component costs one atomic per wave rather than one per node.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "device.h"
 #include "internal.h"
 
 using lbm::set_error;
@@ -19,6 +28,7 @@ using lbm::set_error;
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxIterations = 1000;
 
 // Add (a, b) of every lane to acc[2*label], acc[2*label + 1]; lanes with a
 // negative label add nothing.  Every lane of the wave must call it.
@@ -43,18 +53,13 @@ __device__ inline void wave_add2(double *acc, int label, double a, double b) {
   }
 }
 
-__device__ inline double parity_sign(int64_t i, int axis, int32_t nx, int32_t ny) {
-  int64_t coord = axis == 0 ? i % nx : axis == 1 ? (i / nx) % ny : i / ((int64_t)nx * ny);
-  return (coord & 1) ? -1.0 : 1.0;
-}
+// Labels outside [0, count) are treated as solid: a bad label array leaves
+// its nodes untouched instead of adding out of bounds.
+__device__ inline int checked(int32_t label, int32_t count) { return label < count ? label : -1; }
 
 __global__ void __launch_bounds__(kBlock) k_clear(double *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0.0;
 }
-
-// Labels outside [0, count) are treated as solid: a bad label array leaves
-// its nodes untouched instead of adding out of bounds.
-__device__ inline int checked(int32_t label, int32_t count) { return label < count ? label : -1; }
 
 __global__ void __launch_bounds__(kBlock) k_mass(int64_t n, const int32_t *lab, int32_t count, const double *rho,
                                                  double *acc) {
@@ -77,79 +82,122 @@ __global__ void __launch_bounds__(kBlock) k_rescale(int64_t n, const int32_t *la
   rho[i] = rho[i] * (rho0 * acc[2 * (int64_t)L + 1] / acc[2 * (int64_t)L]);
 }
 
-struct AxisSums {
-  double *acc[3];     // per-axis (S, M) pairs
-  int32_t count[3];   // components per axis
+struct Lattice3 {
+  int32_t nx, ny, nz;
+  uint32_t periodic;
 };
 
-__global__ void __launch_bounds__(kBlock) k_staggered(int64_t n, int dims, int32_t nx, int32_t ny, const int32_t *lab,
-                                                      const double *rho, const double *u, AxisSums sums) {
-  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  const bool in = i < n;
-  for (int k = 0; k < dims; ++k) {
-    int L = -1;
-    double s = 0.0, m = 0.0;
-    if (in) {
-      L = checked(lab[(int64_t)(1 + k) * n + i], sums.count[k]);
-      if (L >= 0) {
-        m = rho[i];
-        s = parity_sign(i, k, nx, ny) * m * u[(int64_t)k * n + i];
-      }
-    }
-    wave_add2(sums.acc[k], L, s, m);
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_unstagger(int64_t n, int dims, int32_t nx, int32_t ny,
-                                                      const int32_t *lab, AxisSums sums, double *u) {
+// j_out = j_in + T(rho u - j_in) on non-solid nodes (0 on solid ones); with
+// j_in == nullptr the sweep starts from j = 0.
+template <class L>
+__global__ void __launch_bounds__(kBlock) k_link_sweep(int64_t n, Lattice3 g, const int32_t *lab, int32_t count,
+                                                       const double *rho, const double *u, const double *j_in,
+                                                       double *j_out) {
   const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   if (i >= n) return;
-  for (int k = 0; k < dims; ++k) {
-    const int L = checked(lab[(int64_t)(1 + k) * n + i], sums.count[k]);
-    if (L < 0) continue;
-    const double *a = sums.acc[k] + 2 * (int64_t)L;
-    u[(int64_t)k * n + i] -= parity_sign(i, k, nx, ny) * (a[0] / a[1]);
+  if (checked(lab[i], count) < 0) {
+    j_out[i] = j_out[n + i] = j_out[2 * n + i] = 0.0;
+    return;
   }
+  const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((int64_t)g.nx * g.ny));
+  auto residual = [&](int64_t p, int k) {
+    const double j = j_in ? j_in[k * n + p] : 0.0;
+    return rho[p] * u[k * n + p] - j;
+  };
+  const double r0[3] = {residual(i, 0), residual(i, 1), residual(i, 2)};
+  double acc[3] = {0.0, 0.0, 0.0};
+  lbm::static_for<L::Q>([&](auto d) {
+    constexpr int cx = L::C[d][0], cy = L::C[d][1], cz = L::C[d][2];
+    if constexpr (cx != 0 || cy != 0 || cz != 0) {
+      int tx = x + cx, ty = y + cy, tz = z + cz;
+      bool inside = true;
+      if (tx < 0 || tx >= g.nx) {
+        inside &= (g.periodic & 1u) != 0;
+        tx = tx < 0 ? tx + g.nx : tx - g.nx;
+      }
+      if (ty < 0 || ty >= g.ny) {
+        inside &= (g.periodic & 2u) != 0;
+        ty = ty < 0 ? ty + g.ny : ty - g.ny;
+      }
+      if (tz < 0 || tz >= g.nz) {
+        inside &= (g.periodic & 4u) != 0;
+        tz = tz < 0 ? tz + g.nz : tz - g.nz;
+      }
+      if (inside) {
+        const int64_t t = (int64_t)tx + (int64_t)g.nx * ((int64_t)ty + (int64_t)g.ny * tz);
+        if (checked(lab[t], count) >= 0) {
+          double s = 0.0;
+          if constexpr (cx != 0) s += cx * (r0[0] + residual(t, 0));
+          if constexpr (cy != 0) s += cy * (r0[1] + residual(t, 1));
+          if constexpr (cz != 0) s += cz * (r0[2] + residual(t, 2));
+          s *= 1.5 * L::Wt[d];
+          if constexpr (cx != 0) acc[0] += cx * s;
+          if constexpr (cy != 0) acc[1] += cy * s;
+          if constexpr (cz != 0) acc[2] += cz * s;
+        }
+      }
+    }
+  });
+  for (int k = 0; k < 3; ++k) j_out[k * n + i] = (j_in ? j_in[k * n + i] : 0.0) + acc[k];
+}
+
+__global__ void __launch_bounds__(kBlock) k_velocity(int64_t n, const int32_t *lab, int32_t count, const double *rho,
+                                                     const double *j, double *u) {
+  const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (i >= n || checked(lab[i], count) < 0) return;
+  const double r = rho[i];
+  for (int k = 0; k < 3; ++k) u[k * n + i] = j[k * n + i] / r;
+}
+
+template <class L>
+void launch_sweeps(int64_t n, Lattice3 g, const int32_t *labels, int32_t count, const double *rho, const double *u,
+                   double *ja, double *jb, int iterations, hipStream_t s, const double **final_j) {
+  const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+  const double *in = nullptr;
+  double *out = ja;
+  for (int it = 0; it < iterations; ++it) {
+    hipLaunchKernelGGL(k_link_sweep<L>, dim3(grid), dim3(kBlock), 0, s, n, g, labels, count, rho, u, in, out);
+    in = out;
+    out = out == ja ? jb : ja;
+  }
+  *final_j = in;
 }
 
 }  // namespace
 
-extern "C" int lbm_project_invariants(int32_t q, const int32_t shape[3], const int32_t *labels, const int32_t *counts,
-                                      double rho0, double *rho, double *u, double *scratch, void *stream) {
-  if (!shape || !labels || !counts || !rho || !u || !scratch)
+extern "C" int lbm_project_invariants(int32_t q, const int32_t shape[3], uint32_t periodic, const int32_t *labels,
+                                      int32_t count, double rho0, int32_t iterations, double *rho, double *u,
+                                      double *scratch, void *stream) {
+  if (!shape || !labels || !rho || !u || !scratch)
     return set_error(LBM_ERR_ARG, "lbm_project_invariants: NULL argument");
   if (q != 9 && q != 19) return set_error(LBM_ERR_UNSUPPORTED, "lbm_project_invariants: q = %d", q);
-  const int dims = q == 9 ? 2 : 3;
   if (shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0 || (q == 9 && shape[2] != 1))
     return set_error(LBM_ERR_ARG, "lbm_project_invariants: shape %d x %d x %d for q = %d", shape[0], shape[1],
                      shape[2], q);
-  if (!(rho0 > 0.0) || rho0 != rho0 || rho0 > 1e300)
-    return set_error(LBM_ERR_ARG, "lbm_project_invariants: rho0 = %g", rho0);
+  if (periodic > 7u) return set_error(LBM_ERR_ARG, "lbm_project_invariants: periodic bits %u", periodic);
+  if (!(rho0 > 0.0) || rho0 > 1e300) return set_error(LBM_ERR_ARG, "lbm_project_invariants: rho0 = %g", rho0);
+  if (iterations < 1 || iterations > kMaxIterations)
+    return set_error(LBM_ERR_ARG, "lbm_project_invariants: iterations = %d (1..%d)", iterations, kMaxIterations);
   const int64_t n = (int64_t)shape[0] * shape[1] * shape[2];
-  int64_t total = 0;
-  for (int k = 0; k <= dims; ++k) {
-    if (counts[k] < 0) return set_error(LBM_ERR_ARG, "lbm_project_invariants: counts[%d] = %d", k, counts[k]);
-    if (counts[k] > n) return set_error(LBM_ERR_ARG, "lbm_project_invariants: counts[%d] = %d > %lld nodes", k,
-                                        counts[k], (long long)n);
-    total += counts[k];
-  }
-  if (counts[0] == 0) return LBM_OK;  // no non-solid node
+  if (count < 0 || count > n)
+    return set_error(LBM_ERR_ARG, "lbm_project_invariants: count = %d for %lld nodes", count, (long long)n);
+  if (count == 0) return LBM_OK;  // no non-solid node
   hipStream_t s = (hipStream_t)stream;
   const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-  const unsigned clear_grid = (unsigned)std::min<int64_t>((2 * total + kBlock - 1) / kBlock, 4096);
-  AxisSums sums{};
-  int64_t off = 2 * (int64_t)counts[0];
-  for (int k = 0; k < dims; ++k) {
-    sums.acc[k] = scratch + off;
-    sums.count[k] = counts[1 + k];
-    off += 2 * (int64_t)counts[1 + k];
-  }
-  hipLaunchKernelGGL(k_clear, dim3(clear_grid), dim3(kBlock), 0, s, scratch, 2 * total);
-  hipLaunchKernelGGL(k_mass, dim3(grid), dim3(kBlock), 0, s, n, labels, counts[0], (const double *)rho, scratch);
-  hipLaunchKernelGGL(k_rescale, dim3(grid), dim3(kBlock), 0, s, n, labels, counts[0], (const double *)scratch, rho0, rho);
-  hipLaunchKernelGGL(k_staggered, dim3(grid), dim3(kBlock), 0, s, n, dims, shape[0], shape[1], labels,
-                     (const double *)rho, (const double *)u, sums);
-  hipLaunchKernelGGL(k_unstagger, dim3(grid), dim3(kBlock), 0, s, n, dims, shape[0], shape[1], labels, sums, u);
+  const int64_t sums = 2 * (int64_t)count;
+  const unsigned clear_grid = (unsigned)std::min<int64_t>((sums + kBlock - 1) / kBlock, 4096);
+  double *acc = scratch;
+  double *ja = scratch + sums, *jb = ja + 3 * n;
+  hipLaunchKernelGGL(k_clear, dim3(clear_grid), dim3(kBlock), 0, s, acc, sums);
+  hipLaunchKernelGGL(k_mass, dim3(grid), dim3(kBlock), 0, s, n, labels, count, (const double *)rho, acc);
+  hipLaunchKernelGGL(k_rescale, dim3(grid), dim3(kBlock), 0, s, n, labels, count, (const double *)acc, rho0, rho);
+  const Lattice3 g{shape[0], shape[1], shape[2], periodic};
+  const double *j = nullptr;
+  if (q == 19)
+    launch_sweeps<lbm::D3Q19>(n, g, labels, count, rho, u, ja, jb, iterations, s, &j);
+  else
+    launch_sweeps<lbm::D2Q9>(n, g, labels, count, rho, u, ja, jb, iterations, s, &j);
+  hipLaunchKernelGGL(k_velocity, dim3(grid), dim3(kBlock), 0, s, n, labels, count, (const double *)rho, j, u);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(LBM_ERR_HIP, "lbm_project_invariants: %s", hipGetErrorString(e));
   return LBM_OK;

@@ -30,11 +30,12 @@ hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileA
 // indices below 2^32.
 bool step19_supported(const Variant &v);
 // nrec: n_ftiles + 1 records (the last one all-solid); nrow: 20 per tile, the
-// 18 neighbour slots of the D3Q19 gather in kernel order (+2 padding).
+// byte offsets into nrec of the 18 neighbour slots of the D3Q19 gather in
+// kernel order (+2 padding).
 // mode 0: wavefront w -> tile w; 1: -> list[w] for w < *count; 2: persistent
 // grid of blocks_persistent workgroups striding over list[0 .. *count).
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const uint32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
                          const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s);
 hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,

@@ -36,7 +36,7 @@ struct Plan {
   std::vector<lbm::CollideCoef> coef_h;
   // scalar-mask D3Q19 kernel: compact records (+ all-solid sentinel) and rows
   std::vector<lbm::NbRec> nrec_h;
-  std::vector<int32_t> nrow_h;
+  std::vector<uint32_t> nrow_h;  // byte offsets into nrec
 };
 
 // Neighbour slots (3x3x3 index) of the D3Q19 gather, in the order the
@@ -153,13 +153,19 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
     P.entries = off;
     if (q == 19 && W == 1) {
       P.nrec_h.resize((size_t)nft + 1);
-      P.nrow_h.assign((size_t)(nft * 20), (int32_t)nft);
+      // neighbour rows hold byte offsets into the record array (the sentinel
+      // record for a missing neighbour), so the kernel adds them to the base
+      // pointer without a 64-bit multiply
+      if ((uint64_t)(nft + 1) * sizeof(lbm::NbRec) > UINT32_MAX)
+        return set_error(LBM_ERR_UNSUPPORTED, "too many tiles (%lld) for 32-bit record offsets", (long long)nft);
+      const uint32_t sentinel = (uint32_t)((uint64_t)nft * sizeof(lbm::NbRec));
+      P.nrow_h.assign((size_t)(nft * 20), sentinel);
       for (int64_t k = 0; k < nft; ++k) {
         const lbm::TileRec &r = P.rec_h[(size_t)k];
         P.nrec_h[(size_t)k] = lbm::NbRec{(uint32_t)r.off, (uint32_t)r.n, P.fluid_h[(size_t)k], r.sample, 0};
         for (int j = 0; j < 18; ++j) {
           const int32_t o = P.nbr_h[(size_t)(k * 27 + kGatherSlots[j])];
-          P.nrow_h[(size_t)(k * 20 + j)] = o < 0 ? (int32_t)nft : o;
+          P.nrow_h[(size_t)(k * 20 + j)] = o < 0 ? sentinel : (uint32_t)((uint64_t)o * sizeof(lbm::NbRec));
         }
       }
       P.nrec_h[(size_t)nft] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
@@ -203,7 +209,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.samples = take(t->samples.size() * sizeof(lbm::SampleRec));
   P.coef = take(t->samples.size() * sizeof(lbm::CollideCoef));
   P.nrec = take(P.nrec_h.size() * sizeof(lbm::NbRec));
-  P.nrow = take(P.nrow_h.size() * sizeof(int32_t));
+  P.nrow = take(P.nrow_h.size() * sizeof(uint32_t));
   P.list = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
   P.count = take(sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
@@ -234,7 +240,7 @@ struct lbm_solver {
   std::vector<lbm::CollideCoef> coef_h;
   lbm::CollideCoef *coef_d = nullptr;
   const lbm::NbRec *nrec_d = nullptr;
-  const int32_t *nrow_d = nullptr;
+  const uint32_t *nrow_d = nullptr;
   // active tile list (batches) and the launch mode of the scalar-mask step
   int32_t *list_d = nullptr, *count_d = nullptr;
   std::vector<int32_t> list_h;
@@ -322,7 +328,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->coef_h = P.coef_h;
   s->coef_d = reinterpret_cast<lbm::CollideCoef *>(base + P.coef);
   s->nrec_d = reinterpret_cast<const lbm::NbRec *>(base + P.nrec);
-  s->nrow_d = reinterpret_cast<const int32_t *>(base + P.nrow);
+  s->nrow_d = reinterpret_cast<const uint32_t *>(base + P.nrow);
   s->list_d = reinterpret_cast<int32_t *>(base + P.list);
   s->count_d = reinterpret_cast<int32_t *>(base + P.count);
   s->storage_bytes = lbm::storage_bytes(v.storage);
@@ -390,7 +396,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if (e == hipSuccess) e = up(P.coord, P.coord_h.data(), (size_t)(nft * 3) * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.coef, P.coef_h.data(), P.coef_h.size() * sizeof(lbm::CollideCoef));
   if (e == hipSuccess) e = up(P.nrec, P.nrec_h.data(), P.nrec_h.size() * sizeof(lbm::NbRec));
-  if (e == hipSuccess) e = up(P.nrow, P.nrow_h.data(), P.nrow_h.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = up(P.nrow, P.nrow_h.data(), P.nrow_h.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = up(P.list, s->list_h.data(), s->list_h.size() * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.count, &s->count_h, sizeof(int32_t));
   if (e == hipSuccess && s->scalar_mask && p->persistent) e = lbm::step19_persistent_blocks(v, &s->persistent_blocks);

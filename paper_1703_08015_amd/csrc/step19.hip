@@ -87,7 +87,7 @@ constexpr int slot_of(int k) {
 template <int S, bool NT>
 __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict__ src_, void *__restrict__ dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
-                                            const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
+                                            const uint32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
   using L = D3Q19;
   using St = Store<S>;
   using T = typename St::T;
@@ -102,7 +102,7 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
   NbRec nb[18];
   static_for<18>([&](auto J) {
     constexpr int j = decltype(J)::value;
-    nb[j] = nrec[nrow[tile * 20 + j]];
+    nb[j] = *reinterpret_cast<const NbRec *>(reinterpret_cast<const char *>(nrec) + nrow[tile * 20 + j]);
   });
   const uint64_t M = own.mask;
   if (!((M >> lane) & 1ull)) return;
@@ -197,7 +197,7 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 template <int S, int WPB, bool NT, int MODE>
 __global__ void __launch_bounds__(64 * WPB)
     k_step19(const void *__restrict__ src, void *__restrict__ dst, TileArgs a, const NbRec *__restrict__ nrec,
-             const int32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
+             const uint32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
              const int32_t *__restrict__ count) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(64 * WPB)
 bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
 
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const int32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const uint32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
                          const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
   const unsigned blocks =

@@ -99,7 +99,7 @@ def lib():
             "lbm_pdfs_import": (ctypes.c_int, [P, P]),
             "lbm_step_count": (I64, [P]),
             "lbm_components": (ctypes.c_int, [I32, P, P, U32, I32, P, P]),
-            "lbm_project_invariants": (ctypes.c_int, [I32, P, P, P, ctypes.c_double, P, P, P, P]),
+            "lbm_project_invariants": (ctypes.c_int, [I32, P, U32, P, I32, ctypes.c_double, I32, P, P, P, P]),
             "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "lbm_last_error": (ctypes.c_char_p, []),
         }
@@ -152,8 +152,8 @@ def components(solid, lattice=19, axis=-1, periodic=(1, 1, 1)):
 
 
 class Invariants:
-    """Component labels of one geometry on the GPU, for
-    lbm_project_invariants: mass components, then one labelling per axis."""
+    """Component labels of one geometry on the GPU and the scratch for
+    lbm_project_invariants."""
 
     def __init__(self, solid, lattice=19, periodic=(1, 1, 1), device="cuda"):
         import torch
@@ -162,17 +162,13 @@ class Invariants:
             m = m[None]
         self.lattice = int(lattice)
         self.shape = tuple(m.shape)
-        dims = 2 if self.lattice == 9 else 3
-        labs, counts = [], []
-        for axis in range(-1, dims):
-            lab, n = components(m, self.lattice, axis, periodic)
-            labs.append(lab)
-            counts.append(n)
-        self.counts = np.array(counts, np.int32)
-        self.labels = torch.from_numpy(np.stack(labs)).to(device)
-        self.scratch = torch.empty(max(1, 2 * int(self.counts.sum())), dtype=torch.float64, device=device)
+        self.periodic = _periodic_bits(periodic)
+        lab, self.count = components(m, self.lattice, -1, self.periodic)
+        self.labels = torch.from_numpy(lab).to(device)
+        n = int(np.prod(self.shape))
+        self.scratch = torch.empty(2 * self.count + 6 * n, dtype=torch.float64, device=device)
 
-    def project(self, rho, u, rho0=1.0, stream=None):
+    def project(self, rho, u, rho0=1.0, iterations=8, stream=None):
         """In place on device FP64 rho (nz, ny, nx) and u (3, nz, ny, nx)."""
         import torch
         n = int(np.prod(self.shape))
@@ -181,8 +177,9 @@ class Invariants:
             raise ValueError("rho and u must be contiguous FP64 of %d and %d elements" % (n, 3 * n))
         shape = np.array([self.shape[2], self.shape[1], self.shape[0]], np.int32)
         s = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().lbm_project_invariants(self.lattice, _np_ptr(shape), ctypes.c_void_p(self.labels.data_ptr()),
-                                            _np_ptr(self.counts), float(rho0), ctypes.c_void_p(rho.data_ptr()),
+        _check(lib().lbm_project_invariants(self.lattice, _np_ptr(shape), self.periodic,
+                                            ctypes.c_void_p(self.labels.data_ptr()), self.count, float(rho0),
+                                            int(iterations), ctypes.c_void_p(rho.data_ptr()),
                                             ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(self.scratch.data_ptr()),
                                             ctypes.c_void_p(s.cuda_stream)), "lbm_project_invariants")
 

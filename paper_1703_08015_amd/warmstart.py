@@ -3,7 +3,8 @@ whose (rho, u) prediction initialises the solver through f_eq (lbm_init).
 
 The prediction is first given the invariants of a start from rest
 (lbm_project_invariants): mass rho0 per node on every lattice-connected
-component and zero staggered momentum per axis component.  The discrete
+component, and a momentum field with no component along any of the step's
+staggered invariants (a few sweeps of the link operator).  The discrete
 dynamics never change those, so without the projection a warm start settles
 into a different long-time state than the cold start.
 

@@ -1,6 +1,7 @@
 """lbm_project_invariants against the FP64 oracle projection: D3Q19 sphere
-packings (periodic, walled, odd extents, many components), D2Q9, the
-all-solid no-op; solid entries untouched; repeated calls reuse the scratch."""
+packings (periodic, walled, odd extents, many components, diagonal-only
+contacts), D2Q9, the all-solid no-op; solid entries untouched; repeated
+calls reuse the scratch; the result carries none of the exact invariants."""
 import zlib
 
 import numpy as np
@@ -26,35 +27,59 @@ def _cases():
     dense, _ = inputs.spheres_3d(32, 0.3, 1.5, 3.0, seed=8)  # many small pores
     walled, _ = inputs.spheres_3d((20, 12, 16), 0.55, 2.0, 4.0, seed=5, periodic=(False, False, False))
     odd, _ = inputs.spheres_3d((13, 9, 11), 0.55, 2.0, 3.0, seed=6)
+    diagonal, _ = inputs.spheres_3d(12, 0.5, 1.5, 3.0, seed=3)  # nodes touching only diagonally
     flat = np.random.default_rng(3).random((1, 36, 40)) < 0.5
     return [("cavity24", 19, cavity, 7), ("dense32", 19, dense, 7), ("walled", 19, walled, 0),
-            ("odd", 19, odd, 7), ("d2q9", 9, flat, 3), ("d2q9_walled", 9, flat, 0)]
+            ("odd", 19, odd, 7), ("diagonal12", 19, diagonal, 7), ("d2q9", 9, flat, 3), ("d2q9_walled", 9, flat, 0)]
 
 
-@pytest.mark.parametrize("name,q,mask,periodic", _cases(), ids=[c[0] for c in _cases()])
-def test_projection_matches_oracle(torch, name, q, mask, periodic):
+def _fields(name, q, mask):
     rng = np.random.default_rng(zlib.crc32(name.encode()))
     rho = np.where(mask, 7.0, 1.0 + 0.01 * rng.normal(size=mask.shape))
     u = np.where(mask[None], 7.0, 0.01 * rng.normal(size=(3,) + mask.shape))
     if q == 9:
         u[2] = np.where(mask, 7.0, 0.0)
-    bits = periodic
-    ref_r, ref_u = invariants.project(mask, rho, u, q, rho0=1.0, periodic=bits)
-    inv = lbm.Invariants(mask, q, periodic=[bool(bits >> a & 1) for a in range(3)])
-    assert list(inv.counts) == [invariants.components(mask, q, k, bits)[1] for k in range(-1, 2 if q == 9 else 3)]
-    print(name, "components", list(inv.counts), flush=True)
-    for call in range(2):
-        r_d = torch.from_numpy(rho.copy()).cuda()
-        u_d = torch.from_numpy(u.copy()).cuda()
-        inv.project(r_d, u_d, rho0=1.0)
-        torch.cuda.synchronize()
-        r_h, u_h = r_d.cpu().numpy(), u_d.cpu().numpy()
-        fl = ~mask
-        assert np.all(r_h[mask] == 7.0) and np.all(u_h[:, mask] == 7.0), "solid entries changed"
-        assert np.abs(r_h[fl] - ref_r[fl]).max() <= 1e-13
-        assert np.abs(u_h[:, fl] - ref_u[:, fl]).max() <= 1e-15
-        if q == 9:
-            assert np.all(u_h[2][fl] == 0.0)
+    return rho, u
+
+
+@pytest.mark.parametrize("name,q,mask,periodic", _cases(), ids=[c[0] for c in _cases()])
+def test_projection_matches_oracle(torch, name, q, mask, periodic):
+    rho, u = _fields(name, q, mask)
+    inv = lbm.Invariants(mask, q, periodic=[bool(periodic >> a & 1) for a in range(3)])
+    assert inv.count == invariants.components(mask, q, -1, periodic)[1]
+    print(name, "components", inv.count, flush=True)
+    for iterations in (1, 8):
+        ref_r, ref_u = invariants.project(mask, rho, u, q, rho0=1.0, periodic=periodic, iterations=iterations)
+        for call in range(2):
+            r_d = torch.from_numpy(rho.copy()).cuda()
+            u_d = torch.from_numpy(u.copy()).cuda()
+            inv.project(r_d, u_d, rho0=1.0, iterations=iterations)
+            torch.cuda.synchronize()
+            r_h, u_h = r_d.cpu().numpy(), u_d.cpu().numpy()
+            fl = ~mask
+            assert np.all(r_h[mask] == 7.0) and np.all(u_h[:, mask] == 7.0), "solid entries changed"
+            assert np.abs(r_h[fl] - ref_r[fl]).max() <= 1e-13
+            assert np.abs(u_h[:, fl] - ref_u[:, fl]).max() <= 1e-14 * np.abs(ref_u[:, fl]).max()
+            if q == 9:
+                assert np.all(u_h[2][fl] == 0.0)
+
+
+def test_projected_momentum_carries_no_invariant(torch):
+    """Against the exact invariant basis (dense null space of the link
+    operator) of a packing with diagonal-only contacts."""
+    mask, _ = inputs.spheres_3d(12, 0.5, 1.5, 3.0, seed=3)
+    basis = invariants.invariant_basis(mask, 19)
+    rho, u = _fields("basis", 19, mask)
+    inv = lbm.Invariants(mask, 19)
+    r_d = torch.from_numpy(rho.copy()).cuda()
+    u_d = torch.from_numpy(u.copy()).cuda()
+    inv.project(r_d, u_d)
+    torch.cuda.synchronize()
+    r_h, u_h = r_d.cpu().numpy(), u_d.cpu().numpy()
+    j = (np.where(mask, 0.0, r_h)[None] * np.where(mask[None], 0.0, u_h)).transpose(1, 2, 3, 0).ravel()
+    raw = (np.where(mask, 0.0, rho)[None] * np.where(mask[None], 0.0, u)).transpose(1, 2, 3, 0).ravel()
+    assert np.abs(basis.T @ raw).max() > 1e-3 * np.linalg.norm(raw)
+    assert np.abs(basis.T @ j).max() <= 1e-14 * np.linalg.norm(j)
 
 
 def test_projection_of_rest_and_all_solid(torch):
@@ -67,9 +92,20 @@ def test_projection_of_rest_and_all_solid(torch):
     assert torch.equal(r.cpu(), torch.from_numpy(np.where(mask, 0.0, 1.0))) and not u.any()
     solid = np.ones((8, 8, 8), bool)
     inv0 = lbm.Invariants(solid, 19)
-    assert list(inv0.counts) == [0, 0, 0, 0]
+    assert inv0.count == 0
     r0 = torch.full((8, 8, 8), 3.0, dtype=torch.float64, device="cuda")
     u0 = torch.full((3, 8, 8, 8), 3.0, dtype=torch.float64, device="cuda")
     inv0.project(r0, u0)
     torch.cuda.synchronize()
     assert bool((r0 == 3.0).all()) and bool((u0 == 3.0).all())
+
+
+def test_projection_argument_errors(torch):
+    mask, _ = inputs.spheres_3d(8, 0.5, 2.0, 3.0, seed=1)
+    inv = lbm.Invariants(mask, 19)
+    r = torch.ones(mask.shape, dtype=torch.float64, device="cuda")
+    u = torch.zeros((3,) + mask.shape, dtype=torch.float64, device="cuda")
+    for kw in (dict(iterations=0), dict(iterations=1001), dict(rho0=0.0)):
+        with pytest.raises(lbm.LbmError) as e:
+            inv.project(r, u, **kw)
+        assert e.value.code == lbm.LBM_ERR_ARG
