@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA, MI355X
 METRIC = "D3Q19 sparse MLUPS & % HBM peak; time-to-steady-state, warm vs cold, FP32 vs FP64"
 SD = {"f64": 8, "f32": 4, "f16": 2}
 
@@ -246,6 +247,72 @@ def mode_batch(args, torch, lbm):
             "node_updates": updates, "mlups": round(updates / wall / 1e6, 1), "geometry_seconds": round(t_geom, 1)}
 
 
+def unet_flops(n, levels=4, base=24, in_ch=8, out_ch=12):
+    """Dense FLOPs of one U-Net forward pass on an n^3 grid: 2*27*cin*cout per
+    voxel and 3x3x3 convolution, 2*8*cin*cout per coarse voxel of a 2x2x2
+    transposed convolution, 2*cin*cout per voxel of the 1x1x1 head."""
+    C = [base * 2 ** l for l in range(levels)]
+    vox = float(n) ** 3
+    f, cin = 0.0, in_ch
+    for l in range(levels):
+        v = vox / 8 ** l
+        f += 2 * 27 * cin * C[l] * v + 2 * 27 * C[l] * C[l] * v
+        cin = C[l]
+    for l in range(levels - 2, -1, -1):
+        v = vox / 8 ** l
+        f += 2 * 8 * C[l + 1] * C[l] * (v / 8) + 2 * 27 * 2 * C[l] * C[l] * v + 2 * 27 * C[l] * C[l] * v
+    return f + 2 * C[0] * ((out_ch + 7) // 8 * 8) * vox
+
+
+def mode_unet(args, torch, lbm):
+    """Throughput of the warm-start network's kernels: one forward pass and one
+    training step (forward, backward, Adam) per sample size, HIP events on the
+    current stream, against the dense BF16 MFMA peak."""
+    from paper_1703_08015_amd import inputs, warmstart
+    net = warmstart.make_net(levels=4, base=24, seed=args.seed)
+    out = {}
+    for n in (64, 128):
+        m, _ = inputs.spheres_3d(n, 0.5, 4.0, 12.0, seed=args.seed + 1)
+        sm = warmstart.Sample(torch, m, (args.g, 0.0, 0.0))
+        x = warmstart.encode(torch, sm)
+        dout = torch.zeros(sm.shape + (8,), dtype=torch.bfloat16, device="cuda")
+
+        def timed(fn, reps):
+            for _ in range(2):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        def train_step():
+            net.forward_mixed(x, sm.dir)
+            net.zero_grad()
+            net.backward_mixed(dout, 8, sm.dir)
+            net.adam_step(1e-6)
+
+        fwd = timed(lambda: net.forward_mixed(x, sm.dir), 10)
+        trn = timed(train_step, 5)
+        F = unet_flops(n)
+        out["%d^3" % n] = {"forward_ms": round(fwd, 3), "forward_tflops": round(F / fwd / 1e9, 1),
+                           "train_step_ms": round(trn, 3), "train_tflops": round(3 * F / trn / 1e9, 1),
+                           "gflop_forward": round(F / 1e9, 1)}
+    big = out["128^3"]
+    return {"metric": "U-Net forward throughput (warm-start network)", "unit": "TFLOP/s",
+            "value": big["forward_tflops"], "higher_is_better": True, "dtype": "bf16 (fp32 accumulate)",
+            "data": "synthetic",
+            "config": {"workload": "U-Net 4 levels x 24 base channels, %d parameters, on 128^3 and 64^3 porous "
+                                   "cubes (distance input), batch 1" % net.n_params()},
+            "roofline": {"bound": "mfma", "achieved": big["forward_tflops"], "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(big["forward_tflops"] / BF16_PEAK_TFLOPS, 4),
+                         "traffic": None},
+            "sizes": out}
+
+
 def mode_warmstart(args, torch, lbm):
     """Train the U-Net on steady states of the porous-cube batch (edges that
     are multiples of 8), then compare warm and cold starts to the same
@@ -294,6 +361,7 @@ def mode_warmstart(args, torch, lbm):
                                    (len(specs), args.epochs, args.lr)},
             "cold_seconds": round(cold_s, 3), "warm_seconds_incl_inference": round(warm_s, 3),
             "speedup": round(cold_s / warm_s, 3) if warm_s > 0 else None,
+            "labels_seconds": round(sum(r["labels_s"] for r in rows), 3),
             "cold_steps_mean": float(np.mean([r["cold_steps"] for r in rows])),
             "warm_steps_mean": float(np.mean([r["warm_steps"] for r in rows])),
             "prediction_u_rel_l2_mean": float(np.mean([r["prediction_u_rel_l2"] for r in rows])),
@@ -322,8 +390,8 @@ def main():
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart"])
-    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--test-samples", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -352,7 +420,7 @@ def main():
             args.tau = 0.8 if args.tau == 0.7 else args.tau
             args.storage = "f32" if args.storage == "f64" else args.storage
         res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch,
-               "warmstart": mode_warmstart}[args.mode](args, torch, lbm)
+               "warmstart": mode_warmstart, "unet": mode_unet}[args.mode](args, torch, lbm)
         res["n_gpus"] = 1
         print(json.dumps(res), flush=True)
         return

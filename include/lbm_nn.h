@@ -66,8 +66,9 @@ int lbm_nn_forward(const lbm_nn_gemm *g, void *stream);
 /* Weight gradient of the same layer: dw[n][t*cin + c] += sum_m x[src(m,t)][c]
  * * dy[dst(m)][n], with g->y the BF16 gradient dy (row stride ldy) and dw an
  * FP32 [cout][taps*cin] accumulator (not cleared); g->w and g->bias unused.
- * If db is not NULL it accumulates sum_m dy[dst(m)][n] (taps 0 / per tap for
- * SCATTER2). */
+ * If db is not NULL it accumulates the bias gradient, the sum of dy[v][n]
+ * over every output voxel v (for SCATTER2 all 8 fine voxels of each coarse
+ * one); at most 2048 output channels then (else LBM_ERR_SHAPE). */
 int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream);
 
 /* Weights of the backward-data pass of a layer, so that lbm_nn_forward with
@@ -115,6 +116,22 @@ int lbm_nn_mix_backward(int64_t n, const void *dp, int32_t ldp, const float dir[
 /* Network input: x (BF16 [nodes][8]) = (solid, gx, gy, gz on fluid nodes, 0...)
  * from a uint8 solid mask and a unit force direction. */
 int lbm_nn_encode_input(int64_t n, const uint8_t *solid, const float dir[3], void *x, void *stream);
+
+/* Distance of every node to the nearest solid node along lattice links:
+ * the shortest path over D3Q19 links of length 1 (faces) or sqrt(2) (edges),
+ * wrapping on periodic axes (bits as in lbm_tiles_build); 0 on solid nodes.
+ * solid: device uint8 [nz][ny][nx] (shape = {nx, ny, nz}); dist, tmp: device
+ * FP32 of the same size (tmp is scratch).  Each sweep is one Bellman-Ford
+ * relaxation d <- min(d, d(x + c) + |c|); sweeps are run in pairs (an odd
+ * count runs one more), and distances longer than about one unit per sweep
+ * stay at 1e30 (also where no solid node is reachable). */
+int lbm_nn_distance(const int32_t shape[3], uint32_t periodic, const uint8_t *solid, int32_t sweeps, float *dist,
+                    float *tmp, void *stream);
+
+/* Network input from the geometry: x (BF16 [nodes][8]) = (solid, s, s^2, 0, ...)
+ * with s = min(dist * scale, cap) on non-solid nodes (0 on solid ones). */
+int lbm_nn_encode_geometry(int64_t n, const uint8_t *solid, const float *dist, float scale, float cap, void *x,
+                           void *stream);
 
 /* Network output (FP32 [nodes][4]: scaled (rho - rho0, u)) to dense FP64
  * fields for lbm_init: rho = rho0 + s*p0, u = s*p[1..3] on fluid nodes, 0 on

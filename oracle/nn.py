@@ -14,6 +14,8 @@ and their gradients (backward data and weights), written as the adjoints of
 these linear maps.
 """
 import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import dijkstra
 
 OFFS = [((t // 9) - 1, ((t // 3) % 3) - 1, (t % 3) - 1) for t in range(27)]  # (dz, dy, dx)
 CORNERS = [((a >> 2) & 1, (a >> 1) & 1, a & 1) for a in range(8)]  # (az, ay, ax)
@@ -106,3 +108,46 @@ def adam(p, m, v, g, lr, b1, b2, eps, step):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# D3Q19 link offsets (faces and edges) and their lengths
+LINKS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+         if 0 < abs(dx) + abs(dy) + abs(dz) <= 2]
+
+
+def distance(solid, periodic=7):
+    """Length of the shortest path over D3Q19 links (1 for faces, sqrt(2) for
+    edges) from every node to the nearest solid node (multi-source Dijkstra);
+    inf where no solid node is reachable.  solid: (nz, ny, nx) bool."""
+    solid = np.asarray(solid, bool)
+    nz, ny, nx = solid.shape
+    idx = np.arange(solid.size).reshape(solid.shape)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    rows, cols, w = [], [], []
+    for dx, dy, dz in LINKS:
+        tx, ty, tz = x + dx, y + dy, z + dz
+        ok = np.ones(solid.shape, bool)
+        for t, n, bit in ((tx, nx, 1), (ty, ny, 2), (tz, nz, 4)):
+            if not (periodic & bit):
+                ok &= (t >= 0) & (t < n)
+        rows.append(idx[ok])
+        cols.append(idx[tz % nz, ty % ny, tx % nx][ok])
+        w.append(np.full(int(ok.sum()), np.sqrt(abs(dx) + abs(dy) + abs(dz))))
+    graph = coo_matrix((np.concatenate(w), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(solid.size, solid.size)).tocsr()
+    sources = np.flatnonzero(solid.ravel())
+    if sources.size == 0:
+        return np.full(solid.shape, np.inf)
+    return dijkstra(graph, directed=True, indices=sources, min_only=True).reshape(solid.shape)
+
+
+def encode_geometry(solid, dist, scale, cap):
+    """(nz, ny, nx, 8): solid flag, s = min(dist * scale, cap) and s^2 on
+    non-solid nodes, zeros elsewhere."""
+    solid = np.asarray(solid, bool)
+    v = np.where(solid, 0.0, np.minimum(np.asarray(dist) * scale, cap))
+    out = np.zeros(solid.shape + (8,))
+    out[..., 0] = solid
+    out[..., 1] = v
+    out[..., 2] = v * v
+    return out

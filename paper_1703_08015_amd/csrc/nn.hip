@@ -10,6 +10,7 @@
 
 #include <cmath>
 
+#include "device.h"
 #include "internal.h"
 #include "lbm_nn.h"
 
@@ -194,25 +195,44 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
   }
 }
 
-// bias gradient: db[n] += sum over rows of dy[dst(m)][n] (per tap for SCATTER2)
-template <int DST>
-__global__ void __launch_bounds__(256) k_bias_grad(GemmArgs a, float *db, int64_t chunk) {
-  const int n = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int part = threadIdx.x >> 6;
-  __shared__ float red[4][64];
-  float s = 0.f;
-  if (n < a.cout) {
-    const int taps = DST == LBM_NN_SCATTER2 ? a.taps : 1;
-    const int64_t v0 = (int64_t)blockIdx.x * chunk;
-    const int64_t v1 = v0 + chunk < a.M ? v0 + chunk : a.M;
-    for (int t = 0; t < taps; ++t)
-      for (int64_t m = v0 + part; m < v1; m += 4)
-        s += (float)static_cast<const bf16 *>(a.y)[dst_voxel<DST>(m, t, a.rows, a.out_grid) * a.ldy + n];
+// bias gradient: db[n] += sum over rows of dy[row][n], a column sum of a
+// (rows x ld) BF16 matrix.  For SCATTER2 every fine output voxel is exactly
+// one (coarse voxel, tap) pair, so the rows are simply all output voxels.
+// Thread t reads 8 channels (one 16-byte load) of rows r0 + k * RP, where the
+// block's 256 threads form RP row lanes x CG channel groups; the row lanes
+// meet in LDS and one atomic per channel and block adds the total.
+__global__ void __launch_bounds__(256) k_colsum(const bf16 *y, int64_t rows, int ld, int cols, float *db,
+                                                int64_t chunk) {
+  const int cg_count = (cols + 7) / 8;
+  const int rp = 256 / cg_count;  // row lanes per block (cols <= 2048)
+  const int t = threadIdx.x;
+  const int lane_row = t / cg_count, cg = t % cg_count;
+  __shared__ float red[256][8];
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  if (lane_row < rp) {
+    const int c = 8 * cg;
+    for (int64_t r = r0 + lane_row; r < r1; r += rp) {
+      const bf16 *row = y + r * ld + c;
+      if (c + 8 <= cols) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(row);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] += (float)v[q];
+      } else {
+        for (int q = 0; q < cols - c; ++q) acc[q] += (float)row[q];
+      }
+    }
   }
-  red[part][threadIdx.x & 63] = s;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[t][q] = acc[q];
   __syncthreads();
-  if (part == 0 && n < a.cout) atomicAdd(db + n, red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                                                     red[3][threadIdx.x]);
+  for (int ch = t; ch < cols; ch += 256) {
+    const int g = ch / 8, q = ch % 8;
+    float sum = 0.f;
+    for (int l = 0; l < rp; ++l) sum += red[l * cg_count + g][q];
+    atomicAdd(db + ch, sum);
+  }
 }
 
 __global__ void k_backward_weights(int mode, int taps, int cin, int cout, const bf16 *w, bf16 *wt) {
@@ -335,6 +355,64 @@ __global__ void k_encode(int64_t n, const uint8_t *solid, float dx, float dy, fl
     row[2] = (bf16)(s ? 0.f : dy);
     row[3] = (bf16)(s ? 0.f : dz);
     for (int c = 4; c < 8; ++c) row[c] = (bf16)0.f;
+  }
+}
+
+// ---- geometry input: distance to the nearest solid node -----------------------
+// Shortest path along D3Q19 links (length 1 for faces, sqrt(2) for edges) to a
+// solid node; each sweep is one Bellman-Ford relaxation d <- min(d, d(x+c) + |c|).
+constexpr float kFar = 1e30f;
+
+__global__ void k_dist_init(int64_t n, const uint8_t *solid, float *d) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    d[e] = solid[e] ? 0.f : kFar;
+}
+
+__global__ void __launch_bounds__(256) k_dist_sweep(Grid g, uint32_t periodic, const uint8_t *solid,
+                                                    const float *din, float *dout) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  if (solid[e]) {
+    dout[e] = 0.f;
+    return;
+  }
+  const int x = (int)(e % g.nx), y = (int)((e / g.nx) % g.ny), z = (int)(e / ((int64_t)g.nx * g.ny));
+  float best = din[e];
+  lbm::static_for<19>([&](auto i) {
+    constexpr int cx = lbm::D3Q19::C[i][0], cy = lbm::D3Q19::C[i][1], cz = lbm::D3Q19::C[i][2];
+    if constexpr (cx != 0 || cy != 0 || cz != 0) {
+      constexpr float len = ((cx != 0) + (cy != 0) + (cz != 0)) == 1 ? 1.0f : 1.41421356237309515f;
+      int tx = x + cx, ty = y + cy, tz = z + cz;
+      bool inside = true;
+      if (tx < 0 || tx >= g.nx) {
+        inside &= (periodic & 1u) != 0;
+        tx = tx < 0 ? tx + g.nx : tx - g.nx;
+      }
+      if (ty < 0 || ty >= g.ny) {
+        inside &= (periodic & 2u) != 0;
+        ty = ty < 0 ? ty + g.ny : ty - g.ny;
+      }
+      if (tz < 0 || tz >= g.nz) {
+        inside &= (periodic & 4u) != 0;
+        tz = tz < 0 ? tz + g.nz : tz - g.nz;
+      }
+      if (inside) best = fminf(best, din[vidx(tx, ty, tz, g)] + len);
+    }
+  });
+  dout[e] = best;
+}
+
+// x row = (solid, s, s^2, 0, ...) with s = min(d * scale, cap) on non-solid nodes
+__global__ void k_encode_geometry(int64_t n, const uint8_t *solid, const float *d, float scale, float cap, bf16 *x) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool sd = solid[e] != 0;
+    const float v = sd ? 0.f : fminf(d[e] * scale, cap);
+    bf16 *row = x + e * 8;
+    row[0] = (bf16)(sd ? 1.f : 0.f);
+    row[1] = (bf16)v;
+    row[2] = (bf16)(v * v);
+    for (int c = 3; c < 8; ++c) row[c] = (bf16)0.f;
   }
 }
 
@@ -496,6 +574,7 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
   int rc = check_gemm(g, true);
   if (rc) return rc;
   if (!dw) return set_error(LBM_ERR_ARG, "lbm_nn_wgrad: NULL dw");
+  if (db && g->cout > 2048) return set_error(LBM_ERR_SHAPE, "lbm_nn_wgrad: bias gradient of %d > 2048 channels", g->cout);
   const GemmArgs a = to_args(g);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (g->dst_mode == LBM_NN_SCATTER2) {
@@ -508,12 +587,12 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
     NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, s)));
   }
   if (db) {
-    int64_t chunk = 4096;
-    const unsigned gx = (unsigned)((a.M + chunk - 1) / chunk), gy = (unsigned)((a.cout + 63) / 64);
-    if (g->dst_mode == LBM_NN_SCATTER2)
-      hipLaunchKernelGGL(k_bias_grad<LBM_NN_SCATTER2>, dim3(gx, gy), dim3(256), 0, s, a, db, chunk);
-    else
-      hipLaunchKernelGGL(k_bias_grad<LBM_NN_IDENT>, dim3(gx, gy), dim3(256), 0, s, a, db, chunk);
+    // all output voxels: M rows, or M * 8 fine voxels of a 2x2x2 transposed convolution
+    const int64_t rows = g->dst_mode == LBM_NN_SCATTER2 ? (int64_t)a.out_grid.nx * a.out_grid.ny * a.out_grid.nz : a.M;
+    const int64_t chunk = 1024;
+    const unsigned gx = (unsigned)((rows + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_colsum, dim3(gx), dim3(256), 0, s, static_cast<const bf16 *>(a.y), rows, a.ldy, a.cout, db,
+                       chunk);
     NN_TRY(hipGetLastError());
   }
   return LBM_OK;
@@ -605,6 +684,35 @@ extern "C" int lbm_nn_encode_input(int64_t n, const uint8_t *solid, const float 
   if (!solid || !dir || !x || n < 0) return set_error(LBM_ERR_ARG, "lbm_nn_encode_input: args");
   hipLaunchKernelGGL(k_encode, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, solid, dir[0],
                      dir[1], dir[2], static_cast<bf16 *>(x));
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_distance(const int32_t shape[3], uint32_t periodic, const uint8_t *solid, int32_t sweeps,
+                               float *dist, float *tmp, void *stream) {
+  if (!shape || !solid || !dist || !tmp || dist == tmp) return set_error(LBM_ERR_ARG, "lbm_nn_distance: args");
+  if (shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0 || periodic > 7u || sweeps < 0 || sweeps > 100000)
+    return set_error(LBM_ERR_ARG, "lbm_nn_distance: shape %d x %d x %d, periodic %u, sweeps %d", shape[0], shape[1],
+                     shape[2], periodic, sweeps);
+  const Grid g{shape[0], shape[1], shape[2]};
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_dist_init, dim3(grid_for(n)), dim3(256), 0, s, n, solid, dist);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  for (int k = 0; k < (sweeps + 1) / 2; ++k) {  // pairs of sweeps end in dist
+    hipLaunchKernelGGL(k_dist_sweep, dim3(grid), dim3(256), 0, s, g, periodic, solid, (const float *)dist, tmp);
+    hipLaunchKernelGGL(k_dist_sweep, dim3(grid), dim3(256), 0, s, g, periodic, solid, (const float *)tmp, dist);
+  }
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+extern "C" int lbm_nn_encode_geometry(int64_t n, const uint8_t *solid, const float *dist, float scale, float cap,
+                                      void *x, void *stream) {
+  if (!solid || !dist || !x || n < 0 || !(scale > 0.f) || !(cap > 0.f))
+    return set_error(LBM_ERR_ARG, "lbm_nn_encode_geometry: args");
+  hipLaunchKernelGGL(k_encode_geometry, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, solid,
+                     dist, scale, cap, static_cast<bf16 *>(x));
   NN_TRY(hipGetLastError());
   return LBM_OK;
 }

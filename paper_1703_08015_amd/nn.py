@@ -44,6 +44,8 @@ def _lib():
             "lbm_nn_mix": [I64, P, P, P, P],
             "lbm_nn_mix_backward": [I64, P, I32, P, P, I32, P],
             "lbm_nn_decode_output": [I64, P, P, D, D, I32, P, P, P, P],
+            "lbm_nn_distance": [P, ctypes.c_uint32, P, I32, P, P, P],
+            "lbm_nn_encode_geometry": [I64, P, P, F, F, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -150,6 +152,18 @@ def encode_input(solid, direction, x, stream=None):
     d = (ctypes.c_float * 3)(*[float(v) for v in direction])
     _check(_lib().lbm_nn_encode_input(solid.numel(), _ptr(solid), d, _ptr(x), _stream(stream)),
            "lbm_nn_encode_input")
+
+
+def distance(solid, dist, tmp, sweeps, periodic=7, stream=None):
+    """dist (FP32, shape of solid) = link-path distance to the nearest solid node."""
+    shape = (ctypes.c_int32 * 3)(int(solid.shape[-1]), int(solid.shape[-2]), int(solid.shape[-3]))
+    _check(_lib().lbm_nn_distance(shape, int(periodic), _ptr(solid), int(sweeps), _ptr(dist), _ptr(tmp),
+                                  _stream(stream)), "lbm_nn_distance")
+
+
+def encode_geometry(solid, dist, scale, cap, x, stream=None):
+    _check(_lib().lbm_nn_encode_geometry(solid.numel(), _ptr(solid), _ptr(dist), float(scale), float(cap), _ptr(x),
+                                         _stream(stream)), "lbm_nn_encode_geometry")
 
 
 def decode_output(pred, solid, rho0, scale, rho, u, scratch=None, renorm=True, stream=None):

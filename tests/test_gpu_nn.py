@@ -315,3 +315,30 @@ def test_unet_forward_and_gradients_match_oracle(torch):
         got = host(p.g)
         assert got.shape == wg.shape, k
         close(got, wg, 6e-2)
+
+
+@pytest.mark.parametrize("periodic", [7, 0, 5])
+def test_distance_and_geometry_encoding(torch, periodic):
+    from paper_1703_08015_amd import inputs
+    solid, _ = inputs.spheres_3d((20, 12, 16), 0.55, 2.0, 4.0, seed=11,
+                                 periodic=tuple(bool(periodic >> a & 1) for a in range(3)))
+    solid[0, :3, :3] = True  # a few isolated bits near an edge
+    want = onn.distance(solid, periodic)
+    sd = torch.from_numpy(solid.astype(np.uint8)).cuda()
+    dist = torch.empty(solid.shape, dtype=torch.float32, device="cuda")
+    tmp = torch.empty_like(dist)
+    nn.distance(sd, dist, tmp, sweeps=64, periodic=periodic)
+    got = dist.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(want)
+    assert np.allclose(got[fin], want[fin], rtol=1e-6, atol=1e-6)
+    assert np.all(got[~fin] >= 1e29)
+    # too few sweeps leave far nodes unreached, never below the true distance
+    nn.distance(sd, dist, tmp, sweeps=2, periodic=periodic)
+    few = dist.cpu().numpy().astype(np.float64)
+    assert np.all(few[fin] >= want[fin] - 1e-5) and np.all(few[want <= 2.0] <= want[want <= 2.0] + 1e-5)
+    nn.distance(sd, dist, tmp, sweeps=64, periodic=periodic)
+    x = torch.empty(solid.shape + (8,), dtype=torch.bfloat16, device="cuda")
+    nn.encode_geometry(sd, dist, 0.25, 3.0, x)
+    ref = onn.encode_geometry(solid, np.where(fin, want, 1e30), 0.25, 3.0)
+    close(host(x), bf(ref), rel=1e-2)
+    assert np.all(host(x)[..., 3:] == 0)

@@ -115,3 +115,37 @@ def test_adam_first_step_moves_by_lr_times_sign():
     p0 = rng.normal(size=50)
     p, m, v = nn.adam(p0, np.zeros(50), np.zeros(50), g, lr=1e-3, b1=0.9, b2=0.999, eps=0.0, step=1)
     assert np.allclose(p, p0 - 1e-3 * np.sign(g), rtol=0, atol=1e-15)
+
+
+def _chamfer_closed_form(a, b, c):
+    """Cost of offset (a, b, c) with unit axis steps and sqrt(2) diagonal
+    steps in a plane: each diagonal step replaces two axis steps, and at most
+    min(floor((a+b+c)/2), b+c) of them fit (a >= b >= c >= 0)."""
+    a, b, c = sorted((abs(a), abs(b), abs(c)), reverse=True)
+    k = min((a + b + c) // 2, b + c)
+    return (a + b + c) - (2 - np.sqrt(2)) * k
+
+
+def test_distance_from_one_solid_node_has_the_closed_form():
+    n = 9
+    solid = np.zeros((n, n, n), bool)
+    solid[4, 4, 4] = True
+    d = nn.distance(solid, periodic=0)
+    for z in range(n):
+        for y in range(n):
+            for x in range(n):
+                assert np.isclose(d[z, y, x], _chamfer_closed_form(x - 4, y - 4, z - 4), rtol=0, atol=1e-12)
+    # periodic: the minimum image
+    dp = nn.distance(solid, periodic=7)
+    assert np.isclose(dp[0, 0, 0], _chamfer_closed_form(4, 4, 4))
+    assert np.isclose(dp[8, 0, 4], _chamfer_closed_form(4, 4, 0))
+
+
+def test_distance_is_zero_on_solid_and_one_lipschitz_along_links():
+    solid = rng.random((6, 7, 8)) < 0.1
+    d = nn.distance(solid)
+    assert np.all(d[solid] == 0) and np.all(d[~solid] >= 1)
+    for dx, dy, dz in nn.LINKS:
+        sh = np.roll(d, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
+        assert np.all(np.abs(sh - d) <= np.sqrt(abs(dx) + abs(dy) + abs(dz)) + 1e-12)
+    assert np.all(np.isinf(nn.distance(np.zeros((3, 3, 3), bool))))
