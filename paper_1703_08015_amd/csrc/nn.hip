@@ -69,53 +69,291 @@ __device__ __forceinline__ int64_t dst_voxel(int64_t m, int t, const Grid &rows,
   }
 }
 
-// ---- forward gather-GEMM: 4 wavefronts x 16 rows, NW column fragments ------
-template <int SRC, int DST, int NW, bool F32, bool RELU>
+// ---- forward gather-GEMM ----------------------------------------------------
+// Block: 4 wavefronts x 16*RF rows (RF 16-row fragments each; RF = 1 for
+// grids too small to fill the device otherwise) x 16*NW columns.
+// K runs over the flattened (tap, channel) index k = t*cin + c: cin is a
+// multiple of 8, so each lane's 8-channel group lies inside one tap and
+// gathers its own input row, and no K is padded per tap (the first layer's 8
+// input channels fill whole 32-wide K steps).  Each K step's weight tile
+// (16*NW columns x 32 k) is staged once per block in LDS, double-buffered, and
+// read by all four wavefronts; the gathered input rows of the next K step are
+// loaded while the current step's MFMAs run; a row's voxel coordinates are
+// decoded once.
+constexpr int kLdsK = 40;  // 32 k + 8 bf16 of padding per LDS row
+
+template <int SRC>
+__device__ __forceinline__ int64_t gather_row(int x, int y, int z, int64_t m, int t, const Grid &in) {
+  if constexpr (SRC == LBM_NN_IDENT) {
+    return m;
+  } else if constexpr (SRC == LBM_NN_CONV3) {
+    int sx = x + t % 3 - 1, sy = y + (t / 3) % 3 - 1, sz = z + t / 9 - 1;
+    sx += sx < 0 ? in.nx : (sx >= in.nx ? -in.nx : 0);
+    sy += sy < 0 ? in.ny : (sy >= in.ny ? -in.ny : 0);
+    sz += sz < 0 ? in.nz : (sz >= in.nz ? -in.nz : 0);
+    return vidx(sx, sy, sz, in);
+  } else {  // GATHER2
+    return vidx(2 * x + (t & 1), 2 * y + ((t >> 1) & 1), 2 * z + (t >> 2), in);
+  }
+}
+
+template <int SRC, int DST, int NW, int RF, bool F32, bool RELU>
 __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ __attribute__((aligned(16))) bf16 sb[2][16 * NW][kLdsK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, kb = lane >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * 64 + wv * 16;
+  const int64_t mb = (int64_t)blockIdx.x * (64 * RF) + wv * 16 * RF;
   const int n0 = blockIdx.y * 16 * NW;
   const int tfix = blockIdx.z;  // the tap of a SCATTER2 launch
-  const int64_t m = m0 + r;
-  const bool mv = m < a.M;
-  f32x4 acc[NW];
-#pragma unroll
-  for (int j = 0; j < NW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int ktot = a.taps * a.cin;
-  const int t0 = DST == LBM_NN_SCATTER2 ? tfix : 0;
-  const int t1 = DST == LBM_NN_SCATTER2 ? tfix + 1 : a.taps;
-  for (int t = t0; t < t1; ++t) {
-    const bf16 *xrow = a.x + (mv ? src_voxel<SRC>(m, t, a.rows, a.in_grid) : 0) * a.ldx;
-    for (int c0 = 0; c0 < a.cin; c0 += 32) {
-      const int c = c0 + 8 * kb;
-      bf16x8 av = {};
-      if (mv && c < a.cin) av = *reinterpret_cast<const bf16x8 *>(xrow + c);
+  const int kbeg = DST == LBM_NN_SCATTER2 ? tfix * a.cin : 0;
+  const int kend = DST == LBM_NN_SCATTER2 ? kbeg + a.cin : ktot;
+
+  int64_t m[RF];
+  bool mv[RF];
+  int px[RF], py[RF], pz[RF];
 #pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const int n = n0 + 16 * j + r;
-        bf16x8 bv = {};
-        if (n < a.cout && c < a.cin) bv = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)n * ktot + t * a.cin + c);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+  for (int f = 0; f < RF; ++f) {
+    m[f] = mb + 16 * f + r;
+    mv[f] = m[f] < a.M;
+    px[f] = py[f] = pz[f] = 0;
+    if constexpr (SRC != LBM_NN_IDENT) {
+      const int mm = mv[f] ? (int)m[f] : 0;
+      px[f] = mm % a.rows.nx;
+      py[f] = (mm / a.rows.nx) % a.rows.ny;
+      pz[f] = mm / (a.rows.nx * a.rows.ny);
+    }
+  }
+
+  // weight staging: thread -> (column, 8-wide k group)
+  const int scol = tid >> 2, sk = 8 * (tid & 3);
+  auto stage = [&](int buf, int k0) {
+    if (scol < 16 * NW) {
+      const int n = n0 + scol, k = k0 + sk;
+      bf16x8 v = {};
+      if (n < a.cout && k < kend) v = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)n * ktot + k);
+      *reinterpret_cast<bf16x8 *>(&sb[buf][scol][sk]) = v;
+    }
+  };
+
+  // this lane's k group kk = k0 + 8*kb as (tap t, channel c); each load
+  // advances it by one 32-wide K step (zeros past the end)
+  int kk = kbeg + 8 * kb;
+  int t = kk / a.cin, c = kk - t * a.cin;
+  auto load_rows = [&](bf16x8(&dst)[RF]) {
+#pragma unroll
+    for (int f = 0; f < RF; ++f) {
+      dst[f] = bf16x8{};
+      if (mv[f] && kk < kend)
+        dst[f] = *reinterpret_cast<const bf16x8 *>(a.x + gather_row<SRC>(px[f], py[f], pz[f], m[f], t, a.in_grid) *
+                                                             a.ldx + c);
+    }
+    kk += 32;
+    c += 32;
+    while (c >= a.cin) {
+      c -= a.cin;
+      ++t;
+    }
+  };
+
+  f32x4 acc[RF][NW];
+#pragma unroll
+  for (int f = 0; f < RF; ++f)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  bf16x8 cur[RF];
+  load_rows(cur);
+  stage(0, kbeg);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    if (k0 + 32 < kend) stage(buf ^ 1, k0 + 32);
+    bf16x8 nxt[RF];
+    load_rows(nxt);
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sb[buf][16 * j + r][8 * kb]);
+#pragma unroll
+      for (int f = 0; f < RF; ++f) acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[f], bv, acc[f][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int f = 0; f < RF; ++f) cur[f] = nxt[f];
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int f = 0; f < RF; ++f) {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int n = n0 + 16 * j + r;
+      if (n >= a.cout) continue;
+      const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t mo = mb + 16 * f + 4 * kb + i;
+        if (mo >= a.M) continue;
+        float v = acc[f][j][i] + bias;
+        if (RELU) v = fmaxf(v, 0.f);
+        const int64_t d = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid) * a.ldy + n;
+        if (F32)
+          static_cast<float *>(a.y)[d] = v;
+        else
+          static_cast<bf16 *>(a.y)[d] = (bf16)v;
       }
     }
   }
+}
+
+// ---- CONV3 forward on spatial bricks -----------------------------------------
+// A block owns an 8x8x4 brick of output voxels and 16*NW output channels; for
+// each chunk of CC input channels it stages the brick's 10x10x6 input halo
+// (periodic wrap) in LDS once, and all 27 taps read their A fragments from
+// there, so each input row is fetched about 2.3 times per block instead of 27.
+// Wavefront w owns the z-plane w of the brick; its fragment f covers rows
+// y = 2f, 2f+1 (x = 0..7).  The tap loop is unrolled, so a tap's halo offset
+// is an immediate of the LDS read; each tap's CC channels are padded to whole
+// 32-wide K steps with zeros staged in LDS (CC = 8 packs four taps into one K
+// step instead).  Weight rows are read straight from global memory at clamped
+// addresses: padded K lanes meet zero A values, and columns past cout are never
+// stored.
+constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = 4;
+constexpr int kHaloX = kBrickX + 2, kHaloY = kBrickY + 2, kHaloZ = kBrickZ + 2;
+constexpr int kHalo = kHaloX * kHaloY * kHaloZ;
+
+template <int CC>
+struct BrickShape {
+  static constexpr int KS = CC == 8 ? 1 : (CC + 31) / 32;  // K steps per tap
+  static constexpr int width = CC == 8 ? 8 : 32 * KS;       // channels read per halo row
+  static constexpr int CP = width + 8 + ((width / 8 + 1) % 2 == 0 ? 8 : 0);  // odd number of 16-byte units
+};
+
+constexpr int tap_offset(int t) { return (t % 3) + kHaloX * (((t / 3) % 3) + kHaloY * (t / 9)); }
+
+template <int NW, int CC, bool RELU>
+__global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
+  using BS = BrickShape<CC>;
+  constexpr int CP = BS::CP;
+  __shared__ __attribute__((aligned(16))) bf16 halo[kHalo * CP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, kb = lane >> 4;
+  const Grid g = a.rows;  // CONV3: output grid == input grid
+  const int bxn = (g.nx + kBrickX - 1) / kBrickX, byn = (g.ny + kBrickY - 1) / kBrickY;
+  const int bid = blockIdx.x;
+  const int ox = (bid % bxn) * kBrickX, oy = ((bid / bxn) % byn) * kBrickY, oz = (bid / (bxn * byn)) * kBrickZ;
+  const int n0 = blockIdx.y * 16 * NW;
+  const int ktot = 27 * a.cin;
+
+  // per-lane LDS element offsets of the four fragments' rows at tap (0,0,0)
+  int rowbase[4];
 #pragma unroll
-  for (int j = 0; j < NW; ++j) {
-    const int n = n0 + 16 * j + r;
-    if (n >= a.cout) continue;
-    const float b = a.bias ? a.bias[n] : 0.f;
+  for (int f = 0; f < 4; ++f) rowbase[f] = ((r & 7) + kHaloX * ((2 * f + (r >> 3)) + kHaloY * wv)) * CP;
+  // per-lane weight rows (clamped to a valid output channel)
+  const bf16 *wrow[NW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t mo = m0 + 4 * kb + i;
-      if (mo >= a.M) continue;
-      float v = acc[j][i] + b;
-      if (RELU) v = fmaxf(v, 0.f);
-      const int64_t d = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid) * a.ldy + n;
-      if (F32)
-        static_cast<float *>(a.y)[d] = v;
-      else
-        static_cast<bf16 *>(a.y)[d] = (bf16)v;
+  for (int j = 0; j < NW; ++j) wrow[j] = a.w + (int64_t)min(n0 + 16 * j + r, a.cout - 1) * ktot;
+
+  f32x4 acc[4][NW];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int G = BS::width / 8;                 // 16-byte groups per halo row that are read
+  constexpr int NST = (kHalo * G + 255) / 256;     // staging loads per thread
+  // input row of each of this thread's staging entries (the same for every chunk)
+  int64_t srow[NST];
+#pragma unroll
+  for (int it = 0; it < NST; ++it) {
+    const int e = tid + 256 * it;
+    const int hv = e / G;
+    const int hx = hv % kHaloX, hy = (hv / kHaloX) % kHaloY, hz = hv / (kHaloX * kHaloY);
+    int gx = (ox + hx - 1) % g.nx, gy = (oy + hy - 1) % g.ny, gz = (oz + hz - 1) % g.nz;
+    gx += gx < 0 ? g.nx : 0;
+    gy += gy < 0 ? g.ny : 0;
+    gz += gz < 0 ? g.nz : 0;
+    srow[it] = vidx(gx, gy, gz, g) * a.ldx;
+  }
+  for (int c0 = 0; c0 < a.cin; c0 += CC) {
+    // issue every staging load of the chunk before the first LDS store
+    bf16x8 v[NST];
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+      const int e = tid + 256 * it;
+      const int q = e % G;
+      v[it] = bf16x8{};
+      if (e < kHalo * G && 8 * q < CC) v[it] = *reinterpret_cast<const bf16x8 *>(a.x + srow[it] + c0 + 8 * q);
+    }
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+      const int e = tid + 256 * it;
+      if (e < kHalo * G) *reinterpret_cast<bf16x8 *>(&halo[(e / G) * CP + 8 * (e % G)]) = v[it];  // zeros past CC
+    }
+    __syncthreads();
+    if constexpr (CC == 8) {
+      // four taps per K step: lane group kb takes tap 4s + kb (tap 27 is padding)
+      static_for<7>([&](auto S) {
+        constexpr int s0 = 4 * decltype(S)::value;
+        const int t = s0 + kb;
+        const int off = kb == 0 ? tap_offset(s0) : kb == 1 ? tap_offset(s0 + 1)
+                      : kb == 2 ? tap_offset(s0 + 2) : tap_offset(s0 + 3 < 27 ? s0 + 3 : 26);
+        const bool tv = t < 27;
+        bf16x8 bv[NW];
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+          bv[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (tv ? t : 26) * a.cin + c0);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off * CP]);
+          if (!tv) av = bf16x8{};
+#pragma unroll
+          for (int j = 0; j < NW; ++j)
+            acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
+        }
+      });
+    } else {
+      int cb[BS::KS];  // weight channel of this lane's k group, clamped into the tap
+#pragma unroll
+      for (int st = 0; st < BS::KS; ++st) cb[st] = min(32 * st + 8 * kb, CC - 8);
+      static_for<27>([&](auto T) {
+        constexpr int t = decltype(T)::value;
+        constexpr int off = tap_offset(t) * CP;
+        const int64_t wt = (int64_t)t * a.cin + c0;
+#pragma unroll
+        for (int st = 0; st < BS::KS; ++st) {
+          bf16x8 bv[NW];
+#pragma unroll
+          for (int j = 0; j < NW; ++j) bv[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + wt + cb[st]);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off + 32 * st + 8 * kb]);
+#pragma unroll
+            for (int j = 0; j < NW; ++j)
+              acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
+          }
+        }
+      });
+    }
+  }
+
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int n = n0 + 16 * j + r;
+      if (n >= a.cout) continue;
+      const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 4 * kb + i;  // row of the fragment
+        const int x = ox + (q & 7), y = oy + 2 * f + (q >> 3), z = oz + wv;
+        if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+        float v = acc[f][j][i] + bias;
+        if (RELU) v = fmaxf(v, 0.f);
+        static_cast<bf16 *>(a.y)[vidx(x, y, z, g) * a.ldy + n] = (bf16)v;
+      }
     }
   }
 }
@@ -478,6 +716,8 @@ int check_gemm(const lbm_nn_gemm *g, bool wgrad) {
   if (!g || !g->x || !g->y || (!wgrad && !g->w)) return set_error(LBM_ERR_ARG, "lbm_nn: NULL tensor");
   for (int k = 0; k < 3; ++k)
     if (g->rows[k] <= 0) return set_error(LBM_ERR_SHAPE, "lbm_nn: rows[%d] = %d", k, g->rows[k]);
+  if ((int64_t)g->rows[0] * g->rows[1] * g->rows[2] > INT32_MAX)
+    return set_error(LBM_ERR_SHAPE, "lbm_nn: more than 2^31 - 1 rows");
   const bool src_ok = g->src_mode == LBM_NN_IDENT || g->src_mode == LBM_NN_CONV3 || g->src_mode == LBM_NN_GATHER2;
   const bool dst_ok = g->dst_mode == LBM_NN_IDENT || g->dst_mode == LBM_NN_SCATTER2;
   if (!src_ok || !dst_ok) return set_error(LBM_ERR_ARG, "lbm_nn: modes %d/%d", g->src_mode, g->dst_mode);
@@ -500,22 +740,82 @@ int check_gemm(const lbm_nn_gemm *g, bool wgrad) {
     if (e_ != hipSuccess) return set_error(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
   } while (0)
 
-template <int SRC, int DST, bool F32, bool RELU>
-hipError_t launch_fwd(const GemmArgs &a, int scatter_taps, hipStream_t s) {
-  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
-  const unsigned gx = (unsigned)((a.M + 63) / 64), gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
-  const dim3 grid(gx, gy, scatter_taps);
+template <int SRC, int DST, int RF, bool F32, bool RELU>
+hipError_t launch_fwd_rf(const GemmArgs &a, int nw, dim3 grid, hipStream_t s) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((k_forward<SRC, DST, 1, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_forward<SRC, DST, 2, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_forward<SRC, DST, 3, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_forward<SRC, DST, 4, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_forward<SRC, DST, 1, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_forward<SRC, DST, 2, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_forward<SRC, DST, 3, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_forward<SRC, DST, 4, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
 }
 
+template <int SRC, int DST, bool F32, bool RELU>
+hipError_t launch_fwd(const GemmArgs &a, int scatter_taps, hipStream_t s) {
+  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
+  const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
+  // 256 rows per block where that still gives the device >= 512 blocks, else 64
+  const int64_t big = (a.M + 255) / 256 * gy * scatter_taps;
+  if (big >= 512)
+    return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy, scatter_taps), s);
+  return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy, scatter_taps), s);
+}
+
+template <int NW, int CC>
+hipError_t launch_brick_cc(const GemmArgs &a, bool relu, dim3 grid, hipStream_t s) {
+  if (relu)
+    hipLaunchKernelGGL((k_conv3_brick<NW, CC, true>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_conv3_brick<NW, CC, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_brick_nw(const GemmArgs &a, int cc, bool relu, dim3 grid, hipStream_t s) {
+  switch (cc) {
+    case 8: return launch_brick_cc<NW, 8>(a, relu, grid, s);
+    case 24: return launch_brick_cc<NW, 24>(a, relu, grid, s);
+    default: return launch_brick_cc<NW, 32>(a, relu, grid, s);
+  }
+}
+
+// The brick kernel for a 3x3x3 convolution with BF16 output: channel chunks of
+// 8 (an 8-channel input), 24 (24 or 48 channels: a 48-wide chunk would need
+// 86 KB of LDS and leave one block per CU) or 32 (multiples of 32), and enough
+// bricks to fill the device; returns false to use k_forward instead.
+bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t *err) {
+  if (f32) return false;
+  int cc;
+  if (a.cin == 8)
+    cc = 8;
+  else if (a.cin == 24 || a.cin == 48)
+    cc = 24;
+  else if (a.cin % 32 == 0)
+    cc = 32;
+  else
+    return false;
+  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
+  const int64_t bricks = (int64_t)((a.rows.nx + kBrickX - 1) / kBrickX) * ((a.rows.ny + kBrickY - 1) / kBrickY) *
+                         ((a.rows.nz + kBrickZ - 1) / kBrickZ);
+  const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
+  if (bricks * gy < 256) return false;
+  const dim3 grid((unsigned)bricks, gy, 1);
+  switch (nw) {
+    case 1: *err = launch_brick_nw<1>(a, cc, relu, grid, s); break;
+    case 2: *err = launch_brick_nw<2>(a, cc, relu, grid, s); break;
+    case 3: *err = launch_brick_nw<3>(a, cc, relu, grid, s); break;
+    default: *err = launch_brick_nw<4>(a, cc, relu, grid, s); break;
+  }
+  return true;
+}
+
 template <int SRC, int DST>
 hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, int st, hipStream_t s) {
+  if constexpr (SRC == LBM_NN_CONV3 && DST == LBM_NN_IDENT) {
+    hipError_t e = hipSuccess;
+    if (try_brick(a, f32, relu, s, &e)) return e;
+  }
   if (f32) return relu ? launch_fwd<SRC, DST, true, true>(a, st, s) : launch_fwd<SRC, DST, true, false>(a, st, s);
   return relu ? launch_fwd<SRC, DST, false, true>(a, st, s) : launch_fwd<SRC, DST, false, false>(a, st, s);
 }

@@ -75,6 +75,34 @@ def test_conv3_forward_backward(torch, cin, cout, relu):
     close(host(db), gb, 2e-5)
 
 
+@pytest.mark.parametrize("grid,cin,cout,relu", [
+    ((34, 36, 68), 24, 24, True),   # partial 8x8x4 bricks on every axis
+    ((32, 32, 64), 8, 24, False),   # the first layer: 8 input channels
+    ((32, 32, 64), 48, 24, True),   # decoder: concatenated skip and upsampled halves
+    ((16, 32, 64), 64, 96, True),   # two 32-channel chunks, three 32-column groups
+])
+def test_conv3_brick_kernel(torch, grid, cin, cout, relu):
+    """Grids with at least 256 8x8x4 bricks run the LDS-halo kernel; the data
+    gradient through the flipped weights takes the same path."""
+    x = bf(rng.normal(size=grid + (cin,)))
+    w = bf(rng.normal(size=(cout, 27, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    y = torch.empty(grid + (cout,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, dev(torch, x), cin, dev(torch, w), y, cout,
+               bias=dev(torch, b, torch.float32), relu=relu)
+    want = onn.conv3(x, w, b)
+    if relu:
+        want = onn.relu(want)
+    close(host(y), want)
+    dy = bf(rng.normal(size=grid + (cout,)))
+    wt = torch.empty((cin, 27, cout), dtype=torch.bfloat16, device="cuda")
+    nn.backward_weights(nn.CONV3, 27, cin, cout, dev(torch, w), wt)
+    dx = torch.empty(grid + (cin,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.CONV3, nn.IDENT, rows_of(grid), 27, cout, cin, dev(torch, dy), cout, wt, dx, cin)
+    gx, _, _ = onn.conv3_backward(x, w, dy)
+    close(host(dx), gx)
+
+
 def test_conv3_wgrad_large_grid_split(torch):
     """Voxel counts far above one workgroup's chunk exercise the split reduction."""
     g = (24, 20, 16)
