@@ -81,7 +81,7 @@ def _cpu_model():
 
 def cpu_baseline(mask, args):
     """The FP64 oracle on the same geometry: all host cores for a bounded
-    number of steps (about 10-20 s of CPU work at the default 64), and one
+    number of steps (about 10-30 s of CPU work at the default 160), and one
     thread for a few steps."""
     from oracle import dense
     dense.build()
@@ -388,7 +388,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "scalar"])
     ap.add_argument("--store", default="auto", choices=["auto", "regular", "nontemporal"])
     ap.add_argument("--f16-scale-log2", type=int, default=22)
-    ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
     ap.add_argument("--epochs", type=int, default=30)
