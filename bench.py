@@ -344,10 +344,12 @@ def mode_warmstart(args, torch, lbm):
         tests.append(warmstart.Sample(torch, m, (1e-6 * d).tolist()))
     rows = []
     for k, sm in enumerate(tests):
-        r = warmstart.evaluate(torch, net, [sm], args.tau)[0]
-        print("[eval] sample %d cold %d steps %.2fs warm %d steps %.2fs pred err %.3f agree %.1e%s"
-              % (k, r["cold_steps"], r["cold_s"], r["warm_steps"], r["warm_s"], r["prediction_u_rel_l2"],
-                 r["warm_vs_cold_u_rel_l2"], " (fell back)" if r["fell_back"] else ""), file=sys.stderr, flush=True)
+        r = warmstart.evaluate(torch, net, [sm], args.tau, fp64_cold=True)[0]
+        print("[eval] sample %d cold f64 %d steps %.2fs, cold %d steps %.2fs, warm %d steps %.2fs, pred err %.3f, "
+              "agree %.1e (vs f64 %.1e)%s"
+              % (k, r["cold_f64_steps"], r["cold_f64_s"], r["cold_steps"], r["cold_s"], r["warm_steps"], r["warm_s"],
+                 r["prediction_u_rel_l2"], r["warm_vs_cold_u_rel_l2"], r["warm_vs_cold_f64_u_rel_l2"],
+                 " (fell back)" if r["fell_back"] else ""), file=sys.stderr, flush=True)
         rows.append(r)
     cold_s = sum(r["cold_s"] for r in rows)
     warm_s = sum(r["warm_s"] for r in rows)
@@ -361,6 +363,9 @@ def mode_warmstart(args, torch, lbm):
                                    (len(specs), args.epochs, args.lr)},
             "cold_seconds": round(cold_s, 3), "warm_seconds_incl_inference": round(warm_s, 3),
             "speedup": round(cold_s / warm_s, 3) if warm_s > 0 else None,
+            "cold_f64_seconds": round(sum(r["cold_f64_s"] for r in rows), 3),
+            "speedup_vs_cold_f64": round(sum(r["cold_f64_s"] for r in rows) / warm_s, 3) if warm_s > 0 else None,
+            "warm_vs_cold_f64_u_rel_l2_max": float(np.max([r["warm_vs_cold_f64_u_rel_l2"] for r in rows])),
             "labels_seconds": round(sum(r["labels_s"] for r in rows), 3),
             "cold_steps_mean": float(np.mean([r["cold_steps"] for r in rows])),
             "warm_steps_mean": float(np.mean([r["warm_steps"] for r in rows])),

@@ -208,12 +208,17 @@ def solve(torch, sample, tau, init=None, storage="f32", tol=1e-6, check_every=10
     return taken if steps[0] > 0 else -1, wall, u, fell_back
 
 
-def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100, project=True):
+def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100, project=True, fp64_cold=False):
     """Warm vs cold time to steady state for each geometry (project=False
-    starts from the raw prediction, for comparison)."""
+    starts from the raw prediction, for comparison; fp64_cold also times the
+    plain FP64 solver from rest and checks the warm answer against it)."""
     rows = []
     for sm in samples:
         cold_steps, cold_s, u_cold, _ = solve(torch, sm, tau, None, storage, tol, check_every)
+        extra = {}
+        if fp64_cold:
+            s64, t64, u64, _ = solve(torch, sm, tau, None, "f64", tol, check_every)
+            extra = dict(cold_f64_steps=s64, cold_f64_s=t64, u64=u64)
         # component labels are geometry preprocessing (host), like the tiling
         # that neither path times
         t_lab = time.perf_counter()
@@ -229,7 +234,13 @@ def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100,
         pred_err = float(((init[1][:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
         warm_steps, warm_s, u_warm, fb = solve(torch, sm, tau, init, storage, tol, check_every)
         agree = float(((u_warm[:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
-        rows.append(dict(cold_steps=cold_steps, cold_s=cold_s, warm_steps=warm_steps, warm_s=warm_s + t_inf,
-                         inference_s=t_inf, labels_s=t_lab, prediction_u_rel_l2=pred_err,
-                         warm_vs_cold_u_rel_l2=agree, fell_back=fb))
+        row = dict(cold_steps=cold_steps, cold_s=cold_s, warm_steps=warm_steps, warm_s=warm_s + t_inf,
+                   inference_s=t_inf, labels_s=t_lab, prediction_u_rel_l2=pred_err, warm_vs_cold_u_rel_l2=agree,
+                   fell_back=fb)
+        if extra:
+            u64 = extra.pop("u64")
+            row.update(extra)
+            row["warm_vs_cold_f64_u_rel_l2"] = float(((u_warm[:, fl] - u64[:, fl]) ** 2).sum().sqrt() /
+                                                     (u64[:, fl] ** 2).sum().sqrt())
+        rows.append(row)
     return rows

@@ -62,3 +62,28 @@ def test_blown_up_prediction_falls_back_to_cold(torch, trained):
     u = torch.zeros((3,) + sm.shape, dtype=torch.float64, device="cuda")
     steps, _, u_out, fell_back = warmstart.solve(torch, sm, 0.8, init=(rho, u))
     assert fell_back and steps > 0 and torch.isfinite(u_out).all()
+
+
+def test_warm_start_matches_the_fp64_oracle_steady_state(torch, trained):
+    """The FP32 warm-started solve ends within 1e-3 (velocity rel-L2) of the
+    FP64 CPU oracle's steady state of the same geometry and force."""
+    from oracle import dense
+    net, data, _ = trained
+    for sm in data[:2]:
+        init = warmstart.predict_fields(torch, net, sm, 0.8)
+        steps, _, u_warm, fell_back = warmstart.solve(torch, sm, 0.8, init=init)
+        assert steps > 0 and not fell_back
+        mask = sm.solid.cpu().numpy().astype(bool)
+        f = dense.init(19, mask)
+        prev = None
+        for _ in range(300):
+            f = dense.step(19, mask, f, 0.8, sm.g, 100, nthreads=4)
+            _, u_ref = dense.moments(19, mask, f, sm.g)
+            if prev is not None and np.linalg.norm(u_ref - prev) < 1e-10 * np.linalg.norm(u_ref):
+                break
+            prev = u_ref
+        u = u_warm.cpu().numpy()
+        fl = ~mask
+        err = np.linalg.norm(u[:, fl] - u_ref[:, fl]) / np.linalg.norm(u_ref[:, fl])
+        print("warm FP32 vs FP64 oracle", err, flush=True)
+        assert err <= 1e-3
