@@ -486,6 +486,7 @@ def main():
             "workload": desc,
             "n_fluid": nf, "n_ftiles": info["n_ftiles"], "n_tiles": info["n_tiles"],
             "phi": round(info["phi"], 4), "phi_t": round(info["phi_t"], 4),
+            "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * 19 * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
         },

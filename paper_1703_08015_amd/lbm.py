@@ -269,7 +269,10 @@ class Solver:
 
     def __init__(self, tiles, lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
                  tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", persistent=0,
-                 graph_steps=0, device="cuda", stream=None):
+                 graph_steps=0, device="cuda", stream=None, workspace=None):
+        """workspace: optional caller-owned device tensor (uint8, at least
+        workspace_bytes(tiles, ...) long, 256-byte aligned); by default the
+        solver allocates its own."""
         import torch
 
         self.torch = torch
@@ -281,7 +284,12 @@ class Solver:
         n = ctypes.c_size_t()
         _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(self.params), ctypes.byref(n)),
                "lbm_workspace_bytes")
-        self.workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            self.workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
+        else:
+            if workspace.dtype != torch.uint8 or workspace.numel() < n.value or not workspace.is_contiguous():
+                raise ValueError("workspace must be contiguous uint8 of at least %d bytes" % n.value)
+            self.workspace = workspace
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._h = ctypes.c_void_p()
         _check(lib().lbm_create(tiles._h, ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()),

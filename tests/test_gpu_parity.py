@@ -259,3 +259,55 @@ def test_offset_storage_error_vs_fp64(torch, storage, tol, kernel):
     err = np.linalg.norm((v - uw)[:, fl]) / np.linalg.norm(uw[:, fl])
     _log("offset storage", storage, "velocity rel-L2 error after 1000 steps:", err)
     assert err <= tol
+
+
+@pytest.mark.parametrize("storage,kernel", [("f64", "scalar"), ("f32", "scalar"), ("f16", "scalar"),
+                                            ("f64", "generic")])
+def test_step_writes_every_fluid_entry(torch, storage, kernel):
+    """The whole workspace starts as 0xFF bytes (NaN in FP64, FP32 and FP16):
+    init must write every non-solid entry of one copy and each step every
+    non-solid entry of the other, and nothing may rely on zeroed scratch."""
+    mask = inputs.spheres_3d(24, 0.45, rmin=2, rmax=5, seed=21)[0]
+    t = _tiles(mask, 19)
+    kw = dict(lattice=19, storage=storage, tau=0.8, g=(1e-6, 0, 0), step_kernel=kernel, f16_scale_log2=20)
+    n = lbm.workspace_bytes(t, **kw)
+    ws = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
+    s = lbm.Solver(t, workspace=ws, **kw)
+    s.init()
+    fl = torch.from_numpy(~mask).cuda()
+    for _ in range(3):
+        f = s.pdfs_export()
+        assert bool(torch.isfinite(f[:, fl]).all()), "an entry was never written"
+        s.step(1)
+    assert np.all(np.isfinite(s.reduce()))
+
+
+def test_batch_persistent_graph_writes_every_fluid_entry(torch):
+    parts = [_tiles(inputs.spheres_3d(n, 0.5, rmin=2, rmax=4, seed=30 + n)[0], 19) for n in (16, 20)]
+    t = lbm.Tiles.concat(parts)
+    kw = dict(lattice=19, storage="f32", tau=0.8, persistent=1, graph_steps=3)
+    n = lbm.workspace_bytes(t, **kw)
+    ws = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
+    s = lbm.Solver(t, workspace=ws, **kw)
+    s.set_sample_force(np.array([[1e-6, 0, 0], [0, 1e-6, 0]]))
+    s.init()
+    s.step(7)
+    tot = s.reduce()
+    assert np.all(np.isfinite(tot)) and tot.shape == (2, 4)
+
+
+def test_nonfinite_state_is_reported(torch):
+    mask = inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=22)[0]
+    t = _tiles(mask, 19)
+    s = lbm.Solver(t, lattice=19, tau=0.8, g=(1e-6, 0, 0))
+    s.init()
+    f = s.pdfs_export().clone()
+    z, y, x = [int(v[0]) for v in np.nonzero(~mask)]
+    f[3, z, y, x] = float("nan")
+    s.pdfs_import(f)
+    for call in (s.reduce, s.residual):
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert e.value.code == lbm.LBM_ERR_NONFINITE
+    s.init()  # a fresh start clears the state
+    assert np.all(np.isfinite(s.reduce()))
