@@ -37,6 +37,29 @@ struct D3Q19 {
   static constexpr int Opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 };
 
+// Lane regions of the scalar-mask D3Q19 step (4x4x4 tiles): for direction i
+// (1..18) region w = 0 holds the lanes whose source x - c_i lies in the tile
+// itself, region w = 1..7 those whose source wraps across the axes flagged by
+// the bits of w (only axes with c_a != 0).  The planner stores, per tile, the
+// base entry index of every (i, w) region in this order; the kernel adds the
+// source's rank.  60 regions, padded to 64.
+constexpr int kRegionBases = 64;
+
+constexpr bool region_valid(int i, int w) {
+  const int cx = D3Q19::C[i][0], cy = D3Q19::C[i][1], cz = D3Q19::C[i][2];
+  return w == 0 || ((!(w & 1) || cx) && (!((w >> 1) & 1) || cy) && (!((w >> 2) & 1) || cz));
+}
+
+constexpr int region_index(int i, int w) {
+  int n = 0;
+  for (int a = 1; a < 19; ++a)
+    for (int b = 0; b < 8; ++b) {
+      if (a == i && b == w) return n;
+      if (region_valid(a, b)) ++n;
+    }
+  return -1;
+}
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
 template <class F, int... I>
 __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {

@@ -31,11 +31,13 @@ hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileA
 bool step19_supported(const Variant &v);
 // nrec: n_ftiles + 1 records (the last one all-solid); nrow: 20 per tile, the
 // byte offsets into nrec of the 18 neighbour slots of the D3Q19 gather in
-// kernel order (+2 padding).
+// kernel order (+2 padding); rbase: kRegionBases per tile, the base entry
+// index of every lane region (device.h).
 // mode 0: wavefront w -> tile w; 1: -> list[w] for w < *count; 2: persistent
 // grid of blocks_persistent workgroups striding over list[0 .. *count).
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const uint32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef, bool nontemporal,
+                         const int32_t *list,
                          const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s);
 hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,

@@ -24,8 +24,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every workspace array, plus the host tables to upload.
 struct Plan {
-  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, list, count, part, chunk, out, uref,
-      total;
+  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, rbase, list, count, part, chunk, out,
+      uref, total;
   int64_t entries = 0;  // PDF entries per copy (with region alignment padding)
   // device tables in the solver's internal tile order
   std::vector<lbm::TileRec> rec_h;
@@ -36,7 +36,8 @@ struct Plan {
   std::vector<lbm::CollideCoef> coef_h;
   // scalar-mask D3Q19 kernel: compact records (+ all-solid sentinel) and rows
   std::vector<lbm::NbRec> nrec_h;
-  std::vector<uint32_t> nrow_h;  // byte offsets into nrec
+  std::vector<uint32_t> nrow_h;   // byte offsets into nrec
+  std::vector<uint32_t> rbase_h;  // kRegionBases per tile: base entry of each lane region
 };
 
 // Neighbour slots (3x3x3 index) of the D3Q19 gather, in the order the
@@ -169,6 +170,35 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
         }
       }
       P.nrec_h[(size_t)nft] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
+      // region bases: off + i*n of the region's source tile, plus the fluid
+      // nodes that the shift to the destination lanes moves out below lane 0
+      // (the kernel adds v_mbcnt of the shifted mask); 0 for a missing source.
+      // Only the FP16 form reads them: it is bound by scalar issue, while for
+      // FP32 and FP64 the 256 extra bytes per tile cost more than the scalar
+      // work they save.
+      if (p->storage == LBM_F16_OFFSET) P.rbase_h.assign((size_t)(nft * lbm::kRegionBases), 0u);
+      for (int64_t k = 0; k < nft && !P.rbase_h.empty(); ++k) {
+        uint32_t *rb = &P.rbase_h[(size_t)(k * lbm::kRegionBases)];
+        for (int i = 1; i < 19; ++i) {
+          const int cx = lbm::D3Q19::C[i][0], cy = lbm::D3Q19::C[i][1], cz = lbm::D3Q19::C[i][2];
+          const int d0 = cx + 4 * cy + 16 * cz;
+          for (int w = 0; w < 8; ++w) {
+            if (!lbm::region_valid(i, w)) continue;
+            const int wx = w & 1, wy = (w >> 1) & 1, wz = (w >> 2) & 1;
+            const int dr = d0 - (wx ? 4 * cx : 0) - (wy ? 16 * cy : 0) - (wz ? 64 * cz : 0);
+            const lbm::NbRec *r = &P.nrec_h[(size_t)k];
+            if (w != 0) {
+              const int slot = 13 + (wx ? -cx : 0) + 3 * (wy ? -cy : 0) + 9 * (wz ? -cz : 0);
+              int j = 0;
+              while (kGatherSlots[j] != slot) ++j;
+              r = &P.nrec_h[P.nrow_h[(size_t)(k * 20 + j)] / sizeof(lbm::NbRec)];
+            }
+            const uint32_t dropped =
+                dr >= 0 ? 0u : (uint32_t)__builtin_popcountll(r->mask & ((1ull << (-dr)) - 1ull));
+            rb[lbm::region_index(i, w)] = r->off + (uint32_t)i * r->n + dropped;
+          }
+        }
+      }
     }
     P.samples_h.resize(t->samples.size());
     P.coef_h.resize(t->samples.size());
@@ -210,6 +240,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.coef = take(t->samples.size() * sizeof(lbm::CollideCoef));
   P.nrec = take(P.nrec_h.size() * sizeof(lbm::NbRec));
   P.nrow = take(P.nrow_h.size() * sizeof(uint32_t));
+  P.rbase = take(P.rbase_h.size() * sizeof(uint32_t));
   P.list = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
   P.count = take(sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
@@ -241,6 +272,7 @@ struct lbm_solver {
   lbm::CollideCoef *coef_d = nullptr;
   const lbm::NbRec *nrec_d = nullptr;
   const uint32_t *nrow_d = nullptr;
+  const uint32_t *rbase_d = nullptr;
   // active tile list (batches) and the launch mode of the scalar-mask step
   int32_t *list_d = nullptr, *count_d = nullptr;
   std::vector<int32_t> list_h;
@@ -329,6 +361,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->coef_d = reinterpret_cast<lbm::CollideCoef *>(base + P.coef);
   s->nrec_d = reinterpret_cast<const lbm::NbRec *>(base + P.nrec);
   s->nrow_d = reinterpret_cast<const uint32_t *>(base + P.nrow);
+  s->rbase_d = reinterpret_cast<const uint32_t *>(base + P.rbase);
   s->list_d = reinterpret_cast<int32_t *>(base + P.list);
   s->count_d = reinterpret_cast<int32_t *>(base + P.count);
   s->storage_bytes = lbm::storage_bytes(v.storage);
@@ -397,6 +430,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if (e == hipSuccess) e = up(P.coef, P.coef_h.data(), P.coef_h.size() * sizeof(lbm::CollideCoef));
   if (e == hipSuccess) e = up(P.nrec, P.nrec_h.data(), P.nrec_h.size() * sizeof(lbm::NbRec));
   if (e == hipSuccess) e = up(P.nrow, P.nrow_h.data(), P.nrow_h.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = up(P.rbase, P.rbase_h.data(), P.rbase_h.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = up(P.list, s->list_h.data(), s->list_h.size() * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.count, &s->count_h, sizeof(int32_t));
   if (e == hipSuccess && s->scalar_mask && p->persistent) e = lbm::step19_persistent_blocks(v, &s->persistent_blocks);
@@ -496,7 +530,8 @@ extern "C" int lbm_init(lbm_solver *s, const double *rho, const double *u) {
 static hipError_t enqueue_step(lbm_solver *s, int from, hipStream_t st) {
   if (s->scalar_mask) {
     const int mode = s->p.persistent ? 2 : (s->all_active ? 0 : 1);
-    return lbm::launch_step19(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d, s->coef_d,
+    return lbm::launch_step19(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d, s->rbase_d,
+                              s->coef_d,
                               s->p.store_policy != LBM_STORE_REGULAR, s->list_d, s->count_d, mode,
                               s->persistent_blocks, st);
   }

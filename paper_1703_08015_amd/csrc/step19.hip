@@ -87,7 +87,8 @@ constexpr int slot_of(int k) {
 template <int S, bool NT>
 __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict__ src_, void *__restrict__ dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
-                                            const uint32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef) {
+                                            const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
+                                            const CollideCoef *__restrict__ coef) {
   using L = D3Q19;
   using St = Store<S>;
   using T = typename St::T;
@@ -108,6 +109,10 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
   if (!((M >> lane) & 1ull)) return;
   const uint32_t ooff = own.off, on = own.n;
   const uint32_t rank = mbcnt(M, 0u);
+  // FP16 reads each lane region's base entry from the planner's table; the
+  // other forms compute it (off + i*n + fluid nodes shifted out below lane 0)
+  constexpr bool kTable = S == LBM_F16_OFFSET;
+  const uint32_t *__restrict__ rb = kTable ? rbase + tile * kRegionBases : nullptr;
 
   R f[19];
   static_for<19>([&](auto I) {
@@ -120,7 +125,12 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
       constexpr uint64_t R0 = region(cx, cy, cz, 0, 0, 0);
       const uint64_t X0 = shifted<d0>(M);
       uint64_t from_fluid = X0 & R0;
-      uint32_t e = mbcnt(X0, ooff + (uint32_t)i * on + dropped<d0>(M));
+      constexpr int ri0 = region_index(i, 0);
+      uint32_t e;
+      if constexpr (kTable)
+        e = mbcnt(X0, rb[ri0]);
+      else
+        e = mbcnt(X0, ooff + (uint32_t)i * on + dropped<d0>(M));
       static_for<8>([&](auto Wc) {
         constexpr int w = decltype(Wc)::value;
         constexpr int wx = w & 1, wy = (w >> 1) & 1, wz = (w >> 2) & 1;
@@ -131,7 +141,13 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
           const NbRec &r = nb[slot_of(k)];
           const uint64_t Xr = shifted<dr>(r.mask);
           from_fluid |= Xr & Rr;
-          e = select_lanes(Rr, mbcnt(Xr, r.off + (uint32_t)i * r.n + dropped<dr>(r.mask)), e);
+          constexpr int riw = region_index(i, w);
+          uint32_t base;
+          if constexpr (kTable)
+            base = rb[riw];
+          else
+            base = r.off + (uint32_t)i * r.n + dropped<dr>(r.mask);
+          e = select_lanes(Rr, mbcnt(Xr, base), e);
         }
       });
       // half-way bounce-back: a solid or missing source returns the node's own opposite value
@@ -197,19 +213,20 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 template <int S, int WPB, bool NT, int MODE>
 __global__ void __launch_bounds__(64 * WPB)
     k_step19(const void *__restrict__ src, void *__restrict__ dst, TileArgs a, const NbRec *__restrict__ nrec,
-             const uint32_t *__restrict__ nrow, const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
+             const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
+             const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
              const int32_t *__restrict__ count) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
-    step19_tile<S, NT>(gw, src, dst, a, nrec, nrow, coef);
+    step19_tile<S, NT>(gw, src, dst, a, nrec, nrow, rbase, coef);
   } else if constexpr (MODE == kList) {
     if (gw >= (int64_t)*count) return;
-    step19_tile<S, NT>(list[gw], src, dst, a, nrec, nrow, coef);
+    step19_tile<S, NT>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
   } else {
     const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
-    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT>(list[k], src, dst, a, nrec, nrow, coef);
+    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT>(list[k], src, dst, a, nrec, nrow, rbase, coef);
   }
 }
 
@@ -218,13 +235,14 @@ __global__ void __launch_bounds__(64 * WPB)
 bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
 
 hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const uint32_t *nrow, const CollideCoef *coef, bool nontemporal, const int32_t *list,
+                         const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef, bool nontemporal,
+                         const int32_t *list,
                          const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
   const unsigned blocks =
       mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, coef, list, count);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
     return hipGetLastError();
   };
 #define LBM_STEP19_MODE(S, W, N)                          \

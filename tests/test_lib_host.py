@@ -104,9 +104,11 @@ def test_workspace_size_counts_fluid_nodes_only():
         n = lbm.workspace_bytes(t, storage=storage, tau=0.7)
         pdf = 2 * 19 * sd * t.info["n_fluid"]
         # two copies of the fluid nodes' PDFs (each tile region padded to 128 bytes), the FP64
-        # residual reference velocity (24 bytes per fluid node) and under 200 bytes of tables per tile
+        # residual reference velocity (24 bytes per fluid node) and under 200 bytes of tables per
+        # tile (FP16: 256 more, the region bases of the step)
         nft = t.info["n_ftiles"]
-        assert pdf < n < pdf + 24 * t.info["n_fluid"] + (2 * 128 + 200) * nft + 8192
+        tables = 200 + (256 if storage == "f16" else 0)
+        assert pdf < n < pdf + 24 * t.info["n_fluid"] + (2 * 128 + tables) * nft + 8192
     assert lbm.workspace_bytes(t, tau=math.inf) > 0
 
 
