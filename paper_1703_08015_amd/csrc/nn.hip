@@ -365,6 +365,37 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
 // atomic add per weight.
 constexpr int kWgradPad = 8;  // bf16 of padding per LDS row
 
+// 32-bit row -> voxel maps (grids are checked to hold fewer than 2^31 rows)
+template <int SRC>
+__device__ __forceinline__ int64_t src_voxel32(int m, int t, const Grid &rows, const Grid &in) {
+  if constexpr (SRC == LBM_NN_IDENT) {
+    return m;
+  } else {
+    const int x = m % rows.nx, y = (m / rows.nx) % rows.ny, z = m / (rows.nx * rows.ny);
+    return gather_row<SRC>(x, y, z, m, t, in);
+  }
+}
+
+template <int DST>
+__device__ __forceinline__ int64_t dst_voxel32(int m, int t, const Grid &rows, const Grid &out) {
+  if constexpr (DST == LBM_NN_IDENT) {
+    return m;
+  } else {
+    const int x = m % rows.nx, y = (m / rows.nx) % rows.ny, z = m / (rows.nx * rows.ny);
+    return vidx(2 * x + (t & 1), 2 * y + ((t >> 1) & 1), 2 * z + (t >> 2), out);
+  }
+}
+
+// LDS written by this wavefront's lanes is visible to its other lanes
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Each wavefront stages its own 32 voxels per iteration (LDS tiles private to
+// the wave, so only wave-level synchronisation), and the next iteration's
+// rows are loaded into registers while the current MFMAs run.
 template <int SRC, int DST, int CF, int NF>
 __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks) {
   __shared__ __attribute__((aligned(16))) bf16 sx[4][16 * CF][32 + kWgradPad];
@@ -377,33 +408,47 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
   const int64_t v0 = (int64_t)blockIdx.x * chunk;
   int64_t v1 = v0 + chunk;
   if (v1 > a.M) v1 = a.M;
+  const int vl = lane & 31, g0 = lane >> 5;  // staging: voxel and first 8-channel group of this lane
+
+  auto load = [&](int64_t vb, bf16x8(&xv)[CF], bf16x8(&yv)[NF]) {
+    const int64_t m = vb + 32 * wv + vl;
+    const bool mv = m < v1;
+    const int mm = mv ? (int)m : 0;
+    const bf16 *xr = a.x + src_voxel32<SRC>(mm, t, a.rows, a.in_grid) * a.ldx;
+    const bf16 *yr = static_cast<const bf16 *>(a.y) + dst_voxel32<DST>(mm, t, a.rows, a.out_grid) * a.ldy;
+#pragma unroll
+    for (int g = 0; g < CF; ++g) {
+      const int c = cbase + 8 * (g0 + 2 * g);
+      xv[g] = bf16x8{};
+      if (mv && c < a.cin) xv[g] = *reinterpret_cast<const bf16x8 *>(xr + c);
+    }
+#pragma unroll
+    for (int g = 0; g < NF; ++g) {
+      const int n = nbase + 8 * (g0 + 2 * g);
+      yv[g] = bf16x8{};
+      if (mv && n < a.cout) yv[g] = *reinterpret_cast<const bf16x8 *>(yr + n);
+    }
+  };
+
   f32x4 acc[CF][NF];
 #pragma unroll
   for (int i = 0; i < CF; ++i)
 #pragma unroll
     for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  bf16x8 xv[CF], yv[NF];
+  if (v0 < v1) load(v0, xv, yv);
   for (int64_t vb = v0; vb < v1; vb += 128) {
-    // stage: lane handles voxel vb + 32*wv + (lane & 31), channel groups by lane >> 5
-    const int64_t m = vb + 32 * wv + (lane & 31);
-    const bool mv = m < v1;
-    const int vl = lane & 31;
-    const bf16 *xr = a.x + (mv ? src_voxel<SRC>(m, t, a.rows, a.in_grid) : 0) * a.ldx;
-    const bf16 *yr = static_cast<const bf16 *>(a.y) + (mv ? dst_voxel<DST>(m, t, a.rows, a.out_grid) : 0) * a.ldy;
-    for (int gch = lane >> 5; gch < 2 * CF; gch += 2) {
-      const int c = cbase + 8 * gch;
-      bf16x8 v = {};
-      if (mv && c < a.cin) v = *reinterpret_cast<const bf16x8 *>(xr + c);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sx[wv][8 * gch + q][vl] = v[q];
-    }
-    for (int gch = lane >> 5; gch < 2 * NF; gch += 2) {
-      const int n = nbase + 8 * gch;
-      bf16x8 v = {};
-      if (mv && n < a.cout) v = *reinterpret_cast<const bf16x8 *>(yr + n);
+    for (int g = 0; g < CF; ++g)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sy[wv][8 * gch + q][vl] = v[q];
-    }
-    __syncthreads();
+      for (int q = 0; q < 8; ++q) sx[wv][8 * (g0 + 2 * g) + q][vl] = xv[g][q];
+#pragma unroll
+    for (int g = 0; g < NF; ++g)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sy[wv][8 * (g0 + 2 * g) + q][vl] = yv[g][q];
+    wave_lds_sync();
+    if (vb + 128 < v1) load(vb + 128, xv, yv);  // in flight during the MFMAs
 #pragma unroll
     for (int i = 0; i < CF; ++i) {
       const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sx[wv][16 * i + r][8 * kb]);
@@ -413,7 +458,7 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // this wave's reads are done before its next staging
   }
   // lane holds C[c = 16i + 4kb + q][n = 16j + r]
 #pragma unroll
