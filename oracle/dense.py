@@ -3,9 +3,11 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Arrays use the dense
 layout f[i, z, y, x] (x fastest) and mask[z, y, x] with True = solid.
 
-Physics (arXiv 1703.08015): BGK collision Eq. (2), quasi-compressible
-equilibrium Eq. (3), velocity Eq. (5), LBGK update Eq. (7), propagation only
-between non-solid nodes (Sec. 3.2) as half-way bounce-back, gather form of
+Physics (arXiv 1703.08015): BGK collision Eq. (2); quasi-compressible
+equilibrium Eq. (3) and velocity Eq. (5) (``model=QUASI``, the default) or
+incompressible equilibrium Eq. (4) and velocity Eq. (6)
+(``model=INCOMPRESSIBLE``); LBGK update Eq. (7), propagation only between
+non-solid nodes (Sec. 3.2) as half-way bounce-back, gather form of
 propagation (Sec. 3, Fig. 5).  Body force: Guo forcing (the paper has none).
 """
 import ctypes
@@ -19,6 +21,17 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 _lib = None
+
+QUASI, INCOMPRESSIBLE = 0, 1
+_MODELS = {"quasi": QUASI, "quasi-compressible": QUASI, "incompressible": INCOMPRESSIBLE}
+
+
+def _model(m):
+    if isinstance(m, str):
+        return _MODELS[m]
+    if m not in (QUASI, INCOMPRESSIBLE):
+        raise ValueError("unknown model %r" % (m,))
+    return int(m)
 
 
 def build(force=False):
@@ -42,12 +55,13 @@ def _load():
         P = ctypes.c_void_p
         i64, u32, dbl = ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
         lib.ora_lattice.argtypes = [ctypes.c_int, P, P, P]
-        lib.ora_feq.argtypes = [ctypes.c_int, dbl, P, P]
-        lib.ora_guo.argtypes = [ctypes.c_int, dbl, P, P, P]
-        lib.ora_collide.argtypes = [ctypes.c_int, P, dbl, P, P]
-        lib.ora_init.argtypes = [ctypes.c_int, P, P, dbl, P, P, P]
-        lib.ora_step.argtypes = [ctypes.c_int, P, u32, P, dbl, P, P, P, i64, ctypes.c_int]
-        lib.ora_moments.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        I = ctypes.c_int
+        lib.ora_feq.argtypes = [I, I, dbl, P, P]
+        lib.ora_guo.argtypes = [I, I, dbl, P, P, P]
+        lib.ora_collide.argtypes = [I, I, P, dbl, P, P]
+        lib.ora_init.argtypes = [I, I, P, P, dbl, P, P, P]
+        lib.ora_step.argtypes = [I, I, P, u32, P, dbl, P, P, P, i64, I]
+        lib.ora_moments.argtypes = [I, I, P, P, P, P, P, P]
         for fn in (lib.ora_lattice, lib.ora_feq, lib.ora_guo, lib.ora_collide, lib.ora_init,
                    lib.ora_step, lib.ora_moments):
             fn.restype = ctypes.c_int
@@ -73,27 +87,27 @@ def lattice(q):
     return c, w, opp
 
 
-def feq(q, rho, u):
+def feq(q, rho, u, model=QUASI):
     out = np.zeros(q)
     u = np.ascontiguousarray(u, np.float64)
-    _check(_load().ora_feq(q, float(rho), _p(u), _p(out)))
+    _check(_load().ora_feq(q, _model(model), float(rho), _p(u), _p(out)))
     return out
 
 
-def guo(q, rho, u, g):
+def guo(q, rho, u, g, model=QUASI):
     """Guo source term without the (1 - omega/2) factor."""
     out = np.zeros(q)
     u = np.ascontiguousarray(u, np.float64)
     g = np.ascontiguousarray(g, np.float64)
-    _check(_load().ora_guo(q, float(rho), _p(u), _p(g), _p(out)))
+    _check(_load().ora_guo(q, _model(model), float(rho), _p(u), _p(g), _p(out)))
     return out
 
 
-def collide(q, f, tau, g):
+def collide(q, f, tau, g, model=QUASI):
     f = np.ascontiguousarray(f, np.float64)
     g = np.ascontiguousarray(g, np.float64)
     out = np.zeros(q)
-    _check(_load().ora_collide(q, _p(f), float(tau), _p(g), _p(out)))
+    _check(_load().ora_collide(q, _model(model), _p(f), float(tau), _p(g), _p(out)))
     return out
 
 
@@ -108,7 +122,7 @@ def _periodic_bits(periodic):
     return int(bool(periodic[0])) | (int(bool(periodic[1])) << 1) | (int(bool(periodic[2])) << 2)
 
 
-def init(q, mask, rho0=1.0, rho=None, u=None):
+def init(q, mask, rho0=1.0, rho=None, u=None, model=QUASI):
     """Post-collision state at t = 0: f*_i = f_eq_i(rho, u) on fluid nodes."""
     mask = np.ascontiguousarray(mask, np.uint8)
     f = np.zeros((q,) + mask.shape, np.float64)
@@ -116,27 +130,27 @@ def init(q, mask, rho0=1.0, rho=None, u=None):
     u = None if u is None else np.ascontiguousarray(u, np.float64)
     rp = None if rho is None else _p(rho)
     up = None if u is None else _p(u)
-    _check(_load().ora_init(q, _p(_shape3(mask)), _p(mask), float(rho0), rp, up, _p(f)))
+    _check(_load().ora_init(q, _model(model), _p(_shape3(mask)), _p(mask), float(rho0), rp, up, _p(f)))
     return f
 
 
-def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1):
+def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1, model=QUASI):
     """Advance the post-collision state ``f`` by ``nsteps`` steps (in place copy)."""
     mask = np.ascontiguousarray(mask, np.uint8)
     f = np.array(f, np.float64, order="C", copy=True)
     tmp = np.empty_like(f)
     g = np.ascontiguousarray(g, np.float64)
-    _check(_load().ora_step(q, _p(_shape3(mask)), _periodic_bits(periodic), _p(mask), float(tau),
-                            _p(g), _p(f), _p(tmp), int(nsteps), int(nthreads)))
+    _check(_load().ora_step(q, _model(model), _p(_shape3(mask)), _periodic_bits(periodic), _p(mask),
+                            float(tau), _p(g), _p(f), _p(tmp), int(nsteps), int(nthreads)))
     return f
 
 
-def moments(q, mask, f, g):
+def moments(q, mask, f, g, model=QUASI):
     """rho[z,y,x], u[3,z,y,x] of the stored post-collision state; solid = 0."""
     mask = np.ascontiguousarray(mask, np.uint8)
     f = np.ascontiguousarray(f, np.float64)
     g = np.ascontiguousarray(g, np.float64)
     rho = np.zeros(mask.shape)
     u = np.zeros((3,) + mask.shape)
-    _check(_load().ora_moments(q, _p(_shape3(mask)), _p(mask), _p(g), _p(f), _p(rho), _p(u)))
+    _check(_load().ora_moments(q, _model(model), _p(_shape3(mask)), _p(mask), _p(g), _p(f), _p(rho), _p(u)))
     return rho, u

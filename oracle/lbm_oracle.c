@@ -8,8 +8,10 @@
  * What it computes (Tomczak & Szafran, "Sparse geometries handling in lattice
  * Boltzmann method implementation for graphic processors", arXiv 1703.08015):
  *   - BGK collision, Eq. (2), relaxation time tau, viscosity (tau - 1/2)/3;
- *   - quasi-compressible equilibrium, Eq. (3) with c_s^2 = 1/3;
- *   - quasi-compressible velocity, Eq. (5);
+ *   - two fluid models, selected by the `model` argument:
+ *       model 0, quasi-compressible: equilibrium Eq. (3) with c_s^2 = 1/3,
+ *         velocity Eq. (5);
+ *       model 1, incompressible: equilibrium Eq. (4), velocity Eq. (6);
  *   - the time-discrete LBGK update, Eq. (7), with delta_x = delta_t = 1;
  *   - propagation only between non-solid nodes (Sec. 3.2), realised as
  *     link-wise half-way bounce-back decided by the source node;
@@ -23,6 +25,10 @@
  *   - the body force g is an acceleration applied with Guo's forcing:
  *     u = (sum_i c_i f_i)/rho + g/2 and a source term
  *     F_i = w_i rho [3 (c_i - u).g + 9 (c_i.u)(c_i.g)] scaled by (1 - omega/2);
+ *   - in the incompressible model, Eqs. (4) and (6) as printed carry no
+ *     density factor on the velocity terms: the reference density is 1 in
+ *     lattice units.  The same holds for the force, whose density is g, so
+ *     u = sum_i c_i f_i + g/2 and F_i = w_i [3 (c_i - u).g + 9 (c_i.u)(c_i.g)];
  *   - a source position outside the domain on a non-periodic axis is solid;
  *   - tau = +infinity gives omega = 0 (pure streaming, used with g = 0).
  *
@@ -97,71 +103,96 @@ int ora_lattice(int q, int32_t *c_out, double *w_out, int32_t *opp_out) {
 
 /* ---- single-node physics -------------------------------------------- */
 
-/* Eq. (3): f_eq_i = w_i rho (1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)),
+#define MODEL_QUASI 0
+#define MODEL_INCOMPRESSIBLE 1
+
+static int valid_model(int model) {
+  return model == MODEL_QUASI || model == MODEL_INCOMPRESSIBLE;
+}
+
+/* Quasi-compressible, Eq. (3):
+ *   f_eq_i = w_i rho (1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2));
+ * incompressible, Eq. (4):
+ *   f_eq_i = w_i (rho + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2));
  * cs2 = 1/3, i.e. coefficients 3, 9/2 and 3/2. */
-static void feq(const lattice_t *L, double rho, const double u[3], double *out) {
+static void feq(const lattice_t *L, int model, double rho, const double u[3],
+                double *out) {
   double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int i = 0; i < L->q; ++i) {
     double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
-    out[i] = L->w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+    if (model == MODEL_QUASI)
+      out[i] = L->w[i] * rho * (1.0 + poly);
+    else
+      out[i] = L->w[i] * (rho + poly);
   }
 }
 
 /* Guo source term without the (1 - omega/2) prefactor:
- * F_i = w_i rho [3 (c_i - u).g + 9 (c_i.u)(c_i.g)]. */
-static void guo(const lattice_t *L, double rho, const double u[3],
+ * F_i = w_i d [3 (c_i - u).g + 9 (c_i.u)(c_i.g)], where d is the density
+ * that carries the force: rho (quasi-compressible) or 1 (incompressible). */
+static void guo(const lattice_t *L, int model, double rho, const double u[3],
                 const double g[3], double *out) {
+  double d = model == MODEL_QUASI ? rho : 1.0;
   for (int i = 0; i < L->q; ++i) {
     double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
     double cg = L->c[i][0] * g[0] + L->c[i][1] * g[1] + L->c[i][2] * g[2];
     double cmug = (L->c[i][0] - u[0]) * g[0] + (L->c[i][1] - u[1]) * g[1] +
                   (L->c[i][2] - u[2]) * g[2];
-    out[i] = L->w[i] * rho * (3.0 * cmug + 9.0 * cu * cg);
+    out[i] = L->w[i] * d * (3.0 * cmug + 9.0 * cu * cg);
   }
 }
 
-/* Eq. (5) plus the half-force shift: rho = sum f, u = (sum c f)/rho + g/2. */
-static void macro(const lattice_t *L, const double *f, const double g[3],
-                  double *rho, double u[3]) {
+/* rho = sum f; the velocity with the half-force shift:
+ * Eq. (5), u = (sum c f)/rho + g/2 (quasi-compressible), or
+ * Eq. (6), u = sum c f + g/2 (incompressible). */
+static void macro(const lattice_t *L, int model, const double *f,
+                  const double g[3], double *rho, double u[3]) {
   double r = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < L->q; ++i) r += f[i];
   for (int i = 0; i < L->q; ++i)
     for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * f[i];
   *rho = r;
-  for (int a = 0; a < 3; ++a) u[a] = j[a] / r + 0.5 * g[a];
+  for (int a = 0; a < 3; ++a) {
+    if (model == MODEL_QUASI)
+      u[a] = j[a] / r + 0.5 * g[a];
+    else
+      u[a] = j[a] + 0.5 * g[a];
+  }
 }
 
 /* Eqs. (2) and (7): f* = f + omega (f_eq - f) + (1 - omega/2) F. */
-static void collide(const lattice_t *L, const double *f, double tau,
+static void collide(const lattice_t *L, int model, const double *f, double tau,
                     const double g[3], double *out) {
   double rho, u[3], fe[19], F[19];
   double omega = 1.0 / tau;
-  macro(L, f, g, &rho, u);
-  feq(L, rho, u, fe);
-  guo(L, rho, u, g, F);
+  macro(L, model, f, g, &rho, u);
+  feq(L, model, rho, u, fe);
+  guo(L, model, rho, u, g, F);
   for (int i = 0; i < L->q; ++i)
     out[i] = f[i] + omega * (fe[i] - f[i]) + (1.0 - 0.5 * omega) * F[i];
 }
 
-int ora_feq(int q, double rho, const double *u, double *out) {
+int ora_feq(int q, int model, double rho, const double *u, double *out) {
   lattice_t L;
-  if (get_lattice(q, &L)) return -1;
-  feq(&L, rho, u, out);
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
+  feq(&L, model, rho, u, out);
   return 0;
 }
 
-int ora_guo(int q, double rho, const double *u, const double *g, double *out) {
+int ora_guo(int q, int model, double rho, const double *u, const double *g,
+            double *out) {
   lattice_t L;
-  if (get_lattice(q, &L)) return -1;
-  guo(&L, rho, u, g, out);
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
+  guo(&L, model, rho, u, g, out);
   return 0;
 }
 
-int ora_collide(int q, const double *f, double tau, const double *g,
+int ora_collide(int q, int model, const double *f, double tau, const double *g,
                 double *out) {
   lattice_t L;
-  if (get_lattice(q, &L)) return -1;
-  collide(&L, f, tau, g, out);
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
+  collide(&L, model, f, tau, g, out);
   return 0;
 }
 
@@ -200,11 +231,11 @@ static int64_t source_of(const grid_t *G, const int p[3], const int c[3]) {
 
 /* Cold start (rho == NULL -> rho0, u == NULL -> 0) or given fields:
  * fluid f*_i = f_eq_i(rho, u); solid entries 0. */
-int ora_init(int q, const int32_t *shape, const uint8_t *mask, double rho0,
-             const double *rho, const double *u, double *f) {
+int ora_init(int q, int model, const int32_t *shape, const uint8_t *mask,
+             double rho0, const double *rho, const double *u, double *f) {
   lattice_t L;
   grid_t G;
-  if (get_lattice(q, &L)) return -1;
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
   make_grid(shape, 0u, &G);
   for (int64_t n = 0; n < G.N; ++n) {
     double fe[19], uu[3] = {0.0, 0.0, 0.0}, r = rho0;
@@ -215,16 +246,16 @@ int ora_init(int q, const int32_t *shape, const uint8_t *mask, double rho0,
     if (rho) r = rho[n];
     if (u)
       for (int a = 0; a < 3; ++a) uu[a] = u[a * G.N + n];
-    feq(&L, r, uu, fe);
+    feq(&L, model, r, uu, fe);
     for (int i = 0; i < q; ++i) f[i * G.N + n] = fe[i];
   }
   return 0;
 }
 
 /* One pull-stream + collide pass from src into dst over fluid nodes. */
-static void one_step(const lattice_t *L, const grid_t *G, const uint8_t *mask,
-                     double tau, const double g[3], const double *src,
-                     double *dst, int nthreads) {
+static void one_step(const lattice_t *L, int model, const grid_t *G,
+                     const uint8_t *mask, double tau, const double g[3],
+                     const double *src, double *dst, int nthreads) {
   (void)nthreads;
 #pragma omp parallel for num_threads(nthreads) collapse(2) schedule(static)
   for (int z = 0; z < G->n[2]; ++z) {
@@ -241,7 +272,7 @@ static void one_step(const lattice_t *L, const grid_t *G, const uint8_t *mask,
           else
             f[i] = src[L->opp[i] * G->N + n]; /* half-way bounce-back */
         }
-        collide(L, f, tau, g, out);
+        collide(L, model, f, tau, g, out);
         for (int i = 0; i < L->q; ++i) dst[i * G->N + n] = out[i];
       }
     }
@@ -250,19 +281,19 @@ static void one_step(const lattice_t *L, const grid_t *G, const uint8_t *mask,
 
 /* nsteps time steps; f holds post-collision values on entry and on return.
  * tmp is caller scratch of the same size as f. */
-int ora_step(int q, const int32_t *shape, uint32_t periodic,
+int ora_step(int q, int model, const int32_t *shape, uint32_t periodic,
              const uint8_t *mask, double tau, const double *g, double *f,
              double *tmp, int64_t nsteps, int nthreads) {
   lattice_t L;
   grid_t G;
-  if (get_lattice(q, &L)) return -1;
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
   if (nthreads < 1) nthreads = 1;
   make_grid(shape, periodic, &G);
   /* solid entries of tmp mirror f so that the result is complete either way */
   memcpy(tmp, f, sizeof(double) * (size_t)q * (size_t)G.N);
   double *a = f, *b = tmp;
   for (int64_t t = 0; t < nsteps; ++t) {
-    one_step(&L, &G, mask, tau, g, a, b, nthreads);
+    one_step(&L, model, &G, mask, tau, g, a, b, nthreads);
     double *s = a;
     a = b;
     b = s;
@@ -272,13 +303,15 @@ int ora_step(int q, const int32_t *shape, uint32_t periodic,
 }
 
 /* Macroscopic fields of the stored post-collision state:
- * rho = sum f*, u = (sum c f*)/rho - g/2 (equal to the step's Guo velocity
- * because the collision adds rho g to the first moment).  Solid nodes: 0. */
-int ora_moments(int q, const int32_t *shape, const uint8_t *mask,
+ * rho = sum f*, u = (sum c f*)/rho - g/2 (quasi-compressible) or
+ * u = sum c f* - g/2 (incompressible): equal to the step's Guo velocity
+ * because the collision adds the force density (rho g or g) to the first
+ * moment.  Solid nodes: 0. */
+int ora_moments(int q, int model, const int32_t *shape, const uint8_t *mask,
                 const double *g, const double *f, double *rho, double *u) {
   lattice_t L;
   grid_t G;
-  if (get_lattice(q, &L)) return -1;
+  if (get_lattice(q, &L) || !valid_model(model)) return -1;
   make_grid(shape, 0u, &G);
   for (int64_t n = 0; n < G.N; ++n) {
     if (mask[n]) {
@@ -291,7 +324,12 @@ int ora_moments(int q, const int32_t *shape, const uint8_t *mask,
     for (int i = 0; i < q; ++i)
       for (int a = 0; a < 3; ++a) j[a] += L.c[i][a] * f[i * G.N + n];
     rho[n] = r;
-    for (int a = 0; a < 3; ++a) u[a * G.N + n] = j[a] / r - 0.5 * g[a];
+    for (int a = 0; a < 3; ++a) {
+      if (model == MODEL_QUASI)
+        u[a * G.N + n] = j[a] / r - 0.5 * g[a];
+      else
+        u[a * G.N + n] = j[a] - 0.5 * g[a];
+    }
   }
   return 0;
 }
