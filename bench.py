@@ -3,7 +3,8 @@
 
 Workload: D3Q19 BGK quasi-compressible, FP64 PDFs, 256^3 periodic box filled
 with seeded overlapping solid spheres (radius 4-12) down to porosity 0.3,
-tau = 0.7, body force 1e-6 along x, 4x4x4 tiles.  A step is one full time step
+tau = 0.7, body force 1e-6 along x, 4x4x4 tiles (``--model incompressible``:
+the paper's incompressible model, Eqs. 4 and 6, on the same workload).  A step is one full time step
 (gather propagation + bounce-back + collision) over every non-empty tile;
 inputs are resident in HBM before timing starts.
 
@@ -28,23 +29,25 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA, MI355X
 METRIC = "D3Q19 sparse MLUPS & % HBM peak; time-to-steady-state, warm vs cold, FP32 vs FP64"
 SD = {"f64": 8, "f32": 4, "f16": 2}
+MODEL_NAME = {"quasi-compressible": "BGK quasi-compressible", "incompressible": "BGK incompressible"}
 
 
 def workload(args):
     from paper_1703_08015_amd import inputs
     if args.geometry == "spheres":
         mask, phi = inputs.spheres_3d(args.n, args.porosity, 4.0, 12.0, seed=args.seed)
-        desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, overlapping solid spheres r 4-12 to porosity %.2f "
-                "(seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles" % (args.n, args.porosity, args.seed, args.tau,
-                                                                     args.g))
+        desc = ("D3Q19 %s, %d^3 periodic, overlapping solid spheres r 4-12 to porosity %.2f "
+                "(seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles" % (MODEL_NAME[args.model], args.n, args.porosity,
+                                                                     args.seed, args.tau, args.g))
     elif args.geometry == "vessel":
         mask, phi = inputs.vessel_tree(args.n, 0.08, seed=args.seed)
-        desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
+        desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
                 "fluid fraction >= 0.08, seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles"
-                % (args.n, args.seed, args.tau, args.g))
+                % (MODEL_NAME[args.model], args.n, args.seed, args.tau, args.g))
     else:  # dense sanity point
         mask, phi = np.zeros((args.n,) * 3, bool), 1.0
-        desc = "D3Q19 BGK quasi-compressible, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (args.n, args.tau)
+        desc = "D3Q19 %s, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (MODEL_NAME[args.model], args.n,
+                                                                                  args.tau)
     return mask, phi, desc
 
 
@@ -68,6 +71,70 @@ def traffic_for(kernel_name, workload_key):
     return rec.get("bytes_per_launch")
 
 
+def step_kernel_key(args):
+    """Name of the timed step kernel and the workload key of its traffic record."""
+    inc = args.model == "incompressible"
+    kernel = "%s<D3Q19,4x4x4,%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
+                                       ",incompressible" if inc else "")
+    wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
+                                        "scalar" if args.kernel == "auto" else args.kernel, args.order,
+                                        "nt" if args.store in ("auto", "nontemporal") else "regular",
+                                        args.tiles_per_block or 4)
+    return kernel, wkey
+
+
+def record_traffic(args, argv):
+    """Store the HBM bytes per launch of the step kernel in profiles/traffic.json.
+
+    Input: two rocprofv3 runs of this same command line (without
+    --record-traffic), one with ``--pmc FETCH_SIZE`` and one with
+    ``--pmc WRITE_SIZE``, written with ``-o run --output-format csv`` into the
+    two given folders.  The counters are calibrated on the copy reference of
+    the same runs (a fill of --copy-gib GiB, which reads nothing, then copies
+    that read and write --copy-gib GiB each), so each counter is scaled by
+    true bytes / counted bytes of that kernel.  Runs on the host only."""
+    import csv
+    fetch_dir, write_dir = args.record_traffic
+    if args.copy_gib <= 0:
+        raise SystemExit("--record-traffic needs the copy reference (--copy-gib > 0) in the profiled runs")
+    kernel, wkey = step_kernel_key(args)
+    csv_name = kernel.split("<")[0]
+
+    def values(d, name):
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if r["Kernel_Name"] == name]
+
+    true_kib = args.copy_gib * (1 << 20)
+    fc, wc = values(fetch_dir, "vectorized_elementwise_kernel"), values(write_dir, "vectorized_elementwise_kernel")
+    fc = sorted(fc)[1:]  # drop the fill, which fetches (almost) nothing
+    f_scale, w_scale = true_kib / (sum(fc) / len(fc)), true_kib / (sum(wc) / len(wc))
+    fk, wk = values(fetch_dir, csv_name), values(write_dir, csv_name)
+    if not fk or not wk:
+        raise SystemExit("no %s dispatches in the counter runs" % csv_name)
+    fb = sum(fk) / len(fk) * 1024 * f_scale
+    wb = sum(wk) / len(wk) * 1024 * w_scale
+    files = ["paper_1703_08015_amd/csrc/%s" % ("kernels.hip" if args.kernel == "generic" else "step19.hip"),
+             "paper_1703_08015_amd/csrc/device.h"]
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in files)
+    cmd = " ".join(["python3", "bench.py"] + argv)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = json.load(open(path)) if os.path.exists(path) else {}
+    table.setdefault(kernel, {})[wkey] = {
+        "bytes_per_launch": int(round(fb + wb)), "fetch_bytes": int(round(fb)), "write_bytes": int(round(wb)),
+        "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5),
+        "fetch_kib_per_dispatch_raw": round(sum(fk) / len(fk), 1),
+        "write_kib_per_dispatch_raw": round(sum(wk) / len(wk), 1),
+        "dispatches": [len(fk), len(wk)],
+        "source_sha256": hashlib.sha256(src).hexdigest(), "source_files": files,
+        "commands": ["rocprofv3 --pmc %s -T -d %s -o run --output-format csv -- %s" % (c, d, cmd)
+                     for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))]}
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({"kernel": kernel, "workload": wkey, "fetch_bytes": int(round(fb)), "write_bytes": int(round(wb)),
+                      "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5)}))
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -86,14 +153,15 @@ def cpu_baseline(mask, args):
     from oracle import dense
     dense.build()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    f = dense.init(19, mask)
+    model = dense.INCOMPRESSIBLE if args.model == "incompressible" else dense.QUASI
+    f = dense.init(19, mask, model=model)
     g = [args.g, 0.0, 0.0]
     t0 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores)
+    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores, model=model)
     dt = time.perf_counter() - t0
     one = max(1, args.cpu_steps // 16)
     t1 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1)
+    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1, model=model)
     dt1 = time.perf_counter() - t1
     nf = int((~mask).sum())
     return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
@@ -148,7 +216,7 @@ def mode_steady(args, torch, lbm):
     fields = {}
     for st in ("f64", "f32"):
         s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0), graph_steps=args.check_every,
-                       f16_scale_log2=args.f16_scale_log2)
+                       f16_scale_log2=args.f16_scale_log2, model=args.model)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.init()
@@ -175,9 +243,9 @@ def mode_vessel(args, torch, lbm):
     from paper_1703_08015_amd import inputs
     mask, phi = inputs.vessel_tree(args.n, 0.08, seed=args.seed)
     tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
-    desc = ("D3Q19 BGK quasi-compressible, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, fluid "
-            "fraction %.4f, seed %d), tau %.2f, g %.0e along x, %d steps from rest" % (args.n, phi, args.seed, args.tau,
-                                                                                   args.g, args.vessel_steps))
+    desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, fluid "
+            "fraction %.4f, seed %d), tau %.2f, g %.0e along x, %d steps from rest"
+            % (MODEL_NAME[args.model], args.n, phi, args.seed, args.tau, args.g, args.vessel_steps))
     out = {"metric": "offset-storage error vs FP64 and MLUPS", "unit": "MLUPS", "higher_is_better": True,
            "data": "synthetic", "config": {"workload": desc, "n_fluid": tiles.info["n_fluid"],
                                            "n_ftiles": tiles.info["n_ftiles"], "phi_t": round(tiles.info["phi_t"], 4),
@@ -186,7 +254,7 @@ def mode_vessel(args, torch, lbm):
     ref = None
     for st in ("f64", "f32", "f16"):
         s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0),
-                       f16_scale_log2=args.f16_scale_log2)
+                       f16_scale_log2=args.f16_scale_log2, model=args.model)
         s.init()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -395,6 +463,8 @@ def main():
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--model", default="quasi-compressible", choices=["quasi-compressible", "incompressible"],
+                    help="fluid model of the collision (modes step, steady and vessel)")
     ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -406,7 +476,15 @@ def main():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the device copy reference (read + write each this many GiB); 0 = skip")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="host only: store the step kernel's HBM bytes from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this command line in profiles/traffic.json")
+    argv = sys.argv[1:]
     args = ap.parse_args()
+    if args.record_traffic:
+        k = argv.index("--record-traffic")
+        record_traffic(args, argv[:k] + argv[k + 3:])
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sparse-tile step is built and timed on a single MI355X; "
@@ -418,6 +496,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode in ("batch", "warmstart", "unet") and args.model != "quasi-compressible":
+        print("--model applies to the step, steady and vessel modes only", file=sys.stderr)
+        sys.exit(2)
     if args.mode != "step":
         if args.mode == "vessel" and args.n == 256:
             args.n = 448
@@ -435,7 +516,7 @@ def main():
     info = tiles.info
     solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
                         tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
-                        tile_order=args.order, step_kernel=args.kernel, store_policy=args.store)
+                        tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model)
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()
@@ -463,11 +544,7 @@ def main():
     alg_bytes = nf * 2 * q * sd  # Eq. (10) per non-solid node, per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     # D3Q19 on 4x4x4 tiles runs the scalar-mask kernel unless the generic one is asked for
-    kernel = "%s<D3Q19,4x4x4,%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage)
-    wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
-                                        "scalar" if args.kernel == "auto" else args.kernel, args.order,
-                                        "nt" if args.store in ("auto", "nontemporal") else "regular",
-                                        args.tiles_per_block or 4)
+    kernel, wkey = step_kernel_key(args)
     traffic = traffic_for(kernel, wkey)
     out = {
         "metric": METRIC,
@@ -489,6 +566,7 @@ def main():
             "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * 19 * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
+            "model": args.model,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -7,8 +7,10 @@
  * no non-solid node are dropped (Sec. 3); a tile map with -1 for empty tiles
  * locates neighbour tiles during propagation (two-copy method, Sec. 3).  One
  * time step fuses gather propagation, half-way bounce-back (propagation only
- * between non-solid nodes, Sec. 3.2) and the BGK collision, Eqs. (2), (3),
- * (5), (7), with Guo forcing for a body acceleration g.
+ * between non-solid nodes, Sec. 3.2) and the BGK collision, Eqs. (2) and (7),
+ * with Guo forcing for a body acceleration g, in one of the paper's two fluid
+ * models: quasi-compressible, Eqs. (3) and (5), or incompressible, Eqs. (4)
+ * and (6).
  *
  * Conventions for every call
  *   - Return value: LBM_OK (0) or a negative LBM_ERR_* code.  Nothing throws
@@ -89,8 +91,20 @@ typedef struct {
   int32_t persistent;      /* 1: the D3Q19 4x4x4 step runs as one persistent grid striding over the
                               active tile list; 0: one wavefront per tile */
   int32_t graph_steps;     /* K > 0: lbm_step replays captured HIP graphs of K steps; 0: plain launches */
-  int32_t reserved[3];     /* set to 0 */
+  int32_t model;           /* LBM_MODEL_*: fluid model of the collision (0 = quasi-compressible) */
+  int32_t reserved[2];     /* set to 0 */
 } lbm_params;
+
+/* Fluid model of the collision (Sec. 2.1).
+ *   QUASI_COMPRESSIBLE: f_eq_i = w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
+ *     Eq. (3); u = sum c_i f_i / rho + g/2, Eq. (5); Guo force density rho g.
+ *   INCOMPRESSIBLE: f_eq_i = w_i (rho + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
+ *     Eq. (4); u = sum c_i f_i + g/2, Eq. (6); the reference density of the
+ *     velocity terms is 1 in lattice units, so the force density is g.
+ * Both use the source F_i = w_i d [3 (c_i - u).g + 9 (c_i.u)(c_i.g)] with d the
+ * force density's factor (rho or 1), scaled by (1 - 1/(2 tau)). */
+#define LBM_MODEL_QUASI_COMPRESSIBLE 0
+#define LBM_MODEL_INCOMPRESSIBLE 1
 
 /* Cache policy of the PDF stores of the step: a stored value is next read one
  * step later, after the whole working set has streamed through the caches, so
@@ -172,24 +186,27 @@ int lbm_set_sample_force(lbm_solver *s, const double *g);
  * D3Q19 kernel (LBM_ERR_UNSUPPORTED otherwise).  Synchronises the stream. */
 int lbm_set_active(lbm_solver *s, const uint8_t *active);
 
-/* Initial state, Eq. (3): on every non-solid node the stored post-collision
- * PDFs become f_eq(rho, u).  rho: device dense FP64 (NULL = rho0 everywhere);
+/* Initial state, Eq. (3) or (4) by the model: on every non-solid node the
+ * stored post-collision PDFs become f_eq(rho, u).  rho: device dense FP64 (NULL = rho0 everywhere);
  * u: device dense FP64 [3][...] (NULL = 0).  Resets the step counter. */
 int lbm_init(lbm_solver *s, const double *rho, const double *u);
 
 /* n >= 0 time steps: gather propagation with half-way bounce-back, then the
- * collision of Eqs. (2), (3), (5), (7) with Guo forcing; the two PDF copies
- * swap roles after each step (Sec. 3).  Asynchronous. */
+ * BGK collision of Eqs. (2) and (7) with Guo forcing in the solver's model
+ * (Eqs. (3), (5) or (4), (6)); the two PDF copies swap roles after each step
+ * (Sec. 3).  Asynchronous. */
 int lbm_step(lbm_solver *s, int32_t n);
 
 /* Macroscopic fields of the current state: rho = sum f*_i and
- * u = (sum c_i f*_i)/rho - g/2 (the velocity the last collision used).
+ * u = (sum c_i f*_i)/rho - g/2, or sum c_i f*_i - g/2 in the incompressible
+ * model (the velocity the last collision used).
  * rho: device dense FP64, u: device dense FP64 [3][...]; solid nodes get 0.
  * Either pointer may be NULL.  Asynchronous. */
 int lbm_moments(lbm_solver *s, double *rho, double *u);
 
 /* FP64 totals over non-solid nodes, per sample: out_host[4*sample + k] =
- * mass, then momentum x, y, z (sum of rho u with u as in lbm_moments).
+ * mass, then momentum x, y, z (sum of rho u with u as in lbm_moments; sum of
+ * u in the incompressible model, whose reference density is 1).
  * Fixed-order reduction (run-to-run identical).  Synchronises the stream.
  * LBM_ERR_NONFINITE if any total is not finite. */
 int lbm_reduce(lbm_solver *s, double *out_host);

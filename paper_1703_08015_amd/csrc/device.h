@@ -170,7 +170,18 @@ struct TileArgs {
   double rho0;
   float f16_scale;         // 2^s
   float f16_inv;           // 2^-s
+  int32_t model;           // LBM_MODEL_*
+  int32_t pad;
 };
+
+// The density that multiplies the velocity terms of the equilibrium and the
+// force: rho in the quasi-compressible model, Eqs. (3) and (5); the reference
+// density 1 in the incompressible model, Eqs. (4) and (6).
+template <bool INC, class R>
+__device__ __forceinline__ R velocity_density(R rho) {
+  if constexpr (INC) return R(1);
+  else return rho;
+}
 
 // Workgroup -> logical block remap: the hardware hands workgroups to the 8
 // XCDs round-robin; this gives each XCD one contiguous range of blocks (and

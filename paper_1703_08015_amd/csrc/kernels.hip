@@ -16,7 +16,8 @@
 // neighbours (found through the neighbour row of the tile map); a solid or
 // missing source means half-way bounce-back, f_i(x) = f*_opp(i)(x)
 // (propagation only between non-solid nodes, Sec. 3.2).  Then the BGK
-// collision of Eqs. (2), (3), (5), (7) with Guo forcing, and 19 stores.
+// collision of Eqs. (2) and (7) with Guo forcing, in the quasi-compressible
+// model (Eqs. (3), (5)) or the incompressible one (Eqs. (4), (6)), and q stores.
 // The neighbour records (region offset, node count, fluid bitmask) of the
 // 3x3x3 tile neighbourhood are staged once per wavefront in LDS, as the
 // paper stages the local tile bitmap and node types in shared memory.
@@ -69,7 +70,7 @@ __device__ __forceinline__ int lane_rank(uint64_t m) {
 }
 
 // ---- fused step -----------------------------------------------------------------
-template <class L, int AX, int AY, int AZ, int S, int WPB>
+template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC>
 __global__ void __launch_bounds__(64 * WPB)
     k_step(const void *__restrict__ src_, void *__restrict__ dst_, TileArgs a, double omega_d) {
   using St = Store<S>;
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(64 * WPB)
     f[i] = St::load(src, addr, a.f16_inv);
   });
 
-  // macroscopic moments, Eq. (5) with the half-force shift
+  // macroscopic moments, Eq. (5) or (6) with the half-force shift
   const SampleRec &smp = a.samples[a.rec[tile].sample];
   const R gx = (R)smp.g[0], gy = (R)smp.g[1], gz = (R)smp.g[2];
   R sum = 0, jx = 0, jy = 0, jz = 0;
@@ -146,13 +147,19 @@ __global__ void __launch_bounds__(64 * WPB)
     if constexpr (cz < 0) jz -= f[i];
   });
   const R rho = St::offset ? (R)a.rho0 + sum : sum;
-  const R inv = R(1) / rho;
-  const R ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  const R m = velocity_density<INC>(rho);
+  R ux, uy, uz;
+  if constexpr (INC) {
+    ux = jx + R(0.5) * gx, uy = jy + R(0.5) * gy, uz = jz + R(0.5) * gz;
+  } else {
+    const R inv = R(1) / rho;
+    ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  }
   const R uu = ux * ux + uy * uy + uz * uz;
   const R om = (R)omega_d;
   const R fo = R(1) - R(0.5) * om;
 
-  // collision, Eqs. (2), (3), (7) + Guo source; store own block entries
+  // collision, Eqs. (2), (3) or (4), (7) + Guo source; store own block entries
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
@@ -161,9 +168,11 @@ __global__ void __launch_bounds__(64 * WPB)
     const R cg = R(cx) * gx + R(cy) * gy + R(cz) * gz;
     const R cmug = (R(cx) - ux) * gx + (R(cy) - uy) * gy + (R(cz) - uz) * gz;
     const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
-    // full form: w rho (1 + poly); offset form: w (drho + rho poly)
-    const R feq = St::offset ? w * (sum + rho * poly) : w * rho * (R(1) + poly);
-    const R F = w * rho * (R(3) * cmug + R(9) * cu * cg);
+    // full form: w (rho + m poly); offset form: w (drho + m poly), m = rho or 1
+    R feq;
+    if constexpr (INC) feq = St::offset ? w * (sum + poly) : w * (rho + poly);
+    else feq = St::offset ? w * (sum + rho * poly) : w * rho * (R(1) + poly);
+    const R F = w * m * (R(3) * cmug + R(9) * cu * cg);
     const R out = f[i] + om * (feq - f[i]) + fo * F;
     St::store(dst, obase + (int64_t)i * on, out, a.f16_scale);
   });
@@ -247,11 +256,14 @@ __global__ void __launch_bounds__(256) k_init(void *dst_, TileArgs a, const doub
   if (u)
     for (int k = 0; k < 3; ++k) v[k] = u[3 * s.dense0 + k * s.n_nodes + c.loc];
   const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const bool inc = a.model == LBM_MODEL_INCOMPRESSIBLE;
   typename St::T *dst = static_cast<typename St::T *>(dst_);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     const double cu = L::C[i][0] * v[0] + L::C[i][1] * v[1] + L::C[i][2] * v[2];
-    const double fe = L::Wt[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+    // Eq. (4) or Eq. (3)
+    const double fe = inc ? L::Wt[i] * (r + poly) : L::Wt[i] * r * (1.0 + poly);
     const double val = St::offset ? fe - L::Wt[i] * a.rho0 : fe;
     St::store(dst, c.entry + (int64_t)i * c.n, (typename St::R)val, a.f16_scale);
   });
@@ -267,8 +279,9 @@ __global__ void __launch_bounds__(256) k_moments(const void *src, TileArgs a, do
   double r, j[3];
   stored_moments<L, S>(src, c.entry, c.n, a, r, j);
   if (rho) rho[s.dense0 + c.loc] = r;
+  const double m = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : r;
   if (u)
-    for (int k = 0; k < 3; ++k) u[3 * s.dense0 + k * s.n_nodes + c.loc] = j[k] / r - 0.5 * s.g[k];
+    for (int k = 0; k < 3; ++k) u[3 * s.dense0 + k * s.n_nodes + c.loc] = j[k] / m - 0.5 * s.g[k];
 }
 
 template <class L, int AX, int AY, int AZ, int S>
@@ -318,7 +331,9 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const void *src, TileArg
     const SampleRec &s = a.samples[c.sample];
     double j[3];
     stored_moments<L, S>(src, c.entry, c.n, a, m, j);
-    for (int k = 0; k < 3; ++k) p[k] = j[k] - 0.5 * m * s.g[k];  // rho u
+    // rho u, or u at the incompressible model's reference density 1
+    const double d = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : m;
+    for (int k = 0; k < 3; ++k) p[k] = j[k] - 0.5 * d * s.g[k];
   }
   m = wave_sum(m);
   for (int k = 0; k < 3; ++k) p[k] = wave_sum(p[k]);
@@ -339,8 +354,9 @@ __global__ void __launch_bounds__(256)
     const SampleRec &s = a.samples[c.sample];
     double r, j[3];
     stored_moments<L, S>(src, c.entry, c.n, a, r, j);
+    const double m = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : r;
     for (int k = 0; k < 3; ++k) {
-      const double uk = j[k] / r - 0.5 * s.g[k];
+      const double uk = j[k] / m - 0.5 * s.g[k];
       double *ref = uref + (int64_t)k * a.n_fluid + c.node;
       const double dk = uk - *ref;
       d2 += dk * dk;
@@ -411,6 +427,7 @@ int storage_bytes(int storage) {
 
 bool variant_supported(const Variant &v) {
   if (storage_bytes(v.storage) == 0) return false;
+  if (v.model != LBM_MODEL_QUASI_COMPRESSIBLE && v.model != LBM_MODEL_INCOMPRESSIBLE) return false;
   if (v.q == 9) return v.ax == 16 && v.ay == 16 && v.az == 1 && v.wpb == 4;
   if (v.q == 19)
     return v.ax == 4 && v.ay == 4 && (v.az == 4 || v.az == 8) &&
@@ -455,8 +472,12 @@ hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileA
                        hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
   return dispatch(v, [&]<class L, int AX, int AY, int AZ, int S, int WPB>() {
-    hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB), 0, s,
-                       src, dst, a, omega);
+    if (v.model == LBM_MODEL_INCOMPRESSIBLE)
+      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, true>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
+                         0, s, src, dst, a, omega);
+    else
+      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, false>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
+                         0, s, src, dst, a, omega);
     return hipGetLastError();
   });
 }

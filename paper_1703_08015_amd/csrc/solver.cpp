@@ -91,6 +91,9 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
   if (p->persistent != 0 && p->persistent != 1) return set_error(LBM_ERR_ARG, "persistent = %d", p->persistent);
   if (p->graph_steps < 0 || p->graph_steps > 100000)
     return set_error(LBM_ERR_ARG, "graph_steps = %d", p->graph_steps);
+  if (p->model != LBM_MODEL_QUASI_COMPRESSIBLE && p->model != LBM_MODEL_INCOMPRESSIBLE)
+    return set_error(LBM_ERR_ARG, "model = %d", p->model);
+  if (p->reserved[0] != 0 || p->reserved[1] != 0) return set_error(LBM_ERR_ARG, "reserved fields must be 0");
   int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
   if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
   v->q = p->lattice;
@@ -99,6 +102,7 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
   v->az = t->tile[2];
   v->storage = p->storage;
   v->wpb = wpb;
+  v->model = p->model;
   if (!lbm::variant_supported(*v))
     return set_error(LBM_ERR_UNSUPPORTED, "lattice D%dQ%d with tile %dx%dx%d and %d waves per block not built",
                      p->lattice == 9 ? 2 : 3, p->lattice, v->ax, v->ay, v->az, p->tiles_per_block);
@@ -413,6 +417,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   a.n_waves = t->n_ftiles * t->words;
   a.n_fluid = t->n_fluid;
   a.rho0 = p->rho0;
+  a.model = p->model;
   a.f16_scale = std::ldexp(1.0f, p->f16_scale_log2);
   a.f16_inv = std::ldexp(1.0f, -p->f16_scale_log2);
 

@@ -17,13 +17,15 @@
 // node count, fluid mask) come through scalar loads; nothing is staged in LDS
 // and there is no barrier.
 //
-// Collision (Eqs. 2, 3, 5, 7 with Guo forcing) is regrouped so that each
-// direction costs four fused multiply-adds:
-//   out_i = (1-w) f_i + w_i [P + rho (b_i + cu_i (a_i + h cu_i))]
+// Collision (Eqs. 2 and 7 with Guo forcing; quasi-compressible Eqs. 3 and 5
+// or incompressible Eqs. 4 and 6) is regrouped so that each direction costs
+// four fused multiply-adds:
+//   out_i = (1-w) f_i + w_i [P + m (b_i + cu_i (a_i + h cu_i))]
 // with cu_i = c_i.u, h = 9w/2, a_i = 3w + 9(1-w/2) c_i.g, b_i = 3(1-w/2) c_i.g
-// (per-sample constants prepared on the host) and, per node,
-// P = w rho (1 - 3/2 u.u) - 3(1-w/2) rho u.g for the full form and
-// P = w (drho - 3/2 rho u.u) - 3(1-w/2) rho u.g for the offset forms.
+// (per-sample constants prepared on the host), m the density of the velocity
+// terms (rho, or 1 in the incompressible model) and, per node,
+// P = w (rho - 3/2 m u.u) - 3(1-w/2) m u.g for the full form and
+// P = w (drho - 3/2 m u.u) - 3(1-w/2) m u.g for the offset forms.
 #include "device.h"
 #include "kernels.h"
 
@@ -84,7 +86,7 @@ constexpr int slot_of(int k) {
 
 // One 4x4x4 tile: gather, collide, store.  Lanes of solid nodes return
 // early; every value the wavefront branches on is uniform.
-template <int S, bool NT>
+template <int S, bool NT, bool INC>
 __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict__ src_, void *__restrict__ dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
                                             const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -172,13 +174,22 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
   const R gx = (R)cc.g[0], gy = (R)cc.g[1], gz = (R)cc.g[2];
   const R om = (R)cc.omega, om1 = R(1) - om, fo = R(1) - R(0.5) * om, h = R(4.5) * om;
   const R rho = St::offset ? (R)a.rho0 + sum : sum;
-  const R inv = R(1) / rho;
-  const R ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  const R m = velocity_density<INC>(rho);
+  R ux, uy, uz;
+  if constexpr (INC) {
+    ux = jx + R(0.5) * gx, uy = jy + R(0.5) * gy, uz = jz + R(0.5) * gz;
+  } else {
+    const R inv = R(1) / rho;
+    ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  }
   const R uu = ux * ux + uy * uy + uz * uz;
   const R ug = ux * gx + uy * gy + uz * gz;
-  const R P = (St::offset ? om * (sum - R(1.5) * rho * uu) : om * rho * (R(1) - R(1.5) * uu)) -
-              R(3) * fo * rho * ug;
-  const R wr1 = R(L::Wt[1]) * rho, wr2 = R(L::Wt[7]) * rho;
+  R P;
+  if constexpr (INC)
+    P = om * ((St::offset ? sum : rho) - R(1.5) * uu) - R(3) * fo * ug;
+  else
+    P = (St::offset ? om * (sum - R(1.5) * rho * uu) : om * rho * (R(1) - R(1.5) * uu)) - R(3) * fo * rho * ug;
+  const R wr1 = R(L::Wt[1]) * m, wr2 = R(L::Wt[7]) * m;
   const R wp1 = R(L::Wt[1]) * P, wp2 = R(L::Wt[7]) * P;
 
   static_for<19>([&](auto I) {
@@ -210,7 +221,7 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 // list[w] if w < *count.  kPersistent: a fixed grid of G wavefronts strides
 // over list[0 .. *count).  The count lives in device memory, so a captured
 // graph stays valid when the active set changes.
-template <int S, int WPB, bool NT, int MODE>
+template <int S, int WPB, bool NT, bool INC, int MODE>
 __global__ void __launch_bounds__(64 * WPB)
     k_step19(const void *__restrict__ src, void *__restrict__ dst, TileArgs a, const NbRec *__restrict__ nrec,
              const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -220,13 +231,39 @@ __global__ void __launch_bounds__(64 * WPB)
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
-    step19_tile<S, NT>(gw, src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC>(gw, src, dst, a, nrec, nrow, rbase, coef);
   } else if constexpr (MODE == kList) {
     if (gw >= (int64_t)*count) return;
-    step19_tile<S, NT>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
   } else {
     const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
-    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT>(list[k], src, dst, a, nrec, nrow, rbase, coef);
+    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT, INC>(list[k], src, dst, a, nrec, nrow, rbase, coef);
+  }
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+template <bool V>
+using BC = std::integral_constant<bool, V>;
+
+// Calls f(storage, waves per block, model) with compile-time constants.
+template <class F>
+hipError_t with_variant(const Variant &v, F &&f) {
+  auto by_model = [&](auto s, auto w) -> hipError_t {
+    return v.model == LBM_MODEL_INCOMPRESSIBLE ? f(s, w, BC<true>{}) : f(s, w, BC<false>{});
+  };
+  auto by_wpb = [&](auto s) -> hipError_t {
+    switch (v.wpb) {
+      case 1: return by_model(s, IC<1>{});
+      case 2: return by_model(s, IC<2>{});
+      case 4: return by_model(s, IC<4>{});
+      default: return by_model(s, IC<8>{});
+    }
+  };
+  switch (v.storage) {
+    case LBM_F64: return by_wpb(IC<LBM_F64>{});
+    case LBM_F32_OFFSET: return by_wpb(IC<LBM_F32_OFFSET>{});
+    default: return by_wpb(IC<LBM_F16_OFFSET>{});
   }
 }
 
@@ -241,37 +278,23 @@ hipError_t launch_step19(const Variant &v, const void *src, void *dst, const Til
   if (a.n_waves == 0) return hipSuccess;
   const unsigned blocks =
       mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * v.wpb), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
-    return hipGetLastError();
-  };
-#define LBM_STEP19_MODE(S, W, N)                          \
-  switch (mode) {                                         \
-    case kDirect: return go(k_step19<S, W, N, kDirect>);  \
-    case kList: return go(k_step19<S, W, N, kList>);      \
-    default: return go(k_step19<S, W, N, kPersistent>);   \
-  }
-#define LBM_STEP19_NT(S, W)                  \
-  if (nontemporal) {                         \
-    LBM_STEP19_MODE(S, W, true)              \
-  } else {                                   \
-    LBM_STEP19_MODE(S, W, false)             \
-  }
-#define LBM_STEP19_WPB(S)   \
-  switch (v.wpb) {          \
-    case 1: LBM_STEP19_NT(S, 1) \
-    case 2: LBM_STEP19_NT(S, 2) \
-    case 4: LBM_STEP19_NT(S, 4) \
-    default: LBM_STEP19_NT(S, 8) \
-  }
-  switch (v.storage) {
-    case LBM_F64: LBM_STEP19_WPB(LBM_F64)
-    case LBM_F32_OFFSET: LBM_STEP19_WPB(LBM_F32_OFFSET)
-    default: LBM_STEP19_WPB(LBM_F16_OFFSET)
-  }
-#undef LBM_STEP19_WPB
-#undef LBM_STEP19_NT
-#undef LBM_STEP19_MODE
+  return with_variant(v, [&](auto sc, auto wc, auto ic) -> hipError_t {
+    constexpr int S = decltype(sc)::value, W = decltype(wc)::value;
+    constexpr bool INC = decltype(ic)::value;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
+      return hipGetLastError();
+    };
+    auto by_mode = [&](auto nt) {
+      constexpr bool NT = decltype(nt)::value;
+      switch (mode) {
+        case kDirect: return go(k_step19<S, W, NT, INC, kDirect>);
+        case kList: return go(k_step19<S, W, NT, INC, kList>);
+        default: return go(k_step19<S, W, NT, INC, kPersistent>);
+      }
+    };
+    return nontemporal ? by_mode(BC<true>{}) : by_mode(BC<false>{});
+  });
 }
 
 // Workgroups of the persistent step that fit on the device at once.
@@ -279,17 +302,12 @@ hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  auto occ = [&](auto kern) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * v.wpb, 0); };
-#define LBM_OCC(S, W) e = (e == hipSuccess) ? occ(k_step19<S, W, true, kPersistent>) : e;
-  const int w = v.wpb;
-  if (v.storage == LBM_F64) {
-    if (w == 1) { LBM_OCC(LBM_F64, 1) } else if (w == 2) { LBM_OCC(LBM_F64, 2) } else if (w == 4) { LBM_OCC(LBM_F64, 4) } else { LBM_OCC(LBM_F64, 8) }
-  } else if (v.storage == LBM_F32_OFFSET) {
-    if (w == 1) { LBM_OCC(LBM_F32_OFFSET, 1) } else if (w == 2) { LBM_OCC(LBM_F32_OFFSET, 2) } else if (w == 4) { LBM_OCC(LBM_F32_OFFSET, 4) } else { LBM_OCC(LBM_F32_OFFSET, 8) }
-  } else {
-    if (w == 1) { LBM_OCC(LBM_F16_OFFSET, 1) } else if (w == 2) { LBM_OCC(LBM_F16_OFFSET, 2) } else if (w == 4) { LBM_OCC(LBM_F16_OFFSET, 4) } else { LBM_OCC(LBM_F16_OFFSET, 8) }
-  }
-#undef LBM_OCC
+  if (e == hipSuccess)
+    e = with_variant(v, [&](auto sc, auto wc, auto ic) -> hipError_t {
+      constexpr int S = decltype(sc)::value, W = decltype(wc)::value;
+      constexpr bool INC = decltype(ic)::value;
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step19<S, W, true, INC, kPersistent>, 64 * W, 0);
+    });
   if (e != hipSuccess) return e;
   *blocks = (int64_t)cus * (per > 0 ? per : 1);
   return hipSuccess;

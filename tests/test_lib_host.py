@@ -89,6 +89,8 @@ def test_tiling_errors():
     (dict(tiles_per_block=3), lbm.LBM_ERR_UNSUPPORTED),
     (dict(tile_order=5), lbm.LBM_ERR_ARG),
     (dict(step_kernel=9), lbm.LBM_ERR_ARG),
+    (dict(model=2), lbm.LBM_ERR_ARG),
+    (dict(model=-1), lbm.LBM_ERR_ARG),
 ])
 def test_param_validation(kw, code):
     t = lbm.Tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0])
