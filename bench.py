@@ -74,8 +74,9 @@ def traffic_for(kernel_name, workload_key):
 def step_kernel_key(args):
     """Name of the timed step kernel and the workload key of its traffic record."""
     inc = args.model == "incompressible"
-    kernel = "%s<D3Q19,4x4x4,%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
-                                       ",incompressible" if inc else "")
+    kernel = "%s<D3Q19,4x4x4,%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
+                                         ",incompressible" if inc else "",
+                                         ",single-copy" if args.pattern == "single-copy" else "")
     wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
                                         "scalar" if args.kernel == "auto" else args.kernel, args.order,
                                         "nt" if args.store in ("auto", "nontemporal") else "regular",
@@ -465,6 +466,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--model", default="quasi-compressible", choices=["quasi-compressible", "incompressible"],
                     help="fluid model of the collision (modes step, steady and vessel)")
+    ap.add_argument("--pattern", default="two-copy", choices=["two-copy", "single-copy"],
+                    help="PDF buffers: the paper's two copies, or one copy updated in place (step mode)")
     ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -499,6 +502,9 @@ def main():
     if args.mode in ("batch", "warmstart", "unet") and args.model != "quasi-compressible":
         print("--model applies to the step, steady and vessel modes only", file=sys.stderr)
         sys.exit(2)
+    if args.mode != "step" and args.pattern != "two-copy":
+        print("--pattern applies to the step mode only", file=sys.stderr)
+        sys.exit(2)
     if args.mode != "step":
         if args.mode == "vessel" and args.n == 256:
             args.n = 448
@@ -516,7 +522,8 @@ def main():
     info = tiles.info
     solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
                         tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
-                        tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model)
+                        tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model,
+                        pattern=args.pattern)
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()
@@ -566,7 +573,8 @@ def main():
             "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * 19 * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
-            "model": args.model,
+            "model": args.model, "pattern": args.pattern,
+            "workspace_bytes": solver.workspace.numel(),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

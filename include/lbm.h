@@ -92,7 +92,8 @@ typedef struct {
                               active tile list; 0: one wavefront per tile */
   int32_t graph_steps;     /* K > 0: lbm_step replays captured HIP graphs of K steps; 0: plain launches */
   int32_t model;           /* LBM_MODEL_*: fluid model of the collision (0 = quasi-compressible) */
-  int32_t reserved[2];     /* set to 0 */
+  int32_t pattern;         /* LBM_PATTERN_*: PDF buffers and streaming pattern (0 = two copies) */
+  int32_t reserved;        /* set to 0 */
 } lbm_params;
 
 /* Fluid model of the collision (Sec. 2.1).
@@ -105,6 +106,21 @@ typedef struct {
  * force density's factor (rho or 1), scaled by (1 - 1/(2 tau)). */
 #define LBM_MODEL_QUASI_COMPRESSIBLE 0
 #define LBM_MODEL_INCOMPRESSIBLE 1
+
+/* PDF storage pattern.
+ *   TWO_COPY: the paper's two-copy method (Sec. 3): each step gathers from one
+ *     copy and writes the other.
+ *   SINGLE_COPY: one copy, updated in place (the "AA" access pattern), with
+ *     half the PDF memory; it stands where the paper's ghost-buffer method
+ *     (Sec. 3, Fig. 4) saves memory.  Steps alternate between a gather/scatter
+ *     step, which reads f*_i(x - c_i) and writes f*_i(x) into the slot that
+ *     x + c_i reads next, and a step local to each node.  Every step does the
+ *     arithmetic of the two-copy step on the same values, so the results are
+ *     identical.  With lbm_set_active, the active set may change only after an
+ *     even number of steps since lbm_init or lbm_pdfs_import (LBM_ERR_STATE
+ *     otherwise). */
+#define LBM_PATTERN_TWO_COPY 0
+#define LBM_PATTERN_SINGLE_COPY 1
 
 /* Cache policy of the PDF stores of the step: a stored value is next read one
  * step later, after the whole working set has streamed through the caches, so
@@ -183,7 +199,9 @@ int lbm_set_sample_force(lbm_solver *s, const double *g);
  * (active[n_samples], host).  A deactivated sample keeps its state (both PDF
  * copies hold it), so it can be read or reactivated later; moments,
  * reductions and exports still cover every sample.  Needs the scalar-mask
- * D3Q19 kernel (LBM_ERR_UNSUPPORTED otherwise).  Synchronises the stream. */
+ * D3Q19 kernel (LBM_ERR_UNSUPPORTED otherwise).  With LBM_PATTERN_SINGLE_COPY
+ * the set may change only after an even number of steps (LBM_ERR_STATE
+ * otherwise).  Synchronises the stream. */
 int lbm_set_active(lbm_solver *s, const uint8_t *active);
 
 /* Initial state, Eq. (3) or (4) by the model: on every non-solid node the

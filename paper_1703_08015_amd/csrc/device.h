@@ -60,6 +60,20 @@ constexpr int region_index(int i, int w) {
   return -1;
 }
 
+// Step phases: the two-copy step (source and destination buffers differ), or
+// one of the two in-place steps of the single-copy form: the gather/scatter
+// step that follows init or a local step (whose state holds f*_i in slot
+// opp(i)), and the local step that follows it (whose state holds the
+// streamed f_i in slot i).
+enum StepPhase : int { kPhaseTwoCopy = 0, kPhaseAAGather = 1, kPhaseAALocal = 2 };
+
+// PDF pointers of a step: restrict-qualified when source and destination are
+// distinct buffers (two-copy), plain in place.
+template <int PH, class T>
+using in_ptr = std::conditional_t<PH == kPhaseTwoCopy, const T *__restrict__, const T *>;
+template <int PH, class T>
+using out_ptr = std::conditional_t<PH == kPhaseTwoCopy, T *__restrict__, T *>;
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
 template <class F, int... I>
 __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
@@ -133,7 +147,7 @@ struct SampleRec {
   int64_t nbase0;   // first fluid node (compact numbering)
   int64_t n_fluid;  // fluid nodes of this sample
   int32_t shape[3]; // nx, ny, nz
-  int32_t pad;
+  int32_t frozen;   // 1: out of the active list (single copy: its state is in layout 0)
 };
 
 // Compact record of a tile for the scalar-mask D3Q19 kernel: region offset,
@@ -171,7 +185,7 @@ struct TileArgs {
   float f16_scale;         // 2^s
   float f16_inv;           // 2^-s
   int32_t model;           // LBM_MODEL_*
-  int32_t pad;
+  int32_t aa_phase;        // -1: two copies; single copy: layout of the state (0 or 1, see kernels.hip)
 };
 
 // The density that multiplies the velocity terms of the equilibrium and the

@@ -25,7 +25,8 @@ struct Variant {
 bool variant_supported(const Variant &v);
 int storage_bytes(int storage);
 
-hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileArgs &a, double omega,
+// phase: kPhase* of device.h
+hipError_t launch_step(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a, double omega,
                        hipStream_t s);
 // D3Q19 4x4x4 step with scalar-mask addressing (step19.hip); needs PDF entry
 // indices below 2^32.
@@ -36,11 +37,13 @@ bool step19_supported(const Variant &v);
 // index of every lane region (device.h).
 // mode 0: wavefront w -> tile w; 1: -> list[w] for w < *count; 2: persistent
 // grid of blocks_persistent workgroups striding over list[0 .. *count).
-hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef, bool nontemporal,
-                         const int32_t *list,
-                         const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s);
-hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks);
+hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a,
+                         const NbRec *nrec, const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef,
+                         bool nontemporal, const int32_t *list, const int32_t *count, int mode,
+                         int64_t blocks_persistent, hipStream_t s);
+// Workgroups of the persistent step resident at once (for both single-copy
+// phases when single_copy).
+hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, int64_t *blocks);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,
                        hipStream_t s);
 hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, double *rho, double *u,

@@ -21,6 +21,13 @@
 // The neighbour records (region offset, node count, fluid bitmask) of the
 // 3x3x3 tile neighbourhood are staged once per wavefront in LDS, as the
 // paper stages the local tile bitmap and node types in shared memory.
+//
+// Single-copy form (one PDF buffer, steps in place; the addressing is
+// described in step19.hip): the state after init or a local step holds f*_i
+// in the node's slot opp(i); after a gather/scatter step it holds the
+// streamed f_i in slot i, so f*_i(x) is then found where x + c_i reads it
+// (slot i of x + c_i, or slot opp(i) of x when x + c_i is solid).  The
+// auxiliary kernels read and write through that mapping.
 #include "device.h"
 #include "kernels.h"
 
@@ -70,17 +77,17 @@ __device__ __forceinline__ int lane_rank(uint64_t m) {
 }
 
 // ---- fused step -----------------------------------------------------------------
-template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC>
+template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC, int PH>
 __global__ void __launch_bounds__(64 * WPB)
-    k_step(const void *__restrict__ src_, void *__restrict__ dst_, TileArgs a, double omega_d) {
+    k_step(in_ptr<PH, void> src_, out_ptr<PH, void> dst_, TileArgs a, double omega_d) {
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
   constexpr int Q = L::Q;
   constexpr int W = AX * AY * AZ / 64;
   __shared__ Slot<W> slots[WPB][27];
-  const T *__restrict__ src = static_cast<const T *>(src_);
-  T *__restrict__ dst = static_cast<T *>(dst_);
+  in_ptr<PH, T> src = static_cast<const T *>(src_);
+  out_ptr<PH, T> dst = static_cast<T *>(dst_);
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
@@ -101,12 +108,14 @@ __global__ void __launch_bounds__(64 * WPB)
   const int on = own.n;
 
   R f[Q];
+  int64_t ea[PH == kPhaseAAGather ? Q : 1];  // entries read, rewritten by the single-copy gather
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    constexpr int ib = PH == kPhaseAAGather ? L::Opp[i] : i;  // slot of the source's value
     int64_t addr;
-    if constexpr (i == 0) {
-      addr = obase;
+    if constexpr (i == 0 || PH == kPhaseAALocal) {
+      addr = obase + (int64_t)i * on;
     } else {
       int sx = x - cx, sy = y - cy, sz = z - cz, dx = 0, dy = 0, dz = 0;
       if constexpr (cx != 0) {
@@ -124,11 +133,12 @@ __global__ void __launch_bounds__(64 * WPB)
       const int b = s & 63;
       const uint64_t m = sl.mask[wd];
       if ((m >> b) & 1ull)
-        addr = sl.off + (int64_t)i * sl.n + sl.pre[wd] + __popcll(m & ((1ull << b) - 1ull));
-      else
-        addr = obase + (int64_t)L::Opp[i] * on;  // half-way bounce-back
+        addr = sl.off + (int64_t)ib * sl.n + sl.pre[wd] + __popcll(m & ((1ull << b) - 1ull));
+      else  // half-way bounce-back: the node's own value opp(i), in slot opp(i) (slot i in place)
+        addr = obase + (int64_t)(PH == kPhaseAAGather ? i : L::Opp[i]) * on;
     }
     f[i] = St::load(src, addr, a.f16_inv);
+    if constexpr (PH == kPhaseAAGather) ea[i] = addr;
   });
 
   // macroscopic moments, Eq. (5) or (6) with the half-force shift
@@ -174,7 +184,16 @@ __global__ void __launch_bounds__(64 * WPB)
     else feq = St::offset ? w * (sum + rho * poly) : w * rho * (R(1) + poly);
     const R F = w * m * (R(3) * cmug + R(9) * cu * cg);
     const R out = f[i] + om * (feq - f[i]) + fo * F;
-    St::store(dst, obase + (int64_t)i * on, out, a.f16_scale);
+    // two-copy: own slot i; single-copy gather: where opp(i) was read;
+    // single-copy local: own slot opp(i)
+    int64_t e;
+    if constexpr (PH == kPhaseTwoCopy)
+      e = obase + (int64_t)i * on;
+    else if constexpr (PH == kPhaseAAGather)
+      e = ea[L::Opp[i]];
+    else
+      e = obase + (int64_t)L::Opp[i] * on;
+    St::store(dst, e, out, a.f16_scale);
   });
 }
 
@@ -182,6 +201,8 @@ __global__ void __launch_bounds__(64 * WPB)
 template <int AX, int AY, int AZ>
 struct NodeCtx {
   bool fluid;
+  int64_t tile;   // internal tile index
+  int ell;        // node index inside the tile
   int64_t entry;  // own direction-0 entry
   int n;          // own tile's fluid count
   int64_t node;   // compact fluid-node index
@@ -200,6 +221,8 @@ __device__ __forceinline__ NodeCtx<AX, AY, AZ> node_ctx(const TileArgs &a, int64
   c.fluid = (M >> lane) & 1ull;
   const int pre = (W == 1) ? 0 : a.pre[tile * W + part];
   const int rank = pre + lane_rank(M);
+  c.tile = tile;
+  c.ell = part * 64 + lane;
   const TileRec r = a.rec[tile];
   c.entry = r.off + rank;
   c.n = r.n;
@@ -215,6 +238,50 @@ __device__ __forceinline__ NodeCtx<AX, AY, AZ> node_ctx(const TileArgs &a, int64
   return c;
 }
 
+// Layout of the stored state of a node: -1 two-copy (f*_i in slot i); for the
+// single copy 0 (f*_i in slot opp(i), after init, import or a local step) or
+// 1 (streamed values, after a gather/scatter step).  A sample taken out of
+// the active list stays at layout 0 (the solver only freezes it there).
+template <int AX, int AY, int AZ>
+__device__ __forceinline__ int node_layout(const TileArgs &a, const NodeCtx<AX, AY, AZ> &c) {
+  if (a.aa_phase < 0) return -1;
+  return a.samples[c.sample].frozen ? 0 : a.aa_phase;
+}
+
+// Entry that holds the post-collision value f*_i of the node.
+template <class L, int AX, int AY, int AZ, int i>
+__device__ __forceinline__ int64_t post_entry(const TileArgs &a, const NodeCtx<AX, AY, AZ> &c, int layout) {
+  constexpr int W = AX * AY * AZ / 64;
+  if (layout < 0) return c.entry + (int64_t)i * c.n;
+  if (layout == 1 && i != 0) {
+    // f*_i(x) is what x + c_i pulls next: slot i of x + c_i when that node is fluid
+    int x = c.ell % AX + L::C[i][0], y = (c.ell / AX) % AY + L::C[i][1], z = c.ell / (AX * AY) + L::C[i][2];
+    int dx = 0, dy = 0, dz = 0;
+    if (x < 0) { dx = -1; x += AX; } else if (x >= AX) { dx = 1; x -= AX; }
+    if (y < 0) { dy = -1; y += AY; } else if (y >= AY) { dy = 1; y -= AY; }
+    if (z < 0) { dz = -1; z += AZ; } else if (z >= AZ) { dz = 1; z -= AZ; }
+    const int64_t t2 = (dx | dy | dz) ? (int64_t)a.nbr[c.tile * 27 + 13 + dx + 3 * dy + 9 * dz] : c.tile;
+    if (t2 >= 0) {
+      const int s = x + AX * (y + AY * z), wd = (W == 1) ? 0 : (s >> 6), b = s & 63;
+      const uint64_t m = a.fluid[t2 * W + wd];
+      if ((m >> b) & 1ull) {
+        const TileRec r = a.rec[t2];
+        const int pre = (W == 1) ? 0 : a.pre[t2 * W + wd];
+        return r.off + (int64_t)i * r.n + pre + __popcll(m & ((1ull << b) - 1ull));
+      }
+    }
+  }
+  // slot opp(i) of the node itself (layout 0, or bounced back in layout 1)
+  return c.entry + (int64_t)L::Opp[i] * c.n;
+}
+
+// Entry to write f*_i of the node when setting a state (init, import): the
+// layout the next step expects.
+template <class L, int AX, int AY, int AZ, int i>
+__device__ __forceinline__ int64_t set_entry(const TileArgs &a, const NodeCtx<AX, AY, AZ> &c) {
+  return c.entry + (int64_t)(a.aa_phase < 0 ? i : L::Opp[i]) * c.n;
+}
+
 // FP64 value of stored PDF i of a node.
 template <class L, int S, int i>
 __device__ __forceinline__ double load_f64(const void *src, int64_t e, const TileArgs &a) {
@@ -226,15 +293,17 @@ __device__ __forceinline__ double load_f64(const void *src, int64_t e, const Til
 // rho = sum f*, j = sum c f* (FP64, from the stored state).  For offsets,
 // rho = rho0 + sum of offsets (the weights sum to one, the first moment of
 // w_i rho0 vanishes).
-template <class L, int S>
-__device__ __forceinline__ void stored_moments(const void *src, int64_t e, int n, const TileArgs &a, double &rho,
-                                               double (&j)[3]) {
+template <class L, int S, int AX, int AY, int AZ>
+__device__ __forceinline__ void stored_moments(const void *src, const NodeCtx<AX, AY, AZ> &c, const TileArgs &a,
+                                               double &rho, double (&j)[3]) {
   using St = Store<S>;
+  const int layout = node_layout(a, c);
   double sum = 0.0;
   j[0] = j[1] = j[2] = 0.0;
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    const double v = (double)St::load(static_cast<const typename St::T *>(src), e + (int64_t)i * n, a.f16_inv);
+    const int64_t e = post_entry<L, AX, AY, AZ, i>(a, c, layout);
+    const double v = (double)St::load(static_cast<const typename St::T *>(src), e, a.f16_inv);
     sum += v;
     j[0] += L::C[i][0] * v;
     j[1] += L::C[i][1] * v;
@@ -265,7 +334,7 @@ __global__ void __launch_bounds__(256) k_init(void *dst_, TileArgs a, const doub
     // Eq. (4) or Eq. (3)
     const double fe = inc ? L::Wt[i] * (r + poly) : L::Wt[i] * r * (1.0 + poly);
     const double val = St::offset ? fe - L::Wt[i] * a.rho0 : fe;
-    St::store(dst, c.entry + (int64_t)i * c.n, (typename St::R)val, a.f16_scale);
+    St::store(dst, set_entry<L, AX, AY, AZ, i>(a, c), (typename St::R)val, a.f16_scale);
   });
 }
 
@@ -277,7 +346,7 @@ __global__ void __launch_bounds__(256) k_moments(const void *src, TileArgs a, do
   if (!c.fluid) return;
   const SampleRec &s = a.samples[c.sample];
   double r, j[3];
-  stored_moments<L, S>(src, c.entry, c.n, a, r, j);
+  stored_moments<L, S>(src, c, a, r, j);
   if (rho) rho[s.dense0 + c.loc] = r;
   const double m = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : r;
   if (u)
@@ -291,9 +360,10 @@ __global__ void __launch_bounds__(256) k_export(const void *src, TileArgs a, dou
   const NodeCtx<AX, AY, AZ> c = node_ctx<AX, AY, AZ>(a, gw);
   if (!c.fluid) return;
   const SampleRec &s = a.samples[c.sample];
+  const int layout = node_layout(a, c);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    dense[L::Q * s.dense0 + i * s.n_nodes + c.loc] = load_f64<L, S, i>(src, c.entry + (int64_t)i * c.n, a);
+    dense[L::Q * s.dense0 + i * s.n_nodes + c.loc] = load_f64<L, S, i>(src, post_entry<L, AX, AY, AZ, i>(a, c, layout), a);
   });
 }
 
@@ -310,7 +380,7 @@ __global__ void __launch_bounds__(256) k_import(void *dst_, TileArgs a, const do
     constexpr int i = decltype(I)::value;
     const double v = dense[L::Q * s.dense0 + i * s.n_nodes + c.loc];
     const double val = St::offset ? v - L::Wt[i] * a.rho0 : v;
-    St::store(dst, c.entry + (int64_t)i * c.n, (typename St::R)val, a.f16_scale);
+    St::store(dst, set_entry<L, AX, AY, AZ, i>(a, c), (typename St::R)val, a.f16_scale);
   });
 }
 
@@ -330,7 +400,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const void *src, TileArg
   if (c.fluid) {
     const SampleRec &s = a.samples[c.sample];
     double j[3];
-    stored_moments<L, S>(src, c.entry, c.n, a, m, j);
+    stored_moments<L, S>(src, c, a, m, j);
     // rho u, or u at the incompressible model's reference density 1
     const double d = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : m;
     for (int k = 0; k < 3; ++k) p[k] = j[k] - 0.5 * d * s.g[k];
@@ -353,7 +423,7 @@ __global__ void __launch_bounds__(256)
   if (c.fluid) {
     const SampleRec &s = a.samples[c.sample];
     double r, j[3];
-    stored_moments<L, S>(src, c.entry, c.n, a, r, j);
+    stored_moments<L, S>(src, c, a, r, j);
     const double m = a.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : r;
     for (int k = 0; k < 3; ++k) {
       const double uk = j[k] / m - 0.5 * s.g[k];
@@ -468,16 +538,28 @@ static hipError_t dispatch(const Variant &v, F &&f) {
 
 static unsigned blocks_for(int64_t waves, int per_block) { return (unsigned)((waves + per_block - 1) / per_block); }
 
-hipError_t launch_step(const Variant &v, const void *src, void *dst, const TileArgs &a, double omega,
+hipError_t launch_step(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a, double omega,
                        hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
+  if ((phase == kPhaseTwoCopy) == (src == dst)) return hipErrorInvalidValue;  // in place exactly for the single copy
   return dispatch(v, [&]<class L, int AX, int AY, int AZ, int S, int WPB>() {
+    auto go = [&](auto inc, auto ph) {
+      constexpr bool INC = decltype(inc)::value;
+      constexpr int PH = decltype(ph)::value;
+      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, INC, PH>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
+                         0, s, src, dst, a, omega);
+    };
+    auto by_phase = [&](auto inc) {
+      switch (phase) {
+        case kPhaseAAGather: go(inc, std::integral_constant<int, kPhaseAAGather>{}); break;
+        case kPhaseAALocal: go(inc, std::integral_constant<int, kPhaseAALocal>{}); break;
+        default: go(inc, std::integral_constant<int, kPhaseTwoCopy>{});
+      }
+    };
     if (v.model == LBM_MODEL_INCOMPRESSIBLE)
-      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, true>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
-                         0, s, src, dst, a, omega);
+      by_phase(std::true_type{});
     else
-      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, false>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
-                         0, s, src, dst, a, omega);
+      by_phase(std::false_type{});
     return hipGetLastError();
   });
 }

@@ -93,7 +93,9 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
     return set_error(LBM_ERR_ARG, "graph_steps = %d", p->graph_steps);
   if (p->model != LBM_MODEL_QUASI_COMPRESSIBLE && p->model != LBM_MODEL_INCOMPRESSIBLE)
     return set_error(LBM_ERR_ARG, "model = %d", p->model);
-  if (p->reserved[0] != 0 || p->reserved[1] != 0) return set_error(LBM_ERR_ARG, "reserved fields must be 0");
+  if (p->pattern != LBM_PATTERN_TWO_COPY && p->pattern != LBM_PATTERN_SINGLE_COPY)
+    return set_error(LBM_ERR_ARG, "pattern = %d", p->pattern);
+  if (p->reserved != 0) return set_error(LBM_ERR_ARG, "reserved field must be 0");
   int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
   if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
   v->q = p->lattice;
@@ -174,9 +176,10 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
         }
       }
       P.nrec_h[(size_t)nft] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
-      // region bases: off + i*n of the region's source tile, plus the fluid
-      // nodes that the shift to the destination lanes moves out below lane 0
-      // (the kernel adds v_mbcnt of the shifted mask); 0 for a missing source.
+      // region bases: off + b*n of the region's source tile (b the slot the
+      // gather reads: i, or opp(i) for the single copy), plus the fluid nodes
+      // that the shift to the destination lanes moves out below lane 0 (the
+      // kernel adds v_mbcnt of the shifted mask); 0 for a missing source.
       // Only the FP16 form reads them: it is bound by scalar issue, while for
       // FP32 and FP64 the 256 extra bytes per tile cost more than the scalar
       // work they save.
@@ -199,7 +202,8 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
             }
             const uint32_t dropped =
                 dr >= 0 ? 0u : (uint32_t)__builtin_popcountll(r->mask & ((1ull << (-dr)) - 1ull));
-            rb[lbm::region_index(i, w)] = r->off + (uint32_t)i * r->n + dropped;
+            const int b = p->pattern == LBM_PATTERN_SINGLE_COPY ? lbm::D3Q19::Opp[i] : i;
+            rb[lbm::region_index(i, w)] = r->off + (uint32_t)b * r->n + dropped;
           }
         }
       }
@@ -233,7 +237,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
     return at;
   };
   P.buf[0] = take((size_t)P.entries * sd);
-  P.buf[1] = take((size_t)P.entries * sd);
+  P.buf[1] = p->pattern == LBM_PATTERN_SINGLE_COPY ? P.buf[0] : take((size_t)P.entries * sd);
   P.rec = take((size_t)nft * sizeof(lbm::TileRec));
   P.fluid = take((size_t)(nft * W) * sizeof(uint64_t));
   P.pre = take((size_t)(nft * W) * sizeof(int32_t));
@@ -262,8 +266,9 @@ struct lbm_solver {
   lbm_params p{};
   hipStream_t stream = nullptr;
   lbm::TileArgs args{};
-  void *buf[2] = {nullptr, nullptr};
-  int cur = 0;
+  void *buf[2] = {nullptr, nullptr};  // the same buffer twice for the single copy
+  bool single_copy = false;
+  int cur = 0;  // two copies: the copy holding the state; single copy: its layout (0 or 1)
   int64_t steps = 0;
   bool initialized = false;
   int n_samples = 0;
@@ -355,6 +360,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->stream = static_cast<hipStream_t>(stream);
   s->buf[0] = base + P.buf[0];
   s->buf[1] = base + P.buf[1];
+  s->single_copy = p->pattern == LBM_PATTERN_SINGLE_COPY;
   s->n_samples = (int)t->samples.size();
   s->words = t->words;
   s->omega = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
@@ -418,6 +424,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   a.n_fluid = t->n_fluid;
   a.rho0 = p->rho0;
   a.model = p->model;
+  a.aa_phase = s->single_copy ? 0 : -1;
   a.f16_scale = std::ldexp(1.0f, p->f16_scale_log2);
   a.f16_inv = std::ldexp(1.0f, -p->f16_scale_log2);
 
@@ -438,7 +445,8 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if (e == hipSuccess) e = up(P.rbase, P.rbase_h.data(), P.rbase_h.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = up(P.list, s->list_h.data(), s->list_h.size() * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.count, &s->count_h, sizeof(int32_t));
-  if (e == hipSuccess && s->scalar_mask && p->persistent) e = lbm::step19_persistent_blocks(v, &s->persistent_blocks);
+  if (e == hipSuccess && s->scalar_mask && p->persistent)
+    e = lbm::step19_persistent_blocks(v, s->single_copy, &s->persistent_blocks);
   if (e == hipSuccess) e = up(P.nbase, P.nbase_h.data(), (size_t)nft * sizeof(int64_t));
   if (e == hipSuccess) e = up(P.samples, P.samples_h.data(), P.samples_h.size() * sizeof(lbm::SampleRec));
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host tables may be freed after return
@@ -475,8 +483,15 @@ extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
   if (!s || !active) return set_error(LBM_ERR_ARG, "lbm_set_active: NULL argument");
   if (!s->scalar_mask)
     return set_error(LBM_ERR_UNSUPPORTED, "lbm_set_active: needs the scalar-mask D3Q19 kernel (4x4x4 tiles)");
+  bool changed = false;
+  for (int k = 0; k < s->n_samples; ++k) changed |= (s->active_h[(size_t)k] != 0) != (active[k] != 0);
+  // single copy: frozen samples are kept in layout 0, which active samples
+  // share only after an even number of steps
+  if (s->single_copy && changed && s->cur != 0)
+    return set_error(LBM_ERR_STATE, "lbm_set_active: with one PDF copy the active set may change only after an "
+                                    "even number of steps");
   // samples that stop here: make both PDF copies hold their current state
-  for (int k = 0; k < s->n_samples; ++k) {
+  for (int k = 0; k < s->n_samples && !s->single_copy; ++k) {
     if (s->active_h[(size_t)k] && !active[k] && s->initialized && s->entry1[(size_t)k] > s->entry0[(size_t)k]) {
       const size_t off = (size_t)s->entry0[(size_t)k] * s->storage_bytes;
       const size_t len = (size_t)(s->entry1[(size_t)k] - s->entry0[(size_t)k]) * s->storage_bytes;
@@ -488,6 +503,7 @@ extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
   bool all = true;
   for (int k = 0; k < s->n_samples; ++k) {
     s->active_h[(size_t)k] = active[k] ? 1 : 0;
+    s->samples_h[(size_t)k].frozen = active[k] ? 0 : 1;
     all &= active[k] != 0;
     if (!active[k]) continue;
     const lbm::SampleRec &S = s->samples_h[(size_t)k];
@@ -496,6 +512,8 @@ extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
   s->count_h = n;
   HIP_TRY(hipMemcpyAsync(s->list_d, s->list_h.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipMemcpyAsync(s->count_d, &s->count_h, sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->samples_d, s->samples_h.data(), s->samples_h.size() * sizeof(lbm::SampleRec),
+                         hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   // the non-persistent step switches between direct and list-driven launches
   // here, so its captured graphs no longer match
@@ -520,27 +538,33 @@ extern "C" int lbm_set_sample_force(lbm_solver *s, const double *g) {
   return LBM_OK;
 }
 
+// Layout of the state for the auxiliary kernels.
+static lbm::TileArgs &aux_args(lbm_solver *s) {
+  s->args.aa_phase = s->single_copy ? s->cur : -1;
+  return s->args;
+}
+
 extern "C" int lbm_init(lbm_solver *s, const double *rho, const double *u) {
   if (!s) return set_error(LBM_ERR_ARG, "lbm_init: NULL solver");
-  HIP_TRY(lbm::launch_init(s->var, s->buf[0], s->args, rho, u, s->stream));
   s->cur = 0;
+  HIP_TRY(lbm::launch_init(s->var, s->buf[0], aux_args(s), rho, u, s->stream));
   s->steps = 0;
   s->initialized = true;
   // record the reference velocity of the residual
-  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[0], s->args, s->uref, s->part, 0, s->stream));
+  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[0], aux_args(s), s->uref, s->part, 0, s->stream));
   return LBM_OK;
 }
 
-// Enqueue one step from copy `from` on `st`.
+// Enqueue one step from copy (two copies) or layout (single copy) `from` on `st`.
 static hipError_t enqueue_step(lbm_solver *s, int from, hipStream_t st) {
+  const int phase = !s->single_copy ? lbm::kPhaseTwoCopy : (from == 0 ? lbm::kPhaseAAGather : lbm::kPhaseAALocal);
   if (s->scalar_mask) {
     const int mode = s->p.persistent ? 2 : (s->all_active ? 0 : 1);
-    return lbm::launch_step19(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d, s->rbase_d,
-                              s->coef_d,
-                              s->p.store_policy != LBM_STORE_REGULAR, s->list_d, s->count_d, mode,
-                              s->persistent_blocks, st);
+    return lbm::launch_step19(s->var, phase, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d,
+                              s->rbase_d, s->coef_d, s->p.store_policy != LBM_STORE_REGULAR, s->list_d, s->count_d,
+                              mode, s->persistent_blocks, st);
   }
-  return lbm::launch_step(s->var, s->buf[from], s->buf[from ^ 1], s->args, s->omega, st);
+  return lbm::launch_step(s->var, phase, s->buf[from], s->buf[from ^ 1], s->args, s->omega, st);
 }
 
 // Capture graph_steps steps starting from copy `from` (on a private stream:
@@ -595,14 +619,14 @@ extern "C" int lbm_moments(lbm_solver *s, double *rho, double *u) {
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_moments: solver not initialised");
   if (rho) HIP_TRY(lbm::launch_fill(rho, s->dense_nodes, 0.0, s->stream));
   if (u) HIP_TRY(lbm::launch_fill(u, 3 * s->dense_nodes, 0.0, s->stream));
-  HIP_TRY(lbm::launch_moments(s->var, s->buf[s->cur], s->args, rho, u, s->stream));
+  HIP_TRY(lbm::launch_moments(s->var, s->buf[s->cur], aux_args(s), rho, u, s->stream));
   return LBM_OK;
 }
 
 extern "C" int lbm_reduce(lbm_solver *s, double *out_host) {
   if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_reduce: NULL argument");
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_reduce: solver not initialised");
-  HIP_TRY(lbm::launch_reduce_partial(s->var, s->buf[s->cur], s->args, s->part, s->stream));
+  HIP_TRY(lbm::launch_reduce_partial(s->var, s->buf[s->cur], aux_args(s), s->part, s->stream));
   HIP_TRY(lbm::launch_reduce_final(s->part, 4, s->samples_d, s->n_samples, s->words, s->chunk, s->out,
                                      s->stream));
   HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 4 * sizeof(double),
@@ -617,7 +641,7 @@ extern "C" int lbm_reduce(lbm_solver *s, double *out_host) {
 extern "C" int lbm_residual(lbm_solver *s, double *out_host) {
   if (!s || !out_host) return set_error(LBM_ERR_ARG, "lbm_residual: NULL argument");
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_residual: solver not initialised");
-  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[s->cur], s->args, s->uref, s->part, 1, s->stream));
+  HIP_TRY(lbm::launch_residual_partial(s->var, s->buf[s->cur], aux_args(s), s->uref, s->part, 1, s->stream));
   HIP_TRY(lbm::launch_reduce_final(s->part, 2, s->samples_d, s->n_samples, s->words, s->chunk, s->out,
                                      s->stream));
   HIP_TRY(hipMemcpyAsync(s->out_h.data(), s->out, (size_t)s->n_samples * 2 * sizeof(double),
@@ -645,13 +669,14 @@ extern "C" int lbm_pdfs_export(lbm_solver *s, double *dev_dense) {
   if (!s || !dev_dense) return set_error(LBM_ERR_ARG, "lbm_pdfs_export: NULL argument");
   if (!s->initialized) return set_error(LBM_ERR_STATE, "lbm_pdfs_export: solver not initialised");
   HIP_TRY(lbm::launch_fill(dev_dense, (int64_t)s->var.q * s->dense_nodes, 0.0, s->stream));
-  HIP_TRY(lbm::launch_export(s->var, s->buf[s->cur], s->args, dev_dense, s->stream));
+  HIP_TRY(lbm::launch_export(s->var, s->buf[s->cur], aux_args(s), dev_dense, s->stream));
   return LBM_OK;
 }
 
 extern "C" int lbm_pdfs_import(lbm_solver *s, const double *dev_dense) {
   if (!s || !dev_dense) return set_error(LBM_ERR_ARG, "lbm_pdfs_import: NULL argument");
-  HIP_TRY(lbm::launch_import(s->var, s->buf[s->cur], s->args, dev_dense, s->stream));
+  if (s->single_copy) s->cur = 0;  // import writes layout 0
+  HIP_TRY(lbm::launch_import(s->var, s->buf[s->cur], aux_args(s), dev_dense, s->stream));
   s->initialized = true;
   return LBM_OK;
 }

@@ -17,6 +17,16 @@
 // node count, fluid mask) come through scalar loads; nothing is staged in LDS
 // and there is no barrier.
 //
+// Single-copy form (the in-place "AA" pattern, one PDF buffer): phase 1
+// gathers f_i(x) from the post-collision value f*_i(x - c_i), which the
+// previous step stored in the source node's slot opp(i) (its own slot i on a
+// bounce-back), and writes f*_i(x) to the address that the same node read
+// for opp(i), i.e. into slot i of x + c_i (slot opp(i) of x on a
+// bounce-back).  Each entry is read and written by one node only, so the
+// step is safe in place.  Phase 2 then reads f_i(x) from the node's own slot
+// i and writes f*_i(x) to its own slot opp(i).  Two steps move the same
+// bytes as two steps of the two-copy method.
+//
 // Collision (Eqs. 2 and 7 with Guo forcing; quasi-compressible Eqs. 3 and 5
 // or incompressible Eqs. 4 and 6) is regrouped so that each direction costs
 // four fused multiply-adds:
@@ -84,10 +94,12 @@ constexpr int slot_of(int k) {
   return -1;
 }
 
+constexpr int kTwoCopy = kPhaseTwoCopy, kAAGather = kPhaseAAGather, kAALocal = kPhaseAALocal;
+
 // One 4x4x4 tile: gather, collide, store.  Lanes of solid nodes return
 // early; every value the wavefront branches on is uniform.
-template <int S, bool NT, bool INC>
-__device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict__ src_, void *__restrict__ dst_,
+template <int S, bool NT, bool INC, int PH>
+__device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_, out_ptr<PH, void> dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
                                             const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
                                             const CollideCoef *__restrict__ coef) {
@@ -95,33 +107,39 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
   using St = Store<S>;
   using T = typename St::T;
   using R = typename St::R;
-  const T *__restrict__ src = static_cast<const T *>(src_);
-  T *__restrict__ dst = static_cast<T *>(dst_);
+  in_ptr<PH, T> src = static_cast<const T *>(src_);
+  out_ptr<PH, T> dst = static_cast<T *>(dst_);
   const int lane = threadIdx.x & 63;
 
   // own record and the 18 neighbour records (empty neighbours point at an
-  // all-solid sentinel record, so every load is unconditional)
+  // all-solid sentinel record, so every load is unconditional); the local
+  // phase of the single-copy form needs only its own
   const NbRec own = nrec[tile];
-  NbRec nb[18];
-  static_for<18>([&](auto J) {
-    constexpr int j = decltype(J)::value;
-    nb[j] = *reinterpret_cast<const NbRec *>(reinterpret_cast<const char *>(nrec) + nrow[tile * 20 + j]);
-  });
+  NbRec nb[PH == kAALocal ? 1 : 18];
+  if constexpr (PH != kAALocal)
+    static_for<18>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      nb[j] = *reinterpret_cast<const NbRec *>(reinterpret_cast<const char *>(nrec) + nrow[tile * 20 + j]);
+    });
   const uint64_t M = own.mask;
   if (!((M >> lane) & 1ull)) return;
   const uint32_t ooff = own.off, on = own.n;
   const uint32_t rank = mbcnt(M, 0u);
   // FP16 reads each lane region's base entry from the planner's table; the
-  // other forms compute it (off + i*n + fluid nodes shifted out below lane 0)
-  constexpr bool kTable = S == LBM_F16_OFFSET;
+  // other forms compute it (off + b*n + fluid nodes shifted out below lane 0,
+  // b the slot read: i, or opp(i) in the single-copy gather)
+  constexpr bool kTable = S == LBM_F16_OFFSET && PH != kAALocal;
   const uint32_t *__restrict__ rb = kTable ? rbase + tile * kRegionBases : nullptr;
 
   R f[19];
+  uint32_t ea[PH == kAAGather ? 19 : 1];  // entries read, rewritten by the single-copy gather
   static_for<19>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
-    if constexpr (i == 0) {
-      f[0] = St::load(src, (int64_t)(ooff + rank), a.f16_inv);
+    constexpr int ib = PH == kAAGather ? L::Opp[i] : i;  // slot of the source's value
+    if constexpr (i == 0 || PH == kAALocal) {
+      f[i] = St::load(src, (int64_t)(ooff + (uint32_t)i * on + rank), a.f16_inv);
+      if constexpr (PH == kAAGather) ea[0] = ooff + rank;
     } else {
       constexpr int d0 = cx + 4 * cy + 16 * cz;
       constexpr uint64_t R0 = region(cx, cy, cz, 0, 0, 0);
@@ -132,7 +150,7 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
       if constexpr (kTable)
         e = mbcnt(X0, rb[ri0]);
       else
-        e = mbcnt(X0, ooff + (uint32_t)i * on + dropped<d0>(M));
+        e = mbcnt(X0, ooff + (uint32_t)ib * on + dropped<d0>(M));
       static_for<8>([&](auto Wc) {
         constexpr int w = decltype(Wc)::value;
         constexpr int wx = w & 1, wy = (w >> 1) & 1, wz = (w >> 2) & 1;
@@ -148,13 +166,16 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
           if constexpr (kTable)
             base = rb[riw];
           else
-            base = r.off + (uint32_t)i * r.n + dropped<dr>(r.mask);
+            base = r.off + (uint32_t)ib * r.n + dropped<dr>(r.mask);
           e = select_lanes(Rr, mbcnt(Xr, base), e);
         }
       });
-      // half-way bounce-back: a solid or missing source returns the node's own opposite value
-      e = select_lanes(from_fluid, e, ooff + (uint32_t)L::Opp[i] * on + rank);
+      // half-way bounce-back: a solid or missing source returns the node's own
+      // post-collision value opp(i), held in slot opp(i) (slot i in place)
+      constexpr int bb = PH == kAAGather ? i : L::Opp[i];
+      e = select_lanes(from_fluid, e, ooff + (uint32_t)bb * on + rank);
       f[i] = St::load(src, (int64_t)e, a.f16_inv);
+      if constexpr (PH == kAAGather) ea[i] = e;
     }
   });
 
@@ -206,11 +227,24 @@ __device__ __forceinline__ void step19_tile(int64_t tile, const void *__restrict
       constexpr bool face = (cx != 0) + (cy != 0) + (cz != 0) == 1;
       out = om1 * f[i] + ((face ? wr1 : wr2) * t2 + (face ? wp1 : wp2));
     }
-    T *blk = dst + (ooff + (uint32_t)i * on);
+    // two-copy: own slot i of the other buffer; single-copy gather: where
+    // opp(i) was read; single-copy local: own slot opp(i)
+    T *blk;
+    uint32_t e;
+    if constexpr (PH == kTwoCopy) {
+      blk = dst + (ooff + (uint32_t)i * on);
+      e = rank;
+    } else if constexpr (PH == kAAGather) {
+      blk = dst;
+      e = ea[L::Opp[i]];
+    } else {
+      blk = dst;
+      e = ooff + (uint32_t)L::Opp[i] * on + rank;
+    }
     if constexpr (NT)
-      St::store_nt(blk, (int64_t)rank, out, a.f16_scale);
+      St::store_nt(blk, (int64_t)e, out, a.f16_scale);
     else
-      St::store(blk, (int64_t)rank, out, a.f16_scale);
+      St::store(blk, (int64_t)e, out, a.f16_scale);
   });
 }
 
@@ -221,9 +255,9 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 // list[w] if w < *count.  kPersistent: a fixed grid of G wavefronts strides
 // over list[0 .. *count).  The count lives in device memory, so a captured
 // graph stays valid when the active set changes.
-template <int S, int WPB, bool NT, bool INC, int MODE>
+template <int S, int WPB, bool NT, bool INC, int PH, int MODE>
 __global__ void __launch_bounds__(64 * WPB)
-    k_step19(const void *__restrict__ src, void *__restrict__ dst, TileArgs a, const NbRec *__restrict__ nrec,
+    k_step19(in_ptr<PH, void> src, out_ptr<PH, void> dst, TileArgs a, const NbRec *__restrict__ nrec,
              const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
              const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
              const int32_t *__restrict__ count) {
@@ -231,13 +265,13 @@ __global__ void __launch_bounds__(64 * WPB)
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
-    step19_tile<S, NT, INC>(gw, src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH>(gw, src, dst, a, nrec, nrow, rbase, coef);
   } else if constexpr (MODE == kList) {
     if (gw >= (int64_t)*count) return;
-    step19_tile<S, NT, INC>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
   } else {
     const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
-    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT, INC>(list[k], src, dst, a, nrec, nrow, rbase, coef);
+    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT, INC, PH>(list[k], src, dst, a, nrec, nrow, rbase, coef);
   }
 }
 
@@ -246,11 +280,18 @@ using IC = std::integral_constant<int, V>;
 template <bool V>
 using BC = std::integral_constant<bool, V>;
 
-// Calls f(storage, waves per block, model) with compile-time constants.
+// Calls f(storage, waves per block, model, phase) with compile-time constants.
 template <class F>
-hipError_t with_variant(const Variant &v, F &&f) {
+hipError_t with_variant(const Variant &v, int phase, F &&f) {
+  auto by_phase = [&](auto s, auto w, auto inc) -> hipError_t {
+    switch (phase) {
+      case kAAGather: return f(s, w, inc, IC<kAAGather>{});
+      case kAALocal: return f(s, w, inc, IC<kAALocal>{});
+      default: return f(s, w, inc, IC<kTwoCopy>{});
+    }
+  };
   auto by_model = [&](auto s, auto w) -> hipError_t {
-    return v.model == LBM_MODEL_INCOMPRESSIBLE ? f(s, w, BC<true>{}) : f(s, w, BC<false>{});
+    return v.model == LBM_MODEL_INCOMPRESSIBLE ? by_phase(s, w, BC<true>{}) : by_phase(s, w, BC<false>{});
   };
   auto by_wpb = [&](auto s) -> hipError_t {
     switch (v.wpb) {
@@ -271,15 +312,16 @@ hipError_t with_variant(const Variant &v, F &&f) {
 
 bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
 
-hipError_t launch_step19(const Variant &v, const void *src, void *dst, const TileArgs &a, const NbRec *nrec,
-                         const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef, bool nontemporal,
-                         const int32_t *list,
-                         const int32_t *count, int mode, int64_t blocks_persistent, hipStream_t s) {
+hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a,
+                         const NbRec *nrec, const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef,
+                         bool nontemporal, const int32_t *list, const int32_t *count, int mode,
+                         int64_t blocks_persistent, hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
+  if ((phase == kTwoCopy) == (src == dst)) return hipErrorInvalidValue;  // in place exactly for the single copy
   const unsigned blocks =
       mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
-  return with_variant(v, [&](auto sc, auto wc, auto ic) -> hipError_t {
-    constexpr int S = decltype(sc)::value, W = decltype(wc)::value;
+  return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc) -> hipError_t {
+    constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
     constexpr bool INC = decltype(ic)::value;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
@@ -288,9 +330,9 @@ hipError_t launch_step19(const Variant &v, const void *src, void *dst, const Til
     auto by_mode = [&](auto nt) {
       constexpr bool NT = decltype(nt)::value;
       switch (mode) {
-        case kDirect: return go(k_step19<S, W, NT, INC, kDirect>);
-        case kList: return go(k_step19<S, W, NT, INC, kList>);
-        default: return go(k_step19<S, W, NT, INC, kPersistent>);
+        case kDirect: return go(k_step19<S, W, NT, INC, PH, kDirect>);
+        case kList: return go(k_step19<S, W, NT, INC, PH, kList>);
+        default: return go(k_step19<S, W, NT, INC, PH, kPersistent>);
       }
     };
     return nontemporal ? by_mode(BC<true>{}) : by_mode(BC<false>{});
@@ -298,16 +340,25 @@ hipError_t launch_step19(const Variant &v, const void *src, void *dst, const Til
 }
 
 // Workgroups of the persistent step that fit on the device at once.
-hipError_t step19_persistent_blocks(const Variant &v, int64_t *blocks) {
+hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, int64_t *blocks) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = with_variant(v, [&](auto sc, auto wc, auto ic) -> hipError_t {
-      constexpr int S = decltype(sc)::value, W = decltype(wc)::value;
+  // the grid must fit for every phase the solver alternates between
+  auto fit = [&](int phase) -> hipError_t {
+    return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc) -> hipError_t {
+      constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
       constexpr bool INC = decltype(ic)::value;
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step19<S, W, true, INC, kPersistent>, 64 * W, 0);
+      int k = 0;
+      const hipError_t r =
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_step19<S, W, true, INC, PH, kPersistent>, 64 * W, 0);
+      per = per < 0 ? k : (k < per ? k : per);
+      return r;
     });
+  };
+  per = -1;
+  if (e == hipSuccess) e = fit(single_copy ? kAAGather : kTwoCopy);
+  if (e == hipSuccess && single_copy) e = fit(kAALocal);
   if (e != hipSuccess) return e;
   *blocks = (int64_t)cus * (per > 0 ? per : 1);
   return hipSuccess;

@@ -91,6 +91,7 @@ def test_tiling_errors():
     (dict(step_kernel=9), lbm.LBM_ERR_ARG),
     (dict(model=2), lbm.LBM_ERR_ARG),
     (dict(model=-1), lbm.LBM_ERR_ARG),
+    (dict(pattern=2), lbm.LBM_ERR_ARG),
 ])
 def test_param_validation(kw, code):
     t = lbm.Tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0])
@@ -112,6 +113,18 @@ def test_workspace_size_counts_fluid_nodes_only():
         tables = 200 + (256 if storage == "f16" else 0)
         assert pdf < n < pdf + 24 * t.info["n_fluid"] + (2 * 128 + tables) * nft + 8192
     assert lbm.workspace_bytes(t, tau=math.inf) > 0
+
+
+def test_single_copy_workspace_holds_one_pdf_copy():
+    """The single-copy pattern needs exactly one PDF copy less."""
+    m = inputs.spheres_3d(32, 0.3, seed=1)[0]
+    t = lbm.Tiles(m)
+    for storage, sd in (("f64", 8), ("f32", 4), ("f16", 2)):
+        two = lbm.workspace_bytes(t, storage=storage, tau=0.7)
+        one = lbm.workspace_bytes(t, storage=storage, tau=0.7, pattern="single-copy")
+        copy = two - one
+        # one copy: the fluid nodes' PDFs, each tile region padded to 128 bytes, the copy to 256
+        assert 19 * sd * t.info["n_fluid"] <= copy <= 19 * sd * t.info["n_fluid"] + 128 * t.info["n_ftiles"] + 256
 
 
 def test_autotune_candidates_and_key():
