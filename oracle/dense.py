@@ -6,7 +6,9 @@ layout f[i, z, y, x] (x fastest) and mask[z, y, x] with True = solid.
 Physics (arXiv 1703.08015): BGK collision Eq. (2); quasi-compressible
 equilibrium Eq. (3) and velocity Eq. (5) (``model=QUASI``, the default) or
 incompressible equilibrium Eq. (4) and velocity Eq. (6)
-(``model=INCOMPRESSIBLE``); LBGK update Eq. (7), propagation only between
+(``model=INCOMPRESSIBLE``); LBGK update Eq. (7), or the MRT collision of
+Eq. (8) when ``mrt`` rates are given (published orthogonal moment bases, see
+the C source); propagation only between
 non-solid nodes (Sec. 3.2) as half-way bounce-back, gather form of
 propagation (Sec. 3, Fig. 5).  Body force: Guo forcing (the paper has none).
 """
@@ -58,12 +60,13 @@ def _load():
         I = ctypes.c_int
         lib.ora_feq.argtypes = [I, I, dbl, P, P]
         lib.ora_guo.argtypes = [I, I, dbl, P, P, P]
-        lib.ora_collide.argtypes = [I, I, P, dbl, P, P]
+        lib.ora_collide.argtypes = [I, I, P, dbl, P, P, P]
+        lib.ora_mrt_matrix.argtypes = [I, P, P]
         lib.ora_init.argtypes = [I, I, P, P, dbl, P, P, P]
-        lib.ora_step.argtypes = [I, I, P, u32, P, dbl, P, P, P, i64, I]
+        lib.ora_step.argtypes = [I, I, P, u32, P, dbl, P, P, P, P, i64, I]
         lib.ora_moments.argtypes = [I, I, P, P, P, P, P, P]
         for fn in (lib.ora_lattice, lib.ora_feq, lib.ora_guo, lib.ora_collide, lib.ora_init,
-                   lib.ora_step, lib.ora_moments):
+                   lib.ora_step, lib.ora_moments, lib.ora_mrt_matrix):
             fn.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -103,11 +106,34 @@ def guo(q, rho, u, g, model=QUASI):
     return out
 
 
-def collide(q, f, tau, g, model=QUASI):
+MRT_CLASSES = ("conserved", "e", "eps", "q", "nu", "pi", "m")
+
+
+def _mrt(mrt):
+    """None (BGK) or the rates (s_e, s_eps, s_q, s_pi, s_m) as a C array."""
+    if mrt is None:
+        return None
+    r = np.ascontiguousarray(mrt, np.float64)
+    if r.shape != (5,):
+        raise ValueError("mrt rates are (s_e, s_eps, s_q, s_pi, s_m)")
+    return r
+
+
+def mrt_matrix(q):
+    """Moment basis M[q, q] (rows = moments) and each row's relaxation class
+    (index into MRT_CLASSES)."""
+    M = np.zeros((q, q))
+    cls = np.zeros(q, np.int32)
+    _check(_load().ora_mrt_matrix(q, _p(M), _p(cls)))
+    return M, cls
+
+
+def collide(q, f, tau, g, model=QUASI, mrt=None):
     f = np.ascontiguousarray(f, np.float64)
     g = np.ascontiguousarray(g, np.float64)
     out = np.zeros(q)
-    _check(_load().ora_collide(q, _model(model), _p(f), float(tau), _p(g), _p(out)))
+    r = _mrt(mrt)
+    _check(_load().ora_collide(q, _model(model), _p(f), float(tau), _p(g), None if r is None else _p(r), _p(out)))
     return out
 
 
@@ -134,14 +160,16 @@ def init(q, mask, rho0=1.0, rho=None, u=None, model=QUASI):
     return f
 
 
-def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1, model=QUASI):
+def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1, model=QUASI, mrt=None):
     """Advance the post-collision state ``f`` by ``nsteps`` steps (in place copy)."""
     mask = np.ascontiguousarray(mask, np.uint8)
     f = np.array(f, np.float64, order="C", copy=True)
     tmp = np.empty_like(f)
     g = np.ascontiguousarray(g, np.float64)
+    r = _mrt(mrt)
     _check(_load().ora_step(q, _model(model), _p(_shape3(mask)), _periodic_bits(periodic), _p(mask),
-                            float(tau), _p(g), _p(f), _p(tmp), int(nsteps), int(nthreads)))
+                            float(tau), _p(g), None if r is None else _p(r), _p(f), _p(tmp), int(nsteps),
+                            int(nthreads)))
     return f
 
 

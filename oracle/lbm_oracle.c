@@ -12,6 +12,11 @@
  *       model 0, quasi-compressible: equilibrium Eq. (3) with c_s^2 = 1/3,
  *         velocity Eq. (5);
  *       model 1, incompressible: equilibrium Eq. (4), velocity Eq. (6);
+ *   - the MRT collision of Eq. (8) when relaxation rates are given: the
+ *     collision matrix is diagonal in an orthogonal moment basis,
+ *     f* = f + M^-1 [-S M (f - f_eq) + (I - S/2) M F], with f_eq of the chosen
+ *     model and the same Guo source F; with every rate equal to 1/tau this
+ *     is the BGK update;
  *   - the time-discrete LBGK update, Eq. (7), with delta_x = delta_t = 1;
  *   - propagation only between non-solid nodes (Sec. 3.2), realised as
  *     link-wise half-way bounce-back decided by the source node;
@@ -29,6 +34,11 @@
  *     density factor on the velocity terms: the reference density is 1 in
  *     lattice units.  The same holds for the force, whose density is g, so
  *     u = sum_i c_i f_i + g/2 and F_i = w_i [3 (c_i - u).g + 9 (c_i.u)(c_i.g)];
+ *   - the paper does not give the MRT matrix: the bases are the published
+ *     orthogonal ones, Lallemand & Luo (PRE 61, 6546, 2000) for D2Q9 and
+ *     d'Humieres et al. (Phil. Trans. R. Soc. A 360, 437, 2002) for D3Q19,
+ *     written here as polynomials in the velocity c; the shear-stress
+ *     moments relax with 1/tau, the others with the given rates;
  *   - a source position outside the domain on a non-periodic axis is solid;
  *   - tau = +infinity gives omega = 0 (pure streaming, used with g = 0).
  *
@@ -161,16 +171,123 @@ static void macro(const lattice_t *L, int model, const double *f,
   }
 }
 
-/* Eqs. (2) and (7): f* = f + omega (f_eq - f) + (1 - omega/2) F. */
+/* ---- MRT moment bases (Eq. 8) ---------------------------------------- */
+
+/* Relaxation class of a moment: conserved (density, momentum), energy e,
+ * energy square eps, energy flux q, shear stress (rate 1/tau), the
+ * fourth-order pi moments and the third-order m moments. */
+enum { CL_CONS, CL_E, CL_EPS, CL_Q, CL_NU, CL_PI, CL_M };
+
+/* Row k of the basis evaluated at velocity c (integer for both bases). */
+static double mrt_entry(int q, int k, const int c[3], int *cls) {
+  const double x = c[0], y = c[1], z = c[2];
+  const double c2 = x * x + y * y + z * z;
+  if (q == 9) {
+    /* rho, e, eps, jx, qx, jy, qy, pxx, pxy */
+    switch (k) {
+      case 0: *cls = CL_CONS; return 1.0;
+      case 1: *cls = CL_E; return 3.0 * c2 - 4.0;
+      case 2: *cls = CL_EPS; return 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+      case 3: *cls = CL_CONS; return x;
+      case 4: *cls = CL_Q; return (3.0 * c2 - 5.0) * x;
+      case 5: *cls = CL_CONS; return y;
+      case 6: *cls = CL_Q; return (3.0 * c2 - 5.0) * y;
+      case 7: *cls = CL_NU; return x * x - y * y;
+      default: *cls = CL_NU; return x * y;
+    }
+  }
+  /* rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz,
+   * pxz, mx, my, mz */
+  switch (k) {
+    case 0: *cls = CL_CONS; return 1.0;
+    case 1: *cls = CL_E; return 19.0 * c2 - 30.0;
+    case 2: *cls = CL_EPS; return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: *cls = CL_CONS; return x;
+    case 4: *cls = CL_Q; return (5.0 * c2 - 9.0) * x;
+    case 5: *cls = CL_CONS; return y;
+    case 6: *cls = CL_Q; return (5.0 * c2 - 9.0) * y;
+    case 7: *cls = CL_CONS; return z;
+    case 8: *cls = CL_Q; return (5.0 * c2 - 9.0) * z;
+    case 9: *cls = CL_NU; return 3.0 * x * x - c2;
+    case 10: *cls = CL_PI; return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: *cls = CL_NU; return y * y - z * z;
+    case 12: *cls = CL_PI; return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: *cls = CL_NU; return x * y;
+    case 14: *cls = CL_NU; return y * z;
+    case 15: *cls = CL_NU; return x * z;
+    case 16: *cls = CL_M; return (y * y - z * z) * x;
+    case 17: *cls = CL_M; return (z * z - x * x) * y;
+    default: *cls = CL_M; return (x * x - y * y) * z;
+  }
+}
+
+static void mrt_matrix(const lattice_t *L, double M[19][19], int cls[19]) {
+  for (int k = 0; k < L->q; ++k)
+    for (int i = 0; i < L->q; ++i) M[k][i] = mrt_entry(L->q, k, L->c[i], &cls[k]);
+}
+
+int ora_mrt_matrix(int q, double *M_out, int32_t *cls_out) {
+  lattice_t L;
+  double M[19][19];
+  int cls[19];
+  if (get_lattice(q, &L)) return -1;
+  mrt_matrix(&L, M, cls);
+  for (int k = 0; k < q; ++k) {
+    cls_out[k] = cls[k];
+    for (int i = 0; i < q; ++i) M_out[k * q + i] = M[k][i];
+  }
+  return 0;
+}
+
+/* Rates of the relaxation classes: mrt = {s_e, s_eps, s_q, s_pi, s_m}; the
+ * shear stress relaxes with 1/tau.  Conserved moments take rate 1: their
+ * relaxation term vanishes for the density, and for the momentum the rate
+ * cancels against the half-force shift of u. */
+static double class_rate(int cls, double omega, const double *mrt) {
+  switch (cls) {
+    case CL_E: return mrt[0];
+    case CL_EPS: return mrt[1];
+    case CL_Q: return mrt[2];
+    case CL_PI: return mrt[3];
+    case CL_M: return mrt[4];
+    case CL_NU: return omega;
+    default: return 1.0;
+  }
+}
+
+/* Eqs. (2) and (7): f* = f + omega (f_eq - f) + (1 - omega/2) F (BGK, mrt ==
+ * NULL); Eq. (8) with the moment basis above otherwise. */
 static void collide(const lattice_t *L, int model, const double *f, double tau,
-                    const double g[3], double *out) {
+                    const double g[3], const double *mrt, double *out) {
   double rho, u[3], fe[19], F[19];
   double omega = 1.0 / tau;
   macro(L, model, f, g, &rho, u);
   feq(L, model, rho, u, fe);
   guo(L, model, rho, u, g, F);
-  for (int i = 0; i < L->q; ++i)
-    out[i] = f[i] + omega * (fe[i] - f[i]) + (1.0 - 0.5 * omega) * F[i];
+  if (!mrt) {
+    for (int i = 0; i < L->q; ++i)
+      out[i] = f[i] + omega * (fe[i] - f[i]) + (1.0 - 0.5 * omega) * F[i];
+    return;
+  }
+  double M[19][19], y[19];
+  int cls[19];
+  mrt_matrix(L, M, cls);
+  for (int k = 0; k < L->q; ++k) {
+    double dm = 0.0, fm = 0.0, norm = 0.0;
+    for (int i = 0; i < L->q; ++i) {
+      dm += M[k][i] * (f[i] - fe[i]);
+      fm += M[k][i] * F[i];
+      norm += M[k][i] * M[k][i];
+    }
+    double s = class_rate(cls[k], omega, mrt);
+    /* rows are orthogonal, so M^-1 = M^T diag(1/norm) */
+    y[k] = (-s * dm + (1.0 - 0.5 * s) * fm) / norm;
+  }
+  for (int i = 0; i < L->q; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < L->q; ++k) acc += M[k][i] * y[k];
+    out[i] = f[i] + acc;
+  }
 }
 
 int ora_feq(int q, int model, double rho, const double *u, double *out) {
@@ -189,10 +306,10 @@ int ora_guo(int q, int model, double rho, const double *u, const double *g,
 }
 
 int ora_collide(int q, int model, const double *f, double tau, const double *g,
-                double *out) {
+                const double *mrt, double *out) {
   lattice_t L;
   if (get_lattice(q, &L) || !valid_model(model)) return -1;
-  collide(&L, model, f, tau, g, out);
+  collide(&L, model, f, tau, g, mrt, out);
   return 0;
 }
 
@@ -255,7 +372,8 @@ int ora_init(int q, int model, const int32_t *shape, const uint8_t *mask,
 /* One pull-stream + collide pass from src into dst over fluid nodes. */
 static void one_step(const lattice_t *L, int model, const grid_t *G,
                      const uint8_t *mask, double tau, const double g[3],
-                     const double *src, double *dst, int nthreads) {
+                     const double *mrt, const double *src, double *dst,
+                     int nthreads) {
   (void)nthreads;
 #pragma omp parallel for num_threads(nthreads) collapse(2) schedule(static)
   for (int z = 0; z < G->n[2]; ++z) {
@@ -272,7 +390,7 @@ static void one_step(const lattice_t *L, int model, const grid_t *G,
           else
             f[i] = src[L->opp[i] * G->N + n]; /* half-way bounce-back */
         }
-        collide(L, model, f, tau, g, out);
+        collide(L, model, f, tau, g, mrt, out);
         for (int i = 0; i < L->q; ++i) dst[i * G->N + n] = out[i];
       }
     }
@@ -282,8 +400,9 @@ static void one_step(const lattice_t *L, int model, const grid_t *G,
 /* nsteps time steps; f holds post-collision values on entry and on return.
  * tmp is caller scratch of the same size as f. */
 int ora_step(int q, int model, const int32_t *shape, uint32_t periodic,
-             const uint8_t *mask, double tau, const double *g, double *f,
-             double *tmp, int64_t nsteps, int nthreads) {
+             const uint8_t *mask, double tau, const double *g,
+             const double *mrt, double *f, double *tmp, int64_t nsteps,
+             int nthreads) {
   lattice_t L;
   grid_t G;
   if (get_lattice(q, &L) || !valid_model(model)) return -1;
@@ -293,7 +412,7 @@ int ora_step(int q, int model, const int32_t *shape, uint32_t periodic,
   memcpy(tmp, f, sizeof(double) * (size_t)q * (size_t)G.N);
   double *a = f, *b = tmp;
   for (int64_t t = 0; t < nsteps; ++t) {
-    one_step(&L, model, &G, mask, tau, g, a, b, nthreads);
+    one_step(&L, model, &G, mask, tau, g, mrt, a, b, nthreads);
     double *s = a;
     a = b;
     b = s;
