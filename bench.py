@@ -29,7 +29,11 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA, MI355X
 METRIC = "D3Q19 sparse MLUPS & % HBM peak; time-to-steady-state, warm vs cold, FP32 vs FP64"
 SD = {"f64": 8, "f32": 4, "f16": 2}
-MODEL_NAME = {"quasi-compressible": "BGK quasi-compressible", "incompressible": "BGK incompressible"}
+MODEL_NAME = {"quasi-compressible": "quasi-compressible", "incompressible": "incompressible"}
+
+
+def model_name(args):
+    return "%s %s" % (args.collision.upper(), MODEL_NAME[args.model])
 
 
 def workload(args):
@@ -37,16 +41,16 @@ def workload(args):
     if args.geometry == "spheres":
         mask, phi = inputs.spheres_3d(args.n, args.porosity, 4.0, 12.0, seed=args.seed)
         desc = ("D3Q19 %s, %d^3 periodic, overlapping solid spheres r 4-12 to porosity %.2f "
-                "(seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles" % (MODEL_NAME[args.model], args.n, args.porosity,
+                "(seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles" % (model_name(args), args.n, args.porosity,
                                                                      args.seed, args.tau, args.g))
     elif args.geometry == "vessel":
         mask, phi = inputs.vessel_tree(args.n, 0.08, seed=args.seed)
         desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
                 "fluid fraction >= 0.08, seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles"
-                % (MODEL_NAME[args.model], args.n, args.seed, args.tau, args.g))
+                % (model_name(args), args.n, args.seed, args.tau, args.g))
     else:  # dense sanity point
         mask, phi = np.zeros((args.n,) * 3, bool), 1.0
-        desc = "D3Q19 %s, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (MODEL_NAME[args.model], args.n,
+        desc = "D3Q19 %s, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (model_name(args), args.n,
                                                                                   args.tau)
     return mask, phi, desc
 
@@ -74,9 +78,10 @@ def traffic_for(kernel_name, workload_key):
 def step_kernel_key(args):
     """Name of the timed step kernel and the workload key of its traffic record."""
     inc = args.model == "incompressible"
-    kernel = "%s<D3Q19,4x4x4,%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
-                                         ",incompressible" if inc else "",
-                                         ",single-copy" if args.pattern == "single-copy" else "")
+    kernel = "%s<D3Q19,4x4x4,%s%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
+                                           ",incompressible" if inc else "",
+                                           ",single-copy" if args.pattern == "single-copy" else "",
+                                           ",mrt" if args.collision == "mrt" else "")
     wkey = "%s_%d_%s_%s_%s_%s_tpb%d" % (args.geometry, args.n, args.storage,
                                         "scalar" if args.kernel == "auto" else args.kernel, args.order,
                                         "nt" if args.store in ("auto", "nontemporal") else "regular",
@@ -155,14 +160,16 @@ def cpu_baseline(mask, args):
     dense.build()
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     model = dense.INCOMPRESSIBLE if args.model == "incompressible" else dense.QUASI
+    # the library's default D3Q19 MRT rates (s_e, s_eps, s_q, s_pi, s_m)
+    mrt = (1.19, 1.4, 1.2, 1.4, 1.98) if args.collision == "mrt" else None
     f = dense.init(19, mask, model=model)
     g = [args.g, 0.0, 0.0]
     t0 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores, model=model)
+    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores, model=model, mrt=mrt)
     dt = time.perf_counter() - t0
     one = max(1, args.cpu_steps // 16)
     t1 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1, model=model)
+    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1, model=model, mrt=mrt)
     dt1 = time.perf_counter() - t1
     nf = int((~mask).sum())
     return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
@@ -217,7 +224,7 @@ def mode_steady(args, torch, lbm):
     fields = {}
     for st in ("f64", "f32"):
         s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0), graph_steps=args.check_every,
-                       f16_scale_log2=args.f16_scale_log2, model=args.model)
+                       f16_scale_log2=args.f16_scale_log2, model=args.model, collision=args.collision)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.init()
@@ -246,7 +253,7 @@ def mode_vessel(args, torch, lbm):
     tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
     desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, fluid "
             "fraction %.4f, seed %d), tau %.2f, g %.0e along x, %d steps from rest"
-            % (MODEL_NAME[args.model], args.n, phi, args.seed, args.tau, args.g, args.vessel_steps))
+            % (model_name(args), args.n, phi, args.seed, args.tau, args.g, args.vessel_steps))
     out = {"metric": "offset-storage error vs FP64 and MLUPS", "unit": "MLUPS", "higher_is_better": True,
            "data": "synthetic", "config": {"workload": desc, "n_fluid": tiles.info["n_fluid"],
                                            "n_ftiles": tiles.info["n_ftiles"], "phi_t": round(tiles.info["phi_t"], 4),
@@ -255,7 +262,7 @@ def mode_vessel(args, torch, lbm):
     ref = None
     for st in ("f64", "f32", "f16"):
         s = lbm.Solver(tiles, lattice=19, storage=st, tau=args.tau, g=(args.g, 0.0, 0.0),
-                       f16_scale_log2=args.f16_scale_log2, model=args.model)
+                       f16_scale_log2=args.f16_scale_log2, model=args.model, collision=args.collision)
         s.init()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -466,6 +473,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--model", default="quasi-compressible", choices=["quasi-compressible", "incompressible"],
                     help="fluid model of the collision (modes step, steady and vessel)")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
+                    help="collision operator: BGK (Eq. 2) or MRT (Eq. 8, published default rates) "
+                         "(modes step, steady and vessel)")
     ap.add_argument("--pattern", default="two-copy", choices=["two-copy", "single-copy"],
                     help="PDF buffers: the paper's two copies, or one copy updated in place (step mode)")
     ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
@@ -499,8 +509,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.mode in ("batch", "warmstart", "unet") and args.model != "quasi-compressible":
-        print("--model applies to the step, steady and vessel modes only", file=sys.stderr)
+    if args.mode in ("batch", "warmstart", "unet") and (args.model != "quasi-compressible" or args.collision != "bgk"):
+        print("--model and --collision apply to the step, steady and vessel modes only", file=sys.stderr)
         sys.exit(2)
     if args.mode != "step" and args.pattern != "two-copy":
         print("--pattern applies to the step mode only", file=sys.stderr)
@@ -523,7 +533,7 @@ def main():
     solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
                         tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
                         tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model,
-                        pattern=args.pattern)
+                        pattern=args.pattern, collision=args.collision)
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()
@@ -573,7 +583,7 @@ def main():
             "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * 19 * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
-            "model": args.model, "pattern": args.pattern,
+            "model": args.model, "pattern": args.pattern, "collision": args.collision,
             "workspace_bytes": solver.workspace.numel(),
         },
         "roofline": {

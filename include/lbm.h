@@ -93,7 +93,9 @@ typedef struct {
   int32_t graph_steps;     /* K > 0: lbm_step replays captured HIP graphs of K steps; 0: plain launches */
   int32_t model;           /* LBM_MODEL_*: fluid model of the collision (0 = quasi-compressible) */
   int32_t pattern;         /* LBM_PATTERN_*: PDF buffers and streaming pattern (0 = two copies) */
+  int32_t collision;       /* LBM_COLLISION_*: BGK (0) or MRT */
   int32_t reserved;        /* set to 0 */
+  double mrt_rates[5];     /* MRT: s_e, s_eps, s_q, s_pi, s_m (0 = published default) */
 } lbm_params;
 
 /* Fluid model of the collision (Sec. 2.1).
@@ -121,6 +123,21 @@ typedef struct {
  *     otherwise). */
 #define LBM_PATTERN_TWO_COPY 0
 #define LBM_PATTERN_SINGLE_COPY 1
+
+/* Collision operator.
+ *   BGK: single relaxation time, Eqs. (2) and (7).
+ *   MRT: multiple relaxation times, Eq. (8), with the collision matrix
+ *     diagonal in an orthogonal moment basis (the paper does not give it):
+ *     Lallemand & Luo (2000) for D2Q9, d'Humieres et al. (2002) for D3Q19:
+ *       f* = f + M^-1 [-S M (f - f_eq) + (I - S/2) M F],
+ *     f_eq and F of the chosen fluid model.  The shear-stress moments relax
+ *     with 1/tau; the energy e, energy square eps, energy flux q, and (D3Q19)
+ *     the fourth-order pi and third-order m moments with mrt_rates =
+ *     {s_e, s_eps, s_q, s_pi, s_m}, each in (0, 2); an entry 0 takes the
+ *     published default (D3Q19 1.19, 1.4, 1.2, 1.4, 1.98; D2Q9 1.64, 1.54,
+ *     1.9, and s_pi, s_m unused).  Equal rates 1/tau give the BGK collision. */
+#define LBM_COLLISION_BGK 0
+#define LBM_COLLISION_MRT 1  /* built for tiles_per_block 0 or 4 and non-regular store policy */
 
 /* Cache policy of the PDF stores of the step: a stored value is next read one
  * step later, after the whole working set has streamed through the caches, so

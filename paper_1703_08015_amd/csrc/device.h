@@ -74,6 +74,84 @@ using in_ptr = std::conditional_t<PH == kPhaseTwoCopy, const T *__restrict__, co
 template <int PH, class T>
 using out_ptr = std::conditional_t<PH == kPhaseTwoCopy, T *__restrict__, T *>;
 
+// ---- MRT moment bases (Eq. 8) -------------------------------------------------
+// The paper does not give the MRT collision matrix; it is taken diagonal in
+// the published orthogonal moment bases, Lallemand & Luo (2000) for D2Q9 and
+// d'Humieres et al. (2002) for D3Q19, written here as integer polynomials in
+// the velocity c.  Each moment relaxes with the rate of its class.
+enum MrtClass : int { kMrtCons = 0, kMrtE, kMrtEps, kMrtQ, kMrtNu, kMrtPi, kMrtM, kMrtClasses };
+
+struct MrtRow {
+  int value;
+  int cls;
+};
+
+// D2Q9: rho, e, eps, jx, qx, jy, qy, pxx, pxy.
+constexpr MrtRow mrt_row9(int k, int x, int y) {
+  const int c2 = x * x + y * y;
+  switch (k) {
+    case 0: return {1, kMrtCons};
+    case 1: return {3 * c2 - 4, kMrtE};
+    case 2: return {(8 - 21 * c2 + 9 * c2 * c2) / 2, kMrtEps};
+    case 3: return {x, kMrtCons};
+    case 4: return {(3 * c2 - 5) * x, kMrtQ};
+    case 5: return {y, kMrtCons};
+    case 6: return {(3 * c2 - 5) * y, kMrtQ};
+    case 7: return {x * x - y * y, kMrtNu};
+    default: return {x * y, kMrtNu};
+  }
+}
+
+// D3Q19: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy,
+// pyz, pxz, mx, my, mz.
+constexpr MrtRow mrt_row19(int k, int x, int y, int z) {
+  const int c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return {1, kMrtCons};
+    case 1: return {19 * c2 - 30, kMrtE};
+    case 2: return {(21 * c2 * c2 - 53 * c2 + 24) / 2, kMrtEps};
+    case 3: return {x, kMrtCons};
+    case 4: return {(5 * c2 - 9) * x, kMrtQ};
+    case 5: return {y, kMrtCons};
+    case 6: return {(5 * c2 - 9) * y, kMrtQ};
+    case 7: return {z, kMrtCons};
+    case 8: return {(5 * c2 - 9) * z, kMrtQ};
+    case 9: return {3 * x * x - c2, kMrtNu};
+    case 10: return {(3 * c2 - 5) * (3 * x * x - c2), kMrtPi};
+    case 11: return {y * y - z * z, kMrtNu};
+    case 12: return {(3 * c2 - 5) * (y * y - z * z), kMrtPi};
+    case 13: return {x * y, kMrtNu};
+    case 14: return {y * z, kMrtNu};
+    case 15: return {x * z, kMrtNu};
+    case 16: return {(y * y - z * z) * x, kMrtM};
+    case 17: return {(z * z - x * x) * y, kMrtM};
+    default: return {(x * x - y * y) * z, kMrtM};
+  }
+}
+
+template <class L>
+constexpr MrtRow mrt_row(int k, int i) {
+  if constexpr (L::Q == 9)
+    return mrt_row9(k, L::C[i][0], L::C[i][1]);
+  else
+    return mrt_row19(k, L::C[i][0], L::C[i][1], L::C[i][2]);
+}
+
+template <class L>
+constexpr int mrt_norm(int k) {
+  int n = 0;
+  for (int i = 0; i < L::Q; ++i) n += mrt_row<L>(k, i).value * mrt_row<L>(k, i).value;
+  return n;
+}
+
+// Per class: -s and 1 - s/2 (FP64 and FP32).  Shear stress: s = 1/tau;
+// conserved moments: s = 1 (the density's relaxation term vanishes and the
+// momentum's cancels against the half-force shift of u).
+struct MrtRates {
+  double ms[kMrtClasses], mh[kMrtClasses];
+  float msf[kMrtClasses], mhf[kMrtClasses];
+};
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
 template <class F, int... I>
 __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
@@ -186,6 +264,7 @@ struct TileArgs {
   float f16_inv;           // 2^-s
   int32_t model;           // LBM_MODEL_*
   int32_t aa_phase;        // -1: two copies; single copy: layout of the state (0 or 1, see kernels.hip)
+  MrtRates mrt;            // relaxation of the MRT collision
 };
 
 // The density that multiplies the velocity terms of the equilibrium and the
@@ -203,6 +282,63 @@ __device__ __forceinline__ R velocity_density(R rho) {
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   const int64_t k = b & 7, q = nb >> 3, r = nb & 7;
   return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+// MRT collision, Eq. (8) with Guo forcing, in place on f (the PDFs, or their
+// offsets f_i - w_i rho0 in the offset forms):
+//   f* = f + M^-1 [-S M (f - f_eq) + (I - S/2) M F],
+// f_eq from Eq. (3) or (4), u with the half-force shift; the rows of M are
+// orthogonal, so M^-1 = M^T diag(1/norm).  With every rate 1/tau this is the
+// BGK collision.
+template <class L, int S, bool INC, class R>
+__device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R rho, R ux, R uy, R uz, R gx, R gy, R gz,
+                                            const MrtRates &mr) {
+  constexpr int Q = L::Q;
+  constexpr bool off = Store<S>::offset;
+  const R m = velocity_density<INC>(rho);
+  const R uu = ux * ux + uy * uy + uz * uz;
+  R d[Q], F[Q];
+  static_for<Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    constexpr R w = (R)L::Wt[i];
+    const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+    const R cg = R(cx) * gx + R(cy) * gy + R(cz) * gz;
+    const R cmug = (R(cx) - ux) * gx + (R(cy) - uy) * gy + (R(cz) - uz) * gz;
+    const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+    // f_eq (or its offset): w (rho + m poly), w (drho + m poly)
+    const R feq = w * ((off ? sum : rho) + m * poly);
+    d[i] = f[i] - feq;
+    F[i] = w * m * (R(3) * cmug + R(9) * cu * cg);
+  });
+  static_for<Q>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    R dm = 0, fm = 0;
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int c = mrt_row<L>(k, i).value;
+      if constexpr (c != 0) {
+        dm += R(c) * d[i];
+        fm += R(c) * F[i];
+      }
+    });
+    constexpr int cl = mrt_row<L>(k, 0).cls;
+    constexpr R inv = R(1.0 / mrt_norm<L>(k));
+    R ms, mh;
+    if constexpr (sizeof(R) == 8) {
+      ms = (R)mr.ms[cl];
+      mh = (R)mr.mh[cl];
+    } else {
+      ms = (R)mr.msf[cl];
+      mh = (R)mr.mhf[cl];
+    }
+    const R y = (ms * dm + mh * fm) * inv;
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int c = mrt_row<L>(k, i).value;
+      if constexpr (c != 0) f[i] += R(c) * y;
+    });
+  });
 }
 
 }  // namespace lbm

@@ -20,6 +20,7 @@ struct Variant {
   int storage;     // LBM_F64 / LBM_F32_OFFSET / LBM_F16_OFFSET
   int wpb;         // waves per workgroup (D2Q9 16x16: 4 = one tile)
   int model;       // LBM_MODEL_*
+  int collision;   // LBM_COLLISION_*
 };
 
 bool variant_supported(const Variant &v);

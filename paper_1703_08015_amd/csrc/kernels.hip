@@ -77,7 +77,7 @@ __device__ __forceinline__ int lane_rank(uint64_t m) {
 }
 
 // ---- fused step -----------------------------------------------------------------
-template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC, int PH>
+template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC, int PH, bool MRT>
 __global__ void __launch_bounds__(64 * WPB)
     k_step(in_ptr<PH, void> src_, out_ptr<PH, void> dst_, TileArgs a, double omega_d) {
   using St = Store<S>;
@@ -169,7 +169,26 @@ __global__ void __launch_bounds__(64 * WPB)
   const R om = (R)omega_d;
   const R fo = R(1) - R(0.5) * om;
 
-  // collision, Eqs. (2), (3) or (4), (7) + Guo source; store own block entries
+  // two-copy: own slot i; single-copy gather: where opp(i) was read;
+  // single-copy local: own slot opp(i)
+  auto put = [&](auto I, R out) {
+    constexpr int i = decltype(I)::value;
+    int64_t e;
+    if constexpr (PH == kPhaseTwoCopy)
+      e = obase + (int64_t)i * on;
+    else if constexpr (PH == kPhaseAAGather)
+      e = ea[L::Opp[i]];
+    else
+      e = obase + (int64_t)L::Opp[i] * on;
+    St::store(dst, e, out, a.f16_scale);
+  };
+  if constexpr (MRT) {
+    // Eq. (8) in the orthogonal moment basis
+    collide_mrt<L, S, INC>(f, sum, rho, ux, uy, uz, gx, gy, gz, a.mrt);
+    static_for<Q>([&](auto I) { put(I, f[decltype(I)::value]); });
+    return;
+  }
+  // BGK collision, Eqs. (2), (3) or (4), (7) + Guo source; store own block entries
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
@@ -183,17 +202,7 @@ __global__ void __launch_bounds__(64 * WPB)
     if constexpr (INC) feq = St::offset ? w * (sum + poly) : w * (rho + poly);
     else feq = St::offset ? w * (sum + rho * poly) : w * rho * (R(1) + poly);
     const R F = w * m * (R(3) * cmug + R(9) * cu * cg);
-    const R out = f[i] + om * (feq - f[i]) + fo * F;
-    // two-copy: own slot i; single-copy gather: where opp(i) was read;
-    // single-copy local: own slot opp(i)
-    int64_t e;
-    if constexpr (PH == kPhaseTwoCopy)
-      e = obase + (int64_t)i * on;
-    else if constexpr (PH == kPhaseAAGather)
-      e = ea[L::Opp[i]];
-    else
-      e = obase + (int64_t)L::Opp[i] * on;
-    St::store(dst, e, out, a.f16_scale);
+    put(I, f[i] + om * (feq - f[i]) + fo * F);
   });
 }
 
@@ -498,6 +507,7 @@ int storage_bytes(int storage) {
 bool variant_supported(const Variant &v) {
   if (storage_bytes(v.storage) == 0) return false;
   if (v.model != LBM_MODEL_QUASI_COMPRESSIBLE && v.model != LBM_MODEL_INCOMPRESSIBLE) return false;
+  if (v.collision != LBM_COLLISION_BGK && v.collision != LBM_COLLISION_MRT) return false;
   if (v.q == 9) return v.ax == 16 && v.ay == 16 && v.az == 1 && v.wpb == 4;
   if (v.q == 19)
     return v.ax == 4 && v.ay == 4 && (v.az == 4 || v.az == 8) &&
@@ -546,8 +556,15 @@ hipError_t launch_step(const Variant &v, int phase, const void *src, void *dst, 
     auto go = [&](auto inc, auto ph) {
       constexpr bool INC = decltype(inc)::value;
       constexpr int PH = decltype(ph)::value;
-      hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, INC, PH>), dim3(blocks_for(a.n_waves, WPB)), dim3(64 * WPB),
-                         0, s, src, dst, a, omega);
+      // MRT is built for 4 waves per workgroup only (the planner rejects others)
+      if constexpr (WPB == 4)
+        if (v.collision == LBM_COLLISION_MRT) {
+          hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, INC, PH, true>), dim3(blocks_for(a.n_waves, WPB)),
+                             dim3(64 * WPB), 0, s, src, dst, a, omega);
+          return;
+        }
+        hipLaunchKernelGGL((k_step<L, AX, AY, AZ, S, WPB, INC, PH, false>), dim3(blocks_for(a.n_waves, WPB)),
+                           dim3(64 * WPB), 0, s, src, dst, a, omega);
     };
     auto by_phase = [&](auto inc) {
       switch (phase) {

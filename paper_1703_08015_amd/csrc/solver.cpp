@@ -71,6 +71,27 @@ void fill_coef(lbm::CollideCoef &c, const double g[3], double omega) {
   }
 }
 
+// Per-class terms of the MRT collision: -s and 1 - s/2, with s = omega for the
+// shear stress, 1 for the conserved moments, the given rates (or the
+// published defaults of the lattice) for the others.
+lbm::MrtRates mrt_rates(const lbm_params *p, double omega) {
+  static const double d19[5] = {1.19, 1.4, 1.2, 1.4, 1.98}, d9[5] = {1.64, 1.54, 1.9, 1.0, 1.0};
+  const double *def = p->lattice == 9 ? d9 : d19;
+  double s[lbm::kMrtClasses];
+  s[lbm::kMrtCons] = 1.0;
+  s[lbm::kMrtNu] = omega;
+  const int cls[5] = {lbm::kMrtE, lbm::kMrtEps, lbm::kMrtQ, lbm::kMrtPi, lbm::kMrtM};
+  for (int k = 0; k < 5; ++k) s[cls[k]] = p->mrt_rates[k] != 0.0 ? p->mrt_rates[k] : def[k];
+  lbm::MrtRates r;
+  for (int c = 0; c < lbm::kMrtClasses; ++c) {
+    r.ms[c] = -s[c];
+    r.mh[c] = 1.0 - 0.5 * s[c];
+    r.msf[c] = (float)r.ms[c];
+    r.mhf[c] = (float)r.mh[c];
+  }
+  return r;
+}
+
 int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
   if (!t || !p) return set_error(LBM_ERR_ARG, "NULL tiles or params");
   if (lbm::storage_bytes(p->storage) == 0) return set_error(LBM_ERR_ARG, "unknown storage form %d", p->storage);
@@ -95,7 +116,12 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
     return set_error(LBM_ERR_ARG, "model = %d", p->model);
   if (p->pattern != LBM_PATTERN_TWO_COPY && p->pattern != LBM_PATTERN_SINGLE_COPY)
     return set_error(LBM_ERR_ARG, "pattern = %d", p->pattern);
+  if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT)
+    return set_error(LBM_ERR_ARG, "collision = %d", p->collision);
   if (p->reserved != 0) return set_error(LBM_ERR_ARG, "reserved field must be 0");
+  for (int k = 0; k < 5; ++k)
+    if (!(p->mrt_rates[k] == 0.0 || (p->mrt_rates[k] > 0.0 && p->mrt_rates[k] < 2.0)))
+      return set_error(LBM_ERR_ARG, "mrt_rates[%d] = %g outside (0, 2)", k, p->mrt_rates[k]);
   int wpb = p->tiles_per_block == 0 ? 4 : p->tiles_per_block;
   if (p->lattice == 9) wpb = 4;  // a 16x16 tile is four wavefronts: one tile per workgroup
   v->q = p->lattice;
@@ -105,9 +131,13 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
   v->storage = p->storage;
   v->wpb = wpb;
   v->model = p->model;
+  v->collision = p->collision;
   if (!lbm::variant_supported(*v))
     return set_error(LBM_ERR_UNSUPPORTED, "lattice D%dQ%d with tile %dx%dx%d and %d waves per block not built",
                      p->lattice == 9 ? 2 : 3, p->lattice, v->ax, v->ay, v->az, p->tiles_per_block);
+  if (p->collision == LBM_COLLISION_MRT && (wpb != 4 || p->store_policy == LBM_STORE_REGULAR))
+    return set_error(LBM_ERR_UNSUPPORTED, "the MRT collision is built for 4 waves per workgroup and non-temporal "
+                                          "stores only");
   return LBM_OK;
 }
 
@@ -425,6 +455,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   a.rho0 = p->rho0;
   a.model = p->model;
   a.aa_phase = s->single_copy ? 0 : -1;
+  a.mrt = mrt_rates(p, s->omega);
   a.f16_scale = std::ldexp(1.0f, p->f16_scale_log2);
   a.f16_inv = std::ldexp(1.0f, -p->f16_scale_log2);
 

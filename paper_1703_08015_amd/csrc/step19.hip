@@ -98,7 +98,7 @@ constexpr int kTwoCopy = kPhaseTwoCopy, kAAGather = kPhaseAAGather, kAALocal = k
 
 // One 4x4x4 tile: gather, collide, store.  Lanes of solid nodes return
 // early; every value the wavefront branches on is uniform.
-template <int S, bool NT, bool INC, int PH>
+template <int S, bool NT, bool INC, int PH, bool MRT>
 __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_, out_ptr<PH, void> dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
                                             const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -180,6 +180,27 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
   });
 
   const CollideCoef &cc = coef[own.sample];
+  // two-copy: own slot i of the other buffer; single-copy gather: where
+  // opp(i) was read; single-copy local: own slot opp(i)
+  auto put = [&](auto I, R out) {
+    constexpr int i = decltype(I)::value;
+    T *blk;
+    uint32_t e;
+    if constexpr (PH == kTwoCopy) {
+      blk = dst + (ooff + (uint32_t)i * on);
+      e = rank;
+    } else if constexpr (PH == kAAGather) {
+      blk = dst;
+      e = ea[L::Opp[i]];
+    } else {
+      blk = dst;
+      e = ooff + (uint32_t)L::Opp[i] * on + rank;
+    }
+    if constexpr (NT)
+      St::store_nt(blk, (int64_t)e, out, a.f16_scale);
+    else
+      St::store(blk, (int64_t)e, out, a.f16_scale);
+  };
   R sum = 0, jx = 0, jy = 0, jz = 0;
   static_for<19>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -202,6 +223,12 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
   } else {
     const R inv = R(1) / rho;
     ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
+  }
+  if constexpr (MRT) {
+    // Eq. (8) in the orthogonal moment basis
+    collide_mrt<L, S, INC>(f, sum, rho, ux, uy, uz, gx, gy, gz, a.mrt);
+    static_for<19>([&](auto I) { put(I, f[decltype(I)::value]); });
+    return;
   }
   const R uu = ux * ux + uy * uy + uz * uz;
   const R ug = ux * gx + uy * gy + uz * gz;
@@ -227,24 +254,7 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
       constexpr bool face = (cx != 0) + (cy != 0) + (cz != 0) == 1;
       out = om1 * f[i] + ((face ? wr1 : wr2) * t2 + (face ? wp1 : wp2));
     }
-    // two-copy: own slot i of the other buffer; single-copy gather: where
-    // opp(i) was read; single-copy local: own slot opp(i)
-    T *blk;
-    uint32_t e;
-    if constexpr (PH == kTwoCopy) {
-      blk = dst + (ooff + (uint32_t)i * on);
-      e = rank;
-    } else if constexpr (PH == kAAGather) {
-      blk = dst;
-      e = ea[L::Opp[i]];
-    } else {
-      blk = dst;
-      e = ooff + (uint32_t)L::Opp[i] * on + rank;
-    }
-    if constexpr (NT)
-      St::store_nt(blk, (int64_t)e, out, a.f16_scale);
-    else
-      St::store(blk, (int64_t)e, out, a.f16_scale);
+    put(I, out);
   });
 }
 
@@ -255,7 +265,7 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 // list[w] if w < *count.  kPersistent: a fixed grid of G wavefronts strides
 // over list[0 .. *count).  The count lives in device memory, so a captured
 // graph stays valid when the active set changes.
-template <int S, int WPB, bool NT, bool INC, int PH, int MODE>
+template <int S, int WPB, bool NT, bool INC, int PH, bool MRT, int MODE>
 __global__ void __launch_bounds__(64 * WPB)
     k_step19(in_ptr<PH, void> src, out_ptr<PH, void> dst, TileArgs a, const NbRec *__restrict__ nrec,
              const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -265,13 +275,14 @@ __global__ void __launch_bounds__(64 * WPB)
   const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
-    step19_tile<S, NT, INC, PH>(gw, src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH, MRT>(gw, src, dst, a, nrec, nrow, rbase, coef);
   } else if constexpr (MODE == kList) {
     if (gw >= (int64_t)*count) return;
-    step19_tile<S, NT, INC, PH>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH, MRT>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
   } else {
     const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
-    for (int64_t k = gw; k < n; k += G) step19_tile<S, NT, INC, PH>(list[k], src, dst, a, nrec, nrow, rbase, coef);
+    for (int64_t k = gw; k < n; k += G)
+      step19_tile<S, NT, INC, PH, MRT>(list[k], src, dst, a, nrec, nrow, rbase, coef);
   }
 }
 
@@ -280,14 +291,20 @@ using IC = std::integral_constant<int, V>;
 template <bool V>
 using BC = std::integral_constant<bool, V>;
 
-// Calls f(storage, waves per block, model, phase) with compile-time constants.
+// Calls f(storage, waves per block, model, phase, MRT) with compile-time constants.
 template <class F>
 hipError_t with_variant(const Variant &v, int phase, F &&f) {
+  // MRT is built for 4 waves per workgroup only (the planner rejects others)
+  auto by_collision = [&](auto s, auto w, auto inc, auto ph) -> hipError_t {
+    if constexpr (decltype(w)::value == 4)
+      if (v.collision == LBM_COLLISION_MRT) return f(s, w, inc, ph, BC<true>{});
+    return f(s, w, inc, ph, BC<false>{});
+  };
   auto by_phase = [&](auto s, auto w, auto inc) -> hipError_t {
     switch (phase) {
-      case kAAGather: return f(s, w, inc, IC<kAAGather>{});
-      case kAALocal: return f(s, w, inc, IC<kAALocal>{});
-      default: return f(s, w, inc, IC<kTwoCopy>{});
+      case kAAGather: return by_collision(s, w, inc, IC<kAAGather>{});
+      case kAALocal: return by_collision(s, w, inc, IC<kAALocal>{});
+      default: return by_collision(s, w, inc, IC<kTwoCopy>{});
     }
   };
   auto by_model = [&](auto s, auto w) -> hipError_t {
@@ -320,9 +337,9 @@ hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst
   if ((phase == kTwoCopy) == (src == dst)) return hipErrorInvalidValue;  // in place exactly for the single copy
   const unsigned blocks =
       mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
-  return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc) -> hipError_t {
+  return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc, auto mc) -> hipError_t {
     constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
-    constexpr bool INC = decltype(ic)::value;
+    constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
       return hipGetLastError();
@@ -330,12 +347,14 @@ hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst
     auto by_mode = [&](auto nt) {
       constexpr bool NT = decltype(nt)::value;
       switch (mode) {
-        case kDirect: return go(k_step19<S, W, NT, INC, PH, kDirect>);
-        case kList: return go(k_step19<S, W, NT, INC, PH, kList>);
-        default: return go(k_step19<S, W, NT, INC, PH, kPersistent>);
+        case kDirect: return go(k_step19<S, W, NT, INC, PH, MRT, kDirect>);
+        case kList: return go(k_step19<S, W, NT, INC, PH, MRT, kList>);
+        default: return go(k_step19<S, W, NT, INC, PH, MRT, kPersistent>);
       }
     };
-    return nontemporal ? by_mode(BC<true>{}) : by_mode(BC<false>{});
+    // MRT is built with non-temporal stores only (the planner rejects others)
+    if constexpr (MRT) return by_mode(BC<true>{});
+    else return nontemporal ? by_mode(BC<true>{}) : by_mode(BC<false>{});
   });
 }
 
@@ -346,12 +365,12 @@ hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, int64_t 
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   // the grid must fit for every phase the solver alternates between
   auto fit = [&](int phase) -> hipError_t {
-    return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc) -> hipError_t {
+    return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc, auto mc) -> hipError_t {
       constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
-      constexpr bool INC = decltype(ic)::value;
+      constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value;
       int k = 0;
-      const hipError_t r =
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_step19<S, W, true, INC, PH, kPersistent>, 64 * W, 0);
+      const hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &k, k_step19<S, W, true, INC, PH, MRT, kPersistent>, 64 * W, 0);
       per = per < 0 ? k : (k < per ? k : per);
       return r;
     });

@@ -30,6 +30,7 @@ KERNEL = {"auto": 0, "generic": 1, "scalar": 2}
 STORE_POLICY = {"auto": 0, "regular": 1, "nontemporal": 2}
 MODEL = {"quasi-compressible": 0, "quasi": 0, "incompressible": 1}
 PATTERN = {"two-copy": 0, "single-copy": 1}
+COLLISION = {"bgk": 0, "mrt": 1}
 
 
 class LbmError(RuntimeError):
@@ -55,7 +56,8 @@ class Params(ctypes.Structure):
         ("g", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("f16_scale_log2", ctypes.c_int32),
         ("tiles_per_block", ctypes.c_int32), ("tile_order", ctypes.c_int32), ("step_kernel", ctypes.c_int32),
         ("store_policy", ctypes.c_int32), ("persistent", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-        ("model", ctypes.c_int32), ("pattern", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("pattern", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("mrt_rates", ctypes.c_double * 5),
     ]
 
 
@@ -241,7 +243,9 @@ class Tiles:
 
 def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
                 tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", persistent=0,
-                graph_steps=0, model="quasi-compressible", pattern="two-copy"):
+                graph_steps=0, model="quasi-compressible", pattern="two-copy", collision="bgk", mrt_rates=None):
+    """mrt_rates: (s_e, s_eps, s_q, s_pi, s_m) of the MRT collision; None or 0 entries take the published
+    defaults of the lattice."""
     p = Params()
     p.lattice = lattice
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
@@ -258,6 +262,9 @@ def make_params(lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0,
     p.graph_steps = int(graph_steps)
     p.model = MODEL[model] if isinstance(model, str) else int(model)
     p.pattern = PATTERN[pattern] if isinstance(pattern, str) else int(pattern)
+    p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
+    for k, r in enumerate(mrt_rates if mrt_rates is not None else ()):
+        p.mrt_rates[k] = float(r)
     return p
 
 
@@ -273,8 +280,8 @@ class Solver:
 
     def __init__(self, tiles, lattice=19, storage="f64", tau=0.7, g=(0.0, 0.0, 0.0), rho0=1.0, f16_scale_log2=20,
                  tiles_per_block=0, tile_order="morton", step_kernel="auto", store_policy="auto", persistent=0,
-                 graph_steps=0, model="quasi-compressible", pattern="two-copy", device="cuda", stream=None,
-                 workspace=None):
+                 graph_steps=0, model="quasi-compressible", pattern="two-copy", collision="bgk", mrt_rates=None,
+                 device="cuda", stream=None, workspace=None):
         """workspace: optional caller-owned device tensor (uint8, at least
         workspace_bytes(tiles, ...) long, 256-byte aligned); by default the
         solver allocates its own."""
@@ -284,7 +291,8 @@ class Solver:
         self.tiles = tiles
         self.q = lattice
         self.params = make_params(lattice, storage, tau, g, rho0, f16_scale_log2, tiles_per_block, tile_order,
-                                  step_kernel, store_policy, persistent, graph_steps, model, pattern)
+                                  step_kernel, store_policy, persistent, graph_steps, model, pattern, collision,
+                                  mrt_rates)
         self.device = torch.device(device)
         n = ctypes.c_size_t()
         _check(lib().lbm_workspace_bytes(tiles._h, ctypes.byref(self.params), ctypes.byref(n)),

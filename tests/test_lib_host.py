@@ -92,6 +92,11 @@ def test_tiling_errors():
     (dict(model=2), lbm.LBM_ERR_ARG),
     (dict(model=-1), lbm.LBM_ERR_ARG),
     (dict(pattern=2), lbm.LBM_ERR_ARG),
+    (dict(collision=5), lbm.LBM_ERR_ARG),
+    (dict(collision="mrt", mrt_rates=(2.5, 0, 0, 0, 0)), lbm.LBM_ERR_ARG),
+    (dict(collision="mrt", mrt_rates=(1.2, -1.0, 0, 0, 0)), lbm.LBM_ERR_ARG),
+    (dict(collision="mrt", tiles_per_block=2), lbm.LBM_ERR_UNSUPPORTED),
+    (dict(collision="mrt", store_policy="regular"), lbm.LBM_ERR_UNSUPPORTED),
 ])
 def test_param_validation(kw, code):
     t = lbm.Tiles(inputs.spheres_3d(16, 0.5, rmin=2, rmax=4, seed=1)[0])
