@@ -63,7 +63,7 @@ def _load():
         lib.ora_collide.argtypes = [I, I, P, dbl, P, P, P]
         lib.ora_mrt_matrix.argtypes = [I, P, P]
         lib.ora_init.argtypes = [I, I, P, P, dbl, P, P, P]
-        lib.ora_step.argtypes = [I, I, P, u32, P, dbl, P, P, P, P, i64, I]
+        lib.ora_step.argtypes = [I, I, P, u32, P, dbl, P, P, P, P, P, i64, I]
         lib.ora_moments.argtypes = [I, I, P, P, P, P, P, P]
         for fn in (lib.ora_lattice, lib.ora_feq, lib.ora_guo, lib.ora_collide, lib.ora_init,
                    lib.ora_step, lib.ora_moments, lib.ora_mrt_matrix):
@@ -160,16 +160,22 @@ def init(q, mask, rho0=1.0, rho=None, u=None, model=QUASI):
     return f
 
 
-def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1, model=QUASI, mrt=None):
+def step(q, mask, f, tau, g, nsteps, periodic=7, nthreads=1, model=QUASI, mrt=None, lid=None):
+    """lid: None or (axis, side, (u_x, u_y, u_z), rho_w): the face of a non-periodic axis beyond the last
+    (side 1) or before the first (side 0) node moves with velocity u_w (moving-wall bounce-back)."""
     """Advance the post-collision state ``f`` by ``nsteps`` steps (in place copy)."""
     mask = np.ascontiguousarray(mask, np.uint8)
     f = np.array(f, np.float64, order="C", copy=True)
     tmp = np.empty_like(f)
     g = np.ascontiguousarray(g, np.float64)
     r = _mrt(mrt)
+    lw = None
+    if lid is not None:
+        axis, side, uw, rho_w = lid
+        lw = np.array([axis, side, uw[0], uw[1], uw[2], rho_w], np.float64)
     _check(_load().ora_step(q, _model(model), _p(_shape3(mask)), _periodic_bits(periodic), _p(mask),
-                            float(tau), _p(g), None if r is None else _p(r), _p(f), _p(tmp), int(nsteps),
-                            int(nthreads)))
+                            float(tau), _p(g), None if r is None else _p(r), None if lw is None else _p(lw), _p(f),
+                            _p(tmp), int(nsteps), int(nthreads)))
     return f
 
 

@@ -40,6 +40,14 @@
  *     written here as polynomials in the velocity c; the shear-stress
  *     moments relax with 1/tau, the others with the given rates;
  *   - a source position outside the domain on a non-periodic axis is solid;
+ *   - a moving wall (the lid of a driven cavity; the paper's dense cavity
+ *     workload gives no boundary rule): the domain face beyond the last (side
+ *     1) or before the first (side 0) node along one non-periodic axis moves
+ *     with velocity u_w; a source beyond that face returns the bounce-back
+ *     value plus 6 w_i rho_w (c_i . u_w) (Ladd's moving-wall rule), with
+ *     rho_w = rho0 in the quasi-compressible model and 1 in the
+ *     incompressible one; the face decides also for diagonal links that
+ *     cross another wall at the same time;
  *   - tau = +infinity gives omega = 0 (pure streaming, used with g = 0).
  *
  * Dense layout everywhere: f[i][z][y][x] (x fastest), mask[z][y][x] with
@@ -370,10 +378,19 @@ int ora_init(int q, int model, const int32_t *shape, const uint8_t *mask,
 }
 
 /* One pull-stream + collide pass from src into dst over fluid nodes. */
+/* Moving wall: lid = {axis, side, u_x, u_y, u_z, rho_w} or NULL. */
+static int beyond_lid(const grid_t *G, const double *lid, const int p[3],
+                      const int c[3]) {
+  if (!lid) return 0;
+  int a = (int)lid[0], side = (int)lid[1];
+  int s = p[a] - c[a];
+  return side ? s >= G->n[a] : s < 0;
+}
+
 static void one_step(const lattice_t *L, int model, const grid_t *G,
                      const uint8_t *mask, double tau, const double g[3],
-                     const double *mrt, const double *src, double *dst,
-                     int nthreads) {
+                     const double *mrt, const double *lid, const double *src,
+                     double *dst, int nthreads) {
   (void)nthreads;
 #pragma omp parallel for num_threads(nthreads) collapse(2) schedule(static)
   for (int z = 0; z < G->n[2]; ++z) {
@@ -385,10 +402,16 @@ static void one_step(const lattice_t *L, int model, const grid_t *G,
         if (mask[n]) continue;
         for (int i = 0; i < L->q; ++i) {
           int64_t s = source_of(G, p, L->c[i]);
-          if (s >= 0 && !mask[s])
+          if (s >= 0 && !mask[s]) {
             f[i] = src[i * G->N + s];
-          else
+          } else {
             f[i] = src[L->opp[i] * G->N + n]; /* half-way bounce-back */
+            if (beyond_lid(G, lid, p, L->c[i])) {
+              double cu = L->c[i][0] * lid[2] + L->c[i][1] * lid[3] +
+                          L->c[i][2] * lid[4];
+              f[i] += 6.0 * L->w[i] * lid[5] * cu;
+            }
+          }
         }
         collide(L, model, f, tau, g, mrt, out);
         for (int i = 0; i < L->q; ++i) dst[i * G->N + n] = out[i];
@@ -401,18 +424,23 @@ static void one_step(const lattice_t *L, int model, const grid_t *G,
  * tmp is caller scratch of the same size as f. */
 int ora_step(int q, int model, const int32_t *shape, uint32_t periodic,
              const uint8_t *mask, double tau, const double *g,
-             const double *mrt, double *f, double *tmp, int64_t nsteps,
-             int nthreads) {
+             const double *mrt, const double *lid, double *f, double *tmp,
+             int64_t nsteps, int nthreads) {
   lattice_t L;
   grid_t G;
   if (get_lattice(q, &L) || !valid_model(model)) return -1;
   if (nthreads < 1) nthreads = 1;
   make_grid(shape, periodic, &G);
+  if (lid) {
+    int a = (int)lid[0];
+    if (a < 0 || a > 2 || G.periodic[a] || (lid[1] != 0.0 && lid[1] != 1.0))
+      return -1; /* a lid sits on a face of a non-periodic axis */
+  }
   /* solid entries of tmp mirror f so that the result is complete either way */
   memcpy(tmp, f, sizeof(double) * (size_t)q * (size_t)G.N);
   double *a = f, *b = tmp;
   for (int64_t t = 0; t < nsteps; ++t) {
-    one_step(&L, model, &G, mask, tau, g, mrt, a, b, nthreads);
+    one_step(&L, model, &G, mask, tau, g, mrt, lid, a, b, nthreads);
     double *s = a;
     a = b;
     b = s;
