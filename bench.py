@@ -48,6 +48,10 @@ def workload(args):
         desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
                 "fluid fraction >= 0.08, seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles"
                 % (model_name(args), args.n, args.seed, args.tau, args.g))
+    elif args.geometry == "cavity":  # the paper's dense workload: a closed box with a moving lid
+        mask, phi = np.zeros((args.n,) * 3, bool), 1.0
+        desc = ("D3Q19 %s, %d^3 lid-driven cavity (walls on every face, the +y face moving at %g along x), "
+                "tau %.2f, no body force, 4x4x4 tiles" % (model_name(args), args.n, args.lid_u, args.tau))
     else:  # dense sanity point
         mask, phi = np.zeros((args.n,) * 3, bool), 1.0
         desc = "D3Q19 %s, %d^3 fully fluid periodic box, tau %.2f, 4x4x4 tiles" % (model_name(args), args.n,
@@ -87,6 +91,13 @@ def step_kernel_key(args):
                                         "nt" if args.store in ("auto", "nontemporal") else "regular",
                                         args.tiles_per_block or 4)
     return kernel, wkey
+
+
+def step_setup(args):
+    """Body force, periodicity and moving lid of the step workload."""
+    if args.geometry == "cavity":
+        return [0.0, 0.0, 0.0], (0, 0, 0), (1, 1, (args.lid_u, 0.0, 0.0))
+    return [args.g, 0.0, 0.0], (1, 1, 1), None
 
 
 def record_traffic(args, argv):
@@ -163,13 +174,15 @@ def cpu_baseline(mask, args):
     # the library's default D3Q19 MRT rates (s_e, s_eps, s_q, s_pi, s_m)
     mrt = (1.19, 1.4, 1.2, 1.4, 1.98) if args.collision == "mrt" else None
     f = dense.init(19, mask, model=model)
-    g = [args.g, 0.0, 0.0]
+    g, per, lid = step_setup(args)
+    if lid is not None:
+        lid = (lid[0], lid[1], lid[2], 1.0)  # rho_w: rho0 = 1 here, and 1 in the incompressible model
     t0 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=7, nthreads=cores, model=model, mrt=mrt)
+    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=per, nthreads=cores, model=model, mrt=mrt, lid=lid)
     dt = time.perf_counter() - t0
     one = max(1, args.cpu_steps // 16)
     t1 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, one, periodic=7, nthreads=1, model=model, mrt=mrt)
+    dense.step(19, mask, f, args.tau, g, one, periodic=per, nthreads=1, model=model, mrt=mrt, lid=lid)
     dt1 = time.perf_counter() - t1
     nf = int((~mask).sum())
     return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
@@ -458,7 +471,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
-    ap.add_argument("--geometry", default="spheres", choices=["spheres", "vessel", "dense"])
+    ap.add_argument("--geometry", default="spheres", choices=["spheres", "vessel", "dense", "cavity"])
+    ap.add_argument("--lid-u", type=float, default=0.05, help="lid velocity of --geometry cavity")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--porosity", type=float, default=0.3)
     ap.add_argument("--seed", type=int, default=0)
@@ -528,12 +542,15 @@ def main():
         return
     copy_ref = copy_reference(torch, args.copy_gib) if args.copy_gib > 0 else None
     mask, phi, desc = workload(args)
-    tiles = lbm.Tiles(mask, (4, 4, 4), (1, 1, 1))
+    g, per, lid = step_setup(args)
+    tiles = lbm.Tiles(mask, (4, 4, 4), per)
     info = tiles.info
-    solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=(args.g, 0.0, 0.0),
+    solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=g,
                         tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
                         tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model,
                         pattern=args.pattern, collision=args.collision)
+    if lid is not None:
+        solver.set_lid(*lid)
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()

@@ -209,6 +209,18 @@ void lbm_destroy(lbm_solver *s);
 /* Change the stream later calls enqueue on. */
 int lbm_set_stream(lbm_solver *s, void *stream);
 
+/* Moving wall: the face of the box along `axis` (0 x, 1 y, 2 z) beyond the
+ * last node (side 1) or before the first (side 0) moves with velocity
+ * u[3] (host), as the lid of a driven cavity (the paper's dense workload,
+ * Sec. 4.1, whose boundary rule it does not state).  A pull from beyond that
+ * face returns the half-way bounce-back value plus 6 w_i rho_w (c_i . u),
+ * with rho_w = rho0 (quasi-compressible) or 1 (incompressible) (Ladd's
+ * moving-wall rule); the face decides also for diagonal links that cross a
+ * second face.  The axis must be non-periodic in every sample (LBM_ERR_ARG
+ * otherwise).  axis = -1 removes the lid.  Applies to every sample of a
+ * batch and to every later step. */
+int lbm_set_lid(lbm_solver *s, int32_t axis, int32_t side, const double *u);
+
 /* Per-sample body acceleration g[3*n_samples] (host), for batches. */
 int lbm_set_sample_force(lbm_solver *s, const double *g);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <type_traits>
 #include <utility>
@@ -152,6 +153,17 @@ struct MrtRates {
   float msf[kMrtClasses], mhf[kMrtClasses];
 };
 
+// Moving wall (the lid of a driven cavity) on the face of a non-periodic axis
+// beyond the last node (side 1) or before the first (side 0): a pull from
+// beyond that face returns the bounce-back value plus corr_i =
+// 6 w_i rho_w (c_i . u_w) (Ladd's moving-wall rule).  axis < 0: no lid.
+struct LidArgs {
+  int32_t axis;
+  int32_t side;
+  double corr[19];
+  float corrf[19];
+};
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0..N-1.
 template <class F, int... I>
 __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
@@ -265,6 +277,7 @@ struct TileArgs {
   int32_t model;           // LBM_MODEL_*
   int32_t aa_phase;        // -1: two copies; single copy: layout of the state (0 or 1, see kernels.hip)
   MrtRates mrt;            // relaxation of the MRT collision
+  LidArgs lid;             // moving wall on one face of the box
 };
 
 // The density that multiplies the velocity terms of the equilibrium and the
@@ -290,26 +303,64 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // f_eq from Eq. (3) or (4), u with the half-force shift; the rows of M are
 // orthogonal, so M^-1 = M^T diag(1/norm).  With every rate 1/tau this is the
 // BGK collision.
+// c.v for a lattice velocity c with components in {-1, 0, 1}, without
+// multiplications (IEEE rules keep 0 * v, so a plain dot product would not
+// fold).
+template <int CX, int CY, int CZ, class R>
+__device__ __forceinline__ R cdot(R x, R y, R z) {
+  R r = R(0);
+  bool first = true;
+  auto add = [&](int c, R v) {
+    if (c == 0) return;
+    const R t = c > 0 ? v : -v;
+    r = first ? t : r + t;
+    first = false;
+  };
+  add(CX, x);
+  add(CY, y);
+  add(CZ, z);
+  return r;
+}
+
 template <class L, int S, bool INC, class R>
-__device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R rho, R ux, R uy, R uz, R gx, R gy, R gz,
+__device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R jz, R rho0, R gx, R gy, R gz,
                                             const MrtRates &mr) {
+  // Every multiply-add is an explicit fma and nothing else is contracted, so
+  // each kernel variant (phase, launch mode) rounds the same way and the
+  // single-copy steps stay bit-identical to the two-copy step.  sum and j
+  // are plain sums of the gathered values.
+#pragma clang fp contract(off)
   constexpr int Q = L::Q;
   constexpr bool off = Store<S>::offset;
+  const R rho = off ? rho0 + sum : sum;
   const R m = velocity_density<INC>(rho);
-  const R uu = ux * ux + uy * uy + uz * uz;
+  R ux, uy, uz;  // Eq. (5) or (6) with the half-force shift
+  if constexpr (INC) {
+    ux = std::fma(R(0.5), gx, jx);
+    uy = std::fma(R(0.5), gy, jy);
+    uz = std::fma(R(0.5), gz, jz);
+  } else {
+    const R inv = R(1) / rho;
+    ux = std::fma(jx, inv, R(0.5) * gx);
+    uy = std::fma(jy, inv, R(0.5) * gy);
+    uz = std::fma(jz, inv, R(0.5) * gz);
+  }
+  const R uu = std::fma(ux, ux, std::fma(uy, uy, uz * uz));
   R d[Q], F[Q];
   static_for<Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
     constexpr R w = (R)L::Wt[i];
-    const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
-    const R cg = R(cx) * gx + R(cy) * gy + R(cz) * gz;
-    const R cmug = (R(cx) - ux) * gx + (R(cy) - uy) * gy + (R(cz) - uz) * gz;
-    const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+    // c has components in {-1, 0, 1}: signed sums of the nonzero terms
+    const R cu = cdot<cx, cy, cz>(ux, uy, uz);
+    const R cg = cdot<cx, cy, cz>(gx, gy, gz);
+    const R ug = std::fma(ux, gx, std::fma(uy, gy, uz * gz));
+    const R poly = std::fma(R(3), cu, std::fma(R(4.5) * cu, cu, R(-1.5) * uu));
     // f_eq (or its offset): w (rho + m poly), w (drho + m poly)
-    const R feq = w * ((off ? sum : rho) + m * poly);
+    const R feq = w * std::fma(m, poly, off ? sum : rho);
     d[i] = f[i] - feq;
-    F[i] = w * m * (R(3) * cmug + R(9) * cu * cg);
+    // Guo source: w m [3 (c - u).g + 9 (c.u)(c.g)]
+    F[i] = (w * m) * std::fma(R(9) * cu, cg, R(3) * (cg - ug));
   });
   static_for<Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -317,9 +368,15 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R rho, R ux, R 
     static_for<Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int c = mrt_row<L>(k, i).value;
-      if constexpr (c != 0) {
-        dm += R(c) * d[i];
-        fm += R(c) * F[i];
+      if constexpr (c == 1) {
+        dm = dm + d[i];
+        fm = fm + F[i];
+      } else if constexpr (c == -1) {
+        dm = dm - d[i];
+        fm = fm - F[i];
+      } else if constexpr (c != 0) {
+        dm = std::fma(R(c), d[i], dm);
+        fm = std::fma(R(c), F[i], fm);
       }
     });
     constexpr int cl = mrt_row<L>(k, 0).cls;
@@ -332,11 +389,16 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R rho, R ux, R 
       ms = (R)mr.msf[cl];
       mh = (R)mr.mhf[cl];
     }
-    const R y = (ms * dm + mh * fm) * inv;
+    const R y = std::fma(ms, dm, mh * fm) * inv;
     static_for<Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int c = mrt_row<L>(k, i).value;
-      if constexpr (c != 0) f[i] += R(c) * y;
+      if constexpr (c == 1)
+        f[i] = f[i] + y;
+      else if constexpr (c == -1)
+        f[i] = f[i] - y;
+      else if constexpr (c != 0)
+        f[i] = std::fma(R(c), y, f[i]);
     });
   });
 }

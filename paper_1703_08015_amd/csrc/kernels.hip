@@ -140,6 +140,22 @@ __global__ void __launch_bounds__(64 * WPB)
     f[i] = St::load(src, addr, a.f16_inv);
     if constexpr (PH == kPhaseAAGather) ea[i] = addr;
   });
+  // moving wall: a source beyond the lid face was bounced back (in the
+  // two-copy and single-copy gather here, in the previous step for the
+  // single-copy local phase); add the wall's momentum term
+  if (a.lid.axis >= 0) {
+    const int ax = a.lid.axis;
+    const int n = a.samples[a.rec[tile].sample].shape[ax];
+    const int p = a.coord[3 * tile + ax] * (ax == 0 ? AX : ax == 1 ? AY : AZ) + (ax == 0 ? x : ax == 1 ? y : z);
+    if (p == (a.lid.side ? n - 1 : 0)) {
+      const int toward = a.lid.side ? -1 : 1;  // c along the axis of a pull from beyond the face
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int ca = ax == 0 ? L::C[i][0] : ax == 1 ? L::C[i][1] : L::C[i][2];
+        if (ca == toward) f[i] += St::offset ? (R)a.lid.corrf[i] : (R)a.lid.corr[i];
+      });
+    }
+  }
 
   // macroscopic moments, Eq. (5) or (6) with the half-force shift
   const SampleRec &smp = a.samples[a.rec[tile].sample];
@@ -184,7 +200,7 @@ __global__ void __launch_bounds__(64 * WPB)
   };
   if constexpr (MRT) {
     // Eq. (8) in the orthogonal moment basis
-    collide_mrt<L, S, INC>(f, sum, rho, ux, uy, uz, gx, gy, gz, a.mrt);
+    collide_mrt<L, S, INC>(f, sum, jx, jy, jz, (R)a.rho0, gx, gy, gz, a.mrt);
     static_for<Q>([&](auto I) { put(I, f[decltype(I)::value]); });
     return;
   }

@@ -307,6 +307,7 @@ struct lbm_solver {
   int64_t dense_nodes = 0;
   std::vector<lbm::SampleRec> samples_h;
   lbm::SampleRec *samples_d = nullptr;
+  std::vector<uint32_t> periodic;  // per sample
   std::vector<lbm::CollideCoef> coef_h;
   lbm::CollideCoef *coef_d = nullptr;
   const lbm::NbRec *nrec_d = nullptr;
@@ -410,6 +411,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
     for (int64_t k = 0; k < t->n_ftiles; ++k) s->list_h[(size_t)k] = (int32_t)k;
     s->count_h = (int32_t)t->n_ftiles;
     s->active_h.assign(t->samples.size(), 1);
+    for (const lbm::Sample &S : t->samples) s->periodic.push_back(S.periodic);
     for (const lbm::Sample &S : t->samples) {
       if (S.n_ftiles == 0) {
         s->entry0.push_back(0);
@@ -456,6 +458,8 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   a.model = p->model;
   a.aa_phase = s->single_copy ? 0 : -1;
   a.mrt = mrt_rates(p, s->omega);
+  a.lid.axis = -1;
+  a.lid.side = 0;
   a.f16_scale = std::ldexp(1.0f, p->f16_scale_log2);
   a.f16_inv = std::ldexp(1.0f, -p->f16_scale_log2);
 
@@ -550,6 +554,42 @@ extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
   // here, so its captured graphs no longer match
   if (!s->p.persistent && s->all_active != all) drop_graphs(s);
   s->all_active = all;
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_lid(lbm_solver *s, int32_t axis, int32_t side, const double *u) {
+  if (!s) return set_error(LBM_ERR_ARG, "lbm_set_lid: NULL solver");
+  lbm::LidArgs &L = s->args.lid;
+  if (axis == -1) {
+    L.axis = -1;
+    drop_graphs(s);
+    return LBM_OK;
+  }
+  if (!u) return set_error(LBM_ERR_ARG, "lbm_set_lid: NULL u");
+  if (axis < 0 || axis > 2 || (s->var.q == 9 && axis == 2))
+    return set_error(LBM_ERR_ARG, "lbm_set_lid: axis = %d", axis);
+  if (side != 0 && side != 1) return set_error(LBM_ERR_ARG, "lbm_set_lid: side = %d", side);
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(u[a])) return set_error(LBM_ERR_ARG, "lbm_set_lid: u[%d] not finite", a);
+  for (size_t k = 0; k < s->periodic.size(); ++k)
+    if ((s->periodic[k] >> axis) & 1u)
+      return set_error(LBM_ERR_ARG, "lbm_set_lid: axis %d is periodic in sample %zu", axis, k);
+  const double rho_w = s->p.model == LBM_MODEL_INCOMPRESSIBLE ? 1.0 : s->p.rho0;
+  for (int i = 0; i < 19; ++i) {
+    double cu = 0.0, w = 0.0;
+    if (s->var.q == 9 && i < 9) {
+      cu = lbm::D2Q9::C[i][0] * u[0] + lbm::D2Q9::C[i][1] * u[1];
+      w = lbm::D2Q9::Wt[i];
+    } else if (s->var.q == 19) {
+      cu = lbm::D3Q19::C[i][0] * u[0] + lbm::D3Q19::C[i][1] * u[1] + lbm::D3Q19::C[i][2] * u[2];
+      w = lbm::D3Q19::Wt[i];
+    }
+    L.corr[i] = 6.0 * w * rho_w * cu;
+    L.corrf[i] = (float)L.corr[i];
+  }
+  L.axis = axis;
+  L.side = side;
+  drop_graphs(s);  // captured launches hold the old arguments
   return LBM_OK;
 }
 

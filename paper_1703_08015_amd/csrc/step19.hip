@@ -178,6 +178,26 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
       if constexpr (PH == kAAGather) ea[i] = e;
     }
   });
+  // moving wall: a source beyond the lid face was bounced back (here, or in
+  // the previous step for the single-copy local phase); add the wall's
+  // momentum term on the lanes of the lattice's first or last row
+  if (a.lid.axis >= 0) {
+    const int ax = a.lid.axis;
+    const int n = a.samples[own.sample].shape[ax];
+    const int row = a.lid.side ? n - 1 : 0;
+    const int t0 = a.coord[3 * tile + ax] * 4;
+    if (row >= t0 && row < t0 + 4) {
+      const int p = t0 + (ax == 0 ? (lane & 3) : ax == 1 ? ((lane >> 2) & 3) : (lane >> 4));
+      if (p == row) {
+        const int toward = a.lid.side ? -1 : 1;  // c along the axis of a pull from beyond the face
+        static_for<19>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          const int ca = ax == 0 ? L::C[i][0] : ax == 1 ? L::C[i][1] : L::C[i][2];
+          if (ca == toward) f[i] += St::offset ? (R)a.lid.corrf[i] : (R)a.lid.corr[i];
+        });
+      }
+    }
+  }
 
   const CollideCoef &cc = coef[own.sample];
   // two-copy: own slot i of the other buffer; single-copy gather: where
@@ -214,6 +234,12 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
     if constexpr (cz < 0) jz -= f[i];
   });
   const R gx = (R)cc.g[0], gy = (R)cc.g[1], gz = (R)cc.g[2];
+  if constexpr (MRT) {
+    // Eq. (8) in the orthogonal moment basis
+    collide_mrt<L, S, INC>(f, sum, jx, jy, jz, (R)a.rho0, gx, gy, gz, a.mrt);
+    static_for<19>([&](auto I) { put(I, f[decltype(I)::value]); });
+    return;
+  }
   const R om = (R)cc.omega, om1 = R(1) - om, fo = R(1) - R(0.5) * om, h = R(4.5) * om;
   const R rho = St::offset ? (R)a.rho0 + sum : sum;
   const R m = velocity_density<INC>(rho);
@@ -223,12 +249,6 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
   } else {
     const R inv = R(1) / rho;
     ux = jx * inv + R(0.5) * gx, uy = jy * inv + R(0.5) * gy, uz = jz * inv + R(0.5) * gz;
-  }
-  if constexpr (MRT) {
-    // Eq. (8) in the orthogonal moment basis
-    collide_mrt<L, S, INC>(f, sum, rho, ux, uy, uz, gx, gy, gz, a.mrt);
-    static_for<19>([&](auto I) { put(I, f[decltype(I)::value]); });
-    return;
   }
   const R uu = ux * ux + uy * uy + uz * uz;
   const R ug = ux * gx + uy * gy + uz * gz;

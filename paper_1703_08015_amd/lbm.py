@@ -93,6 +93,7 @@ def lib():
             "lbm_destroy": (None, [P]),
             "lbm_set_stream": (ctypes.c_int, [P, P]),
             "lbm_set_sample_force": (ctypes.c_int, [P, P]),
+            "lbm_set_lid": (ctypes.c_int, [P, ctypes.c_int32, ctypes.c_int32, P]),
             "lbm_set_active": (ctypes.c_int, [P, P]),
             "lbm_init": (ctypes.c_int, [P, P, P]),
             "lbm_step": (ctypes.c_int, [P, I32]),
@@ -376,6 +377,15 @@ class Solver:
         if g.size != 3 * self.n_samples:
             raise ValueError("need 3 values per sample")
         _check(lib().lbm_set_sample_force(self._h, _np_ptr(g)), "lbm_set_sample_force")
+
+    def set_lid(self, axis, side=1, u=(0.0, 0.0, 0.0)):
+        """Moving wall on the face of non-periodic `axis` beyond the last node (side 1) or before the first
+        (side 0), velocity u; axis=None removes it."""
+        if axis is None:
+            _check(lib().lbm_set_lid(self._h, -1, 0, None), "lbm_set_lid")
+            return
+        uu = np.ascontiguousarray(np.asarray(u, np.float64).reshape(3))
+        _check(lib().lbm_set_lid(self._h, int(axis), int(side), _np_ptr(uu)), "lbm_set_lid")
 
     def set_active(self, active):
         a = np.ascontiguousarray(np.asarray(active).astype(np.uint8).reshape(-1))
