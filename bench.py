@@ -48,6 +48,11 @@ def workload(args):
         desc = ("D3Q19 %s, %d^3 periodic, bifurcating vessel tree r 20->6 (5 generations, "
                 "fluid fraction >= 0.08, seed %d), tau %.2f, g %.0e along x, 4x4x4 tiles"
                 % (model_name(args), args.n, args.seed, args.tau, args.g))
+    elif args.geometry == "channel2d":  # D2Q9: walls at y = 0 and n-1, periodic in x, discs r 3-6 to porosity 0.6
+        mask, phi = inputs.channel_2d(args.n, args.n, porosity=0.6, seed=args.seed, max_tries=20_000_000)
+        desc = ("D2Q9 %s, %d^2 channel (walls at y = 0 and %d, periodic in x), non-overlapping solid discs r 3-6 "
+                "to porosity %.4f (seed %d), tau %.2f, g %.0e along x, 16x16 tiles"
+                % (model_name(args), args.n, args.n - 1, phi, args.seed, args.tau, args.g))
     elif args.geometry == "cavity":  # the paper's dense workload: a closed box with a moving lid
         mask, phi = np.zeros((args.n,) * 3, bool), 1.0
         desc = ("D3Q19 %s, %d^3 lid-driven cavity (walls on every face, the +y face moving at %g along x), "
@@ -82,6 +87,11 @@ def traffic_for(kernel_name, workload_key):
 def step_kernel_key(args):
     """Name of the timed step kernel and the workload key of its traffic record."""
     inc = args.model == "incompressible"
+    if args.geometry == "channel2d":
+        kernel = "k_step<D2Q9,16x16,%s%s%s%s>" % (args.storage, ",incompressible" if inc else "",
+                                                  ",single-copy" if args.pattern == "single-copy" else "",
+                                                  ",mrt" if args.collision == "mrt" else "")
+        return kernel, "%s_%d_%s_generic_%s" % (args.geometry, args.n, args.storage, args.order)
     kernel = "%s<D3Q19,4x4x4,%s%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
                                            ",incompressible" if inc else "",
                                            ",single-copy" if args.pattern == "single-copy" else "",
@@ -94,10 +104,12 @@ def step_kernel_key(args):
 
 
 def step_setup(args):
-    """Body force, periodicity and moving lid of the step workload."""
+    """Body force, periodicity, moving lid, lattice and tile of the step workload."""
     if args.geometry == "cavity":
-        return [0.0, 0.0, 0.0], (0, 0, 0), (1, 1, (args.lid_u, 0.0, 0.0))
-    return [args.g, 0.0, 0.0], (1, 1, 1), None
+        return [0.0, 0.0, 0.0], (0, 0, 0), (1, 1, (args.lid_u, 0.0, 0.0)), 19, (4, 4, 4)
+    if args.geometry == "channel2d":
+        return [args.g, 0.0, 0.0], (1, 0, 0), None, 9, (16, 16, 1)
+    return [args.g, 0.0, 0.0], (1, 1, 1), None, 19, (4, 4, 4)
 
 
 def record_traffic(args, argv):
@@ -130,7 +142,8 @@ def record_traffic(args, argv):
         raise SystemExit("no %s dispatches in the counter runs" % csv_name)
     fb = sum(fk) / len(fk) * 1024 * f_scale
     wb = sum(wk) / len(wk) * 1024 * w_scale
-    files = ["paper_1703_08015_amd/csrc/%s" % ("kernels.hip" if args.kernel == "generic" else "step19.hip"),
+    generic = args.kernel == "generic" or args.geometry == "channel2d"
+    files = ["paper_1703_08015_amd/csrc/%s" % ("kernels.hip" if generic else "step19.hip"),
              "paper_1703_08015_amd/csrc/device.h"]
     src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in files)
     cmd = " ".join(["python3", "bench.py"] + argv)
@@ -173,21 +186,23 @@ def cpu_baseline(mask, args):
     model = dense.INCOMPRESSIBLE if args.model == "incompressible" else dense.QUASI
     # the library's default D3Q19 MRT rates (s_e, s_eps, s_q, s_pi, s_m)
     mrt = (1.19, 1.4, 1.2, 1.4, 1.98) if args.collision == "mrt" else None
-    f = dense.init(19, mask, model=model)
-    g, per, lid = step_setup(args)
+    g, per, lid, q, _ = step_setup(args)
+    if q == 9:
+        mrt = (1.64, 1.54, 1.9, 1.0, 1.0) if args.collision == "mrt" else None
+    f = dense.init(q, mask, model=model)
     if lid is not None:
         lid = (lid[0], lid[1], lid[2], 1.0)  # rho_w: rho0 = 1 here, and 1 in the incompressible model
     t0 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, args.cpu_steps, periodic=per, nthreads=cores, model=model, mrt=mrt, lid=lid)
+    dense.step(q, mask, f, args.tau, g, args.cpu_steps, periodic=per, nthreads=cores, model=model, mrt=mrt, lid=lid)
     dt = time.perf_counter() - t0
     one = max(1, args.cpu_steps // 16)
     t1 = time.perf_counter()
-    dense.step(19, mask, f, args.tau, g, one, periodic=per, nthreads=1, model=model, mrt=mrt, lid=lid)
+    dense.step(q, mask, f, args.tau, g, one, periodic=per, nthreads=1, model=model, mrt=mrt, lid=lid)
     dt1 = time.perf_counter() - t1
     nf = int((~mask).sum())
     return {"value": nf * args.cpu_steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%d steps of the full %d^3 geometry (%d non-solid nodes), FP64 dense C oracle, OpenMP, "
-                      "%.1f s" % (args.cpu_steps, args.n, nf, dt),
+            "sample": "%d steps of the full %d^%d geometry (%d non-solid nodes), FP64 dense C oracle, OpenMP, "
+                      "%.1f s" % (args.cpu_steps, args.n, 2 if q == 9 else 3, nf, dt),
             "single_thread_mlups": nf * one / dt1 / 1e6, "single_thread_steps": one, "cpu_model": _cpu_model()}
 
 
@@ -471,7 +486,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
-    ap.add_argument("--geometry", default="spheres", choices=["spheres", "vessel", "dense", "cavity"])
+    ap.add_argument("--geometry", default="spheres", choices=["spheres", "vessel", "dense", "cavity", "channel2d"])
     ap.add_argument("--lid-u", type=float, default=0.05, help="lid velocity of --geometry cavity")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--porosity", type=float, default=0.3)
@@ -508,6 +523,8 @@ def main():
                          "(FETCH_SIZE, WRITE_SIZE) of this command line in profiles/traffic.json")
     argv = sys.argv[1:]
     args = ap.parse_args()
+    if args.mode == "step" and args.geometry == "channel2d" and args.n == 256:
+        args.n = 4096  # a D2Q9 domain large enough to hide launch gaps
     if args.record_traffic:
         k = argv.index("--record-traffic")
         record_traffic(args, argv[:k] + argv[k + 3:])
@@ -542,10 +559,10 @@ def main():
         return
     copy_ref = copy_reference(torch, args.copy_gib) if args.copy_gib > 0 else None
     mask, phi, desc = workload(args)
-    g, per, lid = step_setup(args)
-    tiles = lbm.Tiles(mask, (4, 4, 4), per)
+    g, per, lid, q, tile = step_setup(args)
+    tiles = lbm.Tiles(mask, tile, per)
     info = tiles.info
-    solver = lbm.Solver(tiles, lattice=19, storage=args.storage, tau=args.tau, g=g,
+    solver = lbm.Solver(tiles, lattice=q, storage=args.storage, tau=args.tau, g=g,
                         tiles_per_block=args.tiles_per_block, f16_scale_log2=args.f16_scale_log2,
                         tile_order=args.order, step_kernel=args.kernel, store_policy=args.store, model=args.model,
                         pattern=args.pattern, collision=args.collision)
@@ -573,7 +590,7 @@ def main():
         raise RuntimeError("non-finite state after the timed steps")
 
     nf = info["n_fluid"]
-    q, sd = 19, SD[args.storage]
+    sd = SD[args.storage]
     mlups = nf * args.steps / wall / 1e6
     alg_bytes = nf * 2 * q * sd  # Eq. (10) per non-solid node, per launch
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
@@ -597,7 +614,7 @@ def main():
             "workload": desc,
             "n_fluid": nf, "n_ftiles": info["n_ftiles"], "n_tiles": info["n_tiles"],
             "phi": round(info["phi"], 4), "phi_t": round(info["phi_t"], 4),
-            "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * 19 * SD[args.storage],
+            "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * q * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
             "model": args.model, "pattern": args.pattern, "collision": args.collision,

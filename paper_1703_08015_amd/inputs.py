@@ -63,24 +63,35 @@ def channel_2d(nx=64, ny=64, porosity=0.6, rmin=3.0, rmax=6.0, seed=0, discs=Tru
     solid[0, 0, :] = True
     solid[0, ny - 1, :] = True
     rng = np.random.default_rng(seed)
-    placed = []
     total = nx * ny
     n_solid = int(solid.sum())
     tries = 0
+    # placed discs bucketed on a grid of cells at least 2 rmax + 1 wide, so a
+    # candidate is tested against the discs of the 3x3 cells around it only
+    # (the same acceptance rule as testing all of them)
+    cell = 2.0 * rmax + 1.0
+    ncx, ncy = max(1, int(nx // cell)), max(1, int(ny // cell))
+    wx, wy = nx / ncx, ny / ncy
+    buckets = {}
     while discs and (total - n_solid) / total > porosity and tries < max_tries:
         tries += 1
         r = rng.uniform(rmin, rmax)
         cx = rng.uniform(0, nx)
         cy = rng.uniform(1 + r, ny - 2 - r)
         ok = True
-        for (px, py, pr) in placed:
-            dx = _wrap_delta(cx - px, nx, True)
-            if dx * dx + (cy - py) ** 2 < (r + pr + 1.0) ** 2:
-                ok = False
+        bx, by = int(cx // wx) % ncx, min(int(cy // wy), ncy - 1)
+        near = {((bx + dx) % ncx, by + dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1) if 0 <= by + dy < ncy}
+        for key in near:
+            for (px, py, pr) in buckets.get(key, ()):
+                ddx = _wrap_delta(cx - px, nx, True)
+                if ddx * ddx + (cy - py) ** 2 < (r + pr + 1.0) ** 2:
+                    ok = False
+                    break
+            if not ok:
                 break
         if not ok:
             continue
-        placed.append((cx, cy, r))
+        buckets.setdefault((bx, by), []).append((cx, cy, r))
         sub = solid[0:1]
         n_solid += _stamp_ball(sub, (cx, cy, 0.0), r, (True, False, False))
     return solid, (total - n_solid) / total
