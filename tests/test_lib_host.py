@@ -6,6 +6,7 @@ import math
 
 import numpy as np
 import pytest
+from hypothesis import given, settings, strategies as st
 
 from oracle import dense
 from oracle import tiles as otiles
@@ -48,6 +49,34 @@ def test_tiles_bitexact_vs_oracle(name, mask, tile, periodic):
     assert i["n_ftiles"] == o["n_ftiles"] and i["n_fluid"] == o["n_fluid"] and i["n_tiles"] == o["n_tiles"]
     assert i["phi"] == o["phi"] and math.isclose(i["phi_t"], o["phi_t"], rel_tol=1e-15)
     assert tuple(i["grid"]) == tuple(o["grid"])
+
+
+@settings(max_examples=80, deadline=None, derandomize=True)
+@given(st.data())
+def test_tiles_random_masks_bitexact(data):
+    """Random masks of random shape, solid fraction and periodicity, for every
+    tile shape: the library's tiling equals the oracle's bit for bit (periodic
+    axes are drawn as multiples of the tile edge, as the library requires)."""
+    tile = data.draw(st.sampled_from([(4, 4, 4), (4, 4, 8), (16, 16, 1)]))
+    per = tuple(data.draw(st.booleans()) for _ in range(3))
+    shape = []
+    for a in range(3):
+        if tile == (16, 16, 1) and a == 2:
+            shape.append(1)
+            continue
+        hi = 40 if tile[a] == 16 else 14
+        n = data.draw(st.integers(1, hi))
+        if per[a]:
+            n = -(-n // tile[a]) * tile[a]
+        shape.append(n)
+    density = data.draw(st.floats(0.0, 1.0))
+    seed = data.draw(st.integers(0, 2 ** 31))
+    mask = np.random.default_rng(seed).random(shape[::-1]) < density  # (nz, ny, nx)
+    t = lbm.Tiles(mask, tile, per)
+    e, o = t.export(), otiles.tile(mask, tile, per)
+    for k in ("tile_map", "tile_coord", "nbr", "fluid"):
+        assert np.array_equal(e[k], o[k]), k
+    assert t.info["n_fluid"] == o["n_fluid"] and t.info["n_ftiles"] == o["n_ftiles"]
 
 
 def test_tiles_concat_offsets_rows():
