@@ -51,6 +51,11 @@ hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, 
                           hipStream_t s);
 hipError_t launch_export(const Variant &v, const void *src, const TileArgs &a, double *dense, hipStream_t s);
 hipError_t launch_import(const Variant &v, void *dst, const TileArgs &a, const double *dense, hipStream_t s);
+// Moving wall: add the wall's term to the bounce-back entries that the lid
+// nodes of the listed tiles pull next step (slot opp(i) of the two-copy
+// source when own_slot == 0, slot i of the single copy when 1).
+hipError_t launch_lid_fixup(const Variant &v, void *buf, const TileArgs &a, const int32_t *tiles, int64_t n_tiles,
+                            int own_slot, hipStream_t s);
 // per-wave partial sums: 4 per wave (mass, rho u) ...
 hipError_t launch_reduce_partial(const Variant &v, const void *src, const TileArgs &a, double *part,
                                  hipStream_t s);

@@ -140,23 +140,6 @@ __global__ void __launch_bounds__(64 * WPB)
     f[i] = St::load(src, addr, a.f16_inv);
     if constexpr (PH == kPhaseAAGather) ea[i] = addr;
   });
-  // moving wall: a source beyond the lid face was bounced back (in the
-  // two-copy and single-copy gather here, in the previous step for the
-  // single-copy local phase); add the wall's momentum term
-  if (a.lid.axis >= 0) {
-    const int ax = a.lid.axis;
-    const int n = a.samples[a.rec[tile].sample].shape[ax];
-    const int p = a.coord[3 * tile + ax] * (ax == 0 ? AX : ax == 1 ? AY : AZ) + (ax == 0 ? x : ax == 1 ? y : z);
-    if (p == (a.lid.side ? n - 1 : 0)) {
-      const int toward = a.lid.side ? -1 : 1;  // c along the axis of a pull from beyond the face
-      static_for<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const int ca = ax == 0 ? L::C[i][0] : ax == 1 ? L::C[i][1] : L::C[i][2];
-        if (ca == toward) f[i] += St::offset ? (R)a.lid.corrf[i] : (R)a.lid.corr[i];
-      });
-    }
-  }
-
   // macroscopic moments, Eq. (5) or (6) with the half-force shift
   const SampleRec &smp = a.samples[a.rec[tile].sample];
   const R gx = (R)smp.g[0], gy = (R)smp.g[1], gz = (R)smp.g[2];
@@ -409,6 +392,41 @@ __global__ void __launch_bounds__(256) k_import(void *dst_, TileArgs a, const do
   });
 }
 
+// Moving wall (the lid of a driven cavity).  The value that a lid node x
+// pulls next step for a direction i from beyond the lid face is its own
+// bounce-back value f*_opp(i)(x), and no other node reads that entry; so the
+// wall's term corr_i = 6 w_i rho_w (c_i . u_w) is added to it just before the
+// step, and the step's gather sees exactly f*_opp(i)(x) + corr_i.  The entry
+// is slot opp(i) of the node in the two-copy source, slot i in either layout
+// of the single copy.  One wavefront per 64 nodes of a listed tile (the
+// tiles holding the lattice's first or last row along the lid's axis).
+template <class L, int AX, int AY, int AZ, int S>
+__global__ void __launch_bounds__(256)
+    k_lid_fixup(void *buf_, TileArgs a, const int32_t *__restrict__ tiles, int64_t n_waves, int own_slot) {
+  using St = Store<S>;
+  using R = typename St::R;
+  constexpr int W = AX * AY * AZ / 64;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= n_waves) return;
+  const NodeCtx<AX, AY, AZ> c = node_ctx<AX, AY, AZ>(a, (int64_t)tiles[gw / W] * W + gw % W);
+  if (!c.fluid || a.samples[c.sample].frozen) return;  // a frozen sample keeps its state
+  const int ax = a.lid.axis;
+  const int x = c.ell % AX, y = (c.ell / AX) % AY, z = c.ell / (AX * AY);
+  const int p = a.coord[3 * c.tile + ax] * (ax == 0 ? AX : ax == 1 ? AY : AZ) + (ax == 0 ? x : ax == 1 ? y : z);
+  const int n = a.samples[c.sample].shape[ax];
+  if (p != (a.lid.side ? n - 1 : 0)) return;
+  const int toward = a.lid.side ? -1 : 1;  // c along the axis of a pull from beyond the face
+  typename St::T *buf = static_cast<typename St::T *>(buf_);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const int ca = ax == 0 ? L::C[i][0] : ax == 1 ? L::C[i][1] : L::C[i][2];
+    if (ca != toward) return;
+    const int64_t e = c.entry + (int64_t)(own_slot ? i : L::Opp[i]) * c.n;
+    const R v = St::load(buf, e, a.f16_inv) + (St::offset ? (R)a.lid.corrf[i] : (R)a.lid.corr[i]);
+    St::store(buf, e, v, a.f16_scale);
+  });
+}
+
 // Fixed-order wavefront sum (butterfly); every lane ends with the total.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -655,6 +673,17 @@ hipError_t launch_residual_partial(const Variant &v, const void *src, const Tile
   return dispatch(aux(v), [&]<class L, int AX, int AY, int AZ, int S, int WPB>() {
     hipLaunchKernelGGL((k_residual_partial<L, AX, AY, AZ, S>), dim3(blocks_for(a.n_waves, 4)), dim3(256), 0, s,
                        src, a, uref, part, accumulate);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_lid_fixup(const Variant &v, void *buf, const TileArgs &a, const int32_t *tiles, int64_t n_tiles,
+                            int own_slot, hipStream_t s) {
+  if (n_tiles == 0) return hipSuccess;
+  const int64_t waves = n_tiles * (v.ax * v.ay * v.az / 64);
+  return dispatch(aux(v), [&]<class L, int AX, int AY, int AZ, int S, int WPB>() {
+    hipLaunchKernelGGL((k_lid_fixup<L, AX, AY, AZ, S>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, buf, a, tiles,
+                       waves, own_slot);
     return hipGetLastError();
   });
 }

@@ -24,7 +24,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every workspace array, plus the host tables to upload.
 struct Plan {
-  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, rbase, list, count, part, chunk, out,
+  size_t buf[2], rec, fluid, pre, nbr, coord, nbase, samples, coef, nrec, nrow, rbase, list, lid, count, part, chunk, out,
       uref, total;
   int64_t entries = 0;  // PDF entries per copy (with region alignment padding)
   // device tables in the solver's internal tile order
@@ -280,6 +280,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.nrow = take(P.nrow_h.size() * sizeof(uint32_t));
   P.rbase = take(P.rbase_h.size() * sizeof(uint32_t));
   P.list = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
+  P.lid = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
   P.count = take(sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
   P.chunk = take(t->samples.size() * (size_t)lbm::reduce_chunks() * 4 * sizeof(double));
@@ -315,6 +316,9 @@ struct lbm_solver {
   const uint32_t *rbase_d = nullptr;
   // active tile list (batches) and the launch mode of the scalar-mask step
   int32_t *list_d = nullptr, *count_d = nullptr;
+  // moving wall: tiles holding the lattice's first or last row along its axis
+  int32_t *lid_tiles_d = nullptr;
+  int64_t n_lid_tiles = 0;
   std::vector<int32_t> list_h;
   int32_t count_h = 0;
   std::vector<uint8_t> active_h;
@@ -404,6 +408,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->nrow_d = reinterpret_cast<const uint32_t *>(base + P.nrow);
   s->rbase_d = reinterpret_cast<const uint32_t *>(base + P.rbase);
   s->list_d = reinterpret_cast<int32_t *>(base + P.list);
+  s->lid_tiles_d = reinterpret_cast<int32_t *>(base + P.lid);
   s->count_d = reinterpret_cast<int32_t *>(base + P.count);
   s->storage_bytes = lbm::storage_bytes(v.storage);
   try {
@@ -562,6 +567,7 @@ extern "C" int lbm_set_lid(lbm_solver *s, int32_t axis, int32_t side, const doub
   lbm::LidArgs &L = s->args.lid;
   if (axis == -1) {
     L.axis = -1;
+    s->n_lid_tiles = 0;
     drop_graphs(s);
     return LBM_OK;
   }
@@ -587,6 +593,35 @@ extern "C" int lbm_set_lid(lbm_solver *s, int32_t axis, int32_t side, const doub
     L.corr[i] = 6.0 * w * rho_w * cu;
     L.corrf[i] = (float)L.corr[i];
   }
+  // the tiles that hold the lid row of their sample (tile tables back from the device)
+  const int64_t nft = s->args.n_waves / s->words;
+  std::vector<int32_t> coord, lid;
+  std::vector<lbm::TileRec> rec;
+  try {
+    coord.resize((size_t)(3 * nft));
+    rec.resize((size_t)nft);
+  } catch (const std::bad_alloc &) {
+    return set_error(LBM_ERR_NOMEM, "lbm_set_lid: out of host memory");
+  }
+  if (nft > 0) {
+    HIP_TRY(hipMemcpyAsync(coord.data(), s->args.coord, coord.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(rec.data(), s->args.rec, rec.size() * sizeof(lbm::TileRec), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  const int edge = axis == 0 ? s->var.ax : axis == 1 ? s->var.ay : s->var.az;
+  for (int64_t k = 0; k < nft; ++k) {
+    const int n = s->samples_h[(size_t)rec[(size_t)k].sample].shape[axis];
+    const int row = side ? n - 1 : 0, t0 = coord[(size_t)(3 * k + axis)] * edge;
+    if (row >= t0 && row < t0 + edge) lid.push_back((int32_t)k);
+  }
+  if (!lid.empty()) {
+    HIP_TRY(hipMemcpyAsync(s->lid_tiles_d, lid.data(), lid.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  s->n_lid_tiles = (int64_t)lid.size();
   L.axis = axis;
   L.side = side;
   drop_graphs(s);  // captured launches hold the old arguments
@@ -629,6 +664,11 @@ extern "C" int lbm_init(lbm_solver *s, const double *rho, const double *u) {
 // Enqueue one step from copy (two copies) or layout (single copy) `from` on `st`.
 static hipError_t enqueue_step(lbm_solver *s, int from, hipStream_t st) {
   const int phase = !s->single_copy ? lbm::kPhaseTwoCopy : (from == 0 ? lbm::kPhaseAAGather : lbm::kPhaseAALocal);
+  if (s->args.lid.axis >= 0 && s->n_lid_tiles > 0) {
+    const hipError_t e =
+        lbm::launch_lid_fixup(s->var, s->buf[from], s->args, s->lid_tiles_d, s->n_lid_tiles, s->single_copy, st);
+    if (e != hipSuccess) return e;
+  }
   if (s->scalar_mask) {
     const int mode = s->p.persistent ? 2 : (s->all_active ? 0 : 1);
     return lbm::launch_step19(s->var, phase, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d,

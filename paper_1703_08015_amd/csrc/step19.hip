@@ -178,27 +178,6 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
       if constexpr (PH == kAAGather) ea[i] = e;
     }
   });
-  // moving wall: a source beyond the lid face was bounced back (here, or in
-  // the previous step for the single-copy local phase); add the wall's
-  // momentum term on the lanes of the lattice's first or last row
-  if (a.lid.axis >= 0) {
-    const int ax = a.lid.axis;
-    const int n = a.samples[own.sample].shape[ax];
-    const int row = a.lid.side ? n - 1 : 0;
-    const int t0 = a.coord[3 * tile + ax] * 4;
-    if (row >= t0 && row < t0 + 4) {
-      const int p = t0 + (ax == 0 ? (lane & 3) : ax == 1 ? ((lane >> 2) & 3) : (lane >> 4));
-      if (p == row) {
-        const int toward = a.lid.side ? -1 : 1;  // c along the axis of a pull from beyond the face
-        static_for<19>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          const int ca = ax == 0 ? L::C[i][0] : ax == 1 ? L::C[i][1] : L::C[i][2];
-          if (ca == toward) f[i] += St::offset ? (R)a.lid.corrf[i] : (R)a.lid.corr[i];
-        });
-      }
-    }
-  }
-
   const CollideCoef &cc = coef[own.sample];
   // two-copy: own slot i of the other buffer; single-copy gather: where
   // opp(i) was read; single-copy local: own slot opp(i)
