@@ -289,9 +289,20 @@ __device__ __forceinline__ R velocity_density(R rho) {
   else return rho;
 }
 
-// Workgroup -> logical block remap: the hardware hands workgroups to the 8
-// XCDs round-robin; this gives each XCD one contiguous range of blocks (and
-// so of tiles), keeping neighbour tiles inside one XCD's L2.
+// Workgroup -> logical block remaps.  The hardware hands workgroups to the 8
+// XCDs round-robin.  xcd_remap gives each XCD one contiguous range of blocks
+// (and so of tiles), keeping neighbour tiles inside one XCD's L2.
+// xcd_chunk gives XCD k the chunks k, k+8, k+16, ... of C consecutive blocks:
+// neighbours stay together within a chunk while all XCDs stream through
+// neighbouring memory at the same time (blocks past the last whole round of
+// 8 C keep their index, so the map stays a bijection).
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nb, int64_t C) {
+  const int64_t full = nb / (8 * C) * (8 * C);
+  if (b >= full) return b;
+  const int64_t k = b & 7, i = b >> 3;
+  return ((i / C) * 8 + k) * C + i % C;
+}
+
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   const int64_t k = b & 7, q = nb >> 3, r = nb & 7;
   return k * q + (k < r ? k : r) + (b >> 3);

@@ -271,7 +271,12 @@ __global__ void __launch_bounds__(64 * WPB)
              const CollideCoef *__restrict__ coef, const int32_t *__restrict__ list,
              const int32_t *__restrict__ count) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  // XCD assignment, chosen per form by measurement: chunks of 8 blocks for
+  // the two-copy FP64/FP32 BGK step, 16 for the single copy, one contiguous
+  // range per XCD for FP16, MRT and the persistent grid
+  constexpr int kChunk = (S == LBM_F16_OFFSET || MRT || MODE == kPersistent) ? 0 : (PH == kTwoCopy ? 8 : 16);
+  const int64_t blk = kChunk ? xcd_chunk(blockIdx.x, gridDim.x, kChunk) : xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t gw = blk * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
     step19_tile<S, NT, INC, PH, MRT>(gw, src, dst, a, nrec, nrow, rbase, coef);
