@@ -10,6 +10,9 @@ channels-last, shaped (nz, ny, nx, C).  Definitions:
                               first maximum in the order a = az*4 + ay*2 + ax
   dense(x, w, b)           = x @ w.T + b                                   (1x1x1 convolution)
 
+conv3_at, up2_at and maxpool2_at evaluate the same definitions at chosen
+voxels only, for checks on grids too large to evaluate whole.
+
 and their gradients (backward data and weights), written as the adjoints of
 these linear maps.
 """
@@ -33,6 +36,16 @@ def conv3(x, w, b=None):
     return y if b is None else y + b
 
 
+def conv3_at(x, w, b, nodes):
+    """conv3(x, w, b) at the voxels nodes[k] = (z, y, x) only: shape (K, n_out)."""
+    nz, ny, nx, _ = x.shape
+    z, y_, x_ = nodes[:, 0], nodes[:, 1], nodes[:, 2]
+    y = np.zeros((len(nodes), w.shape[0]))
+    for t, (dz, dy, dx) in enumerate(OFFS):
+        y += x[(z + dz) % nz, (y_ + dy) % ny, (x_ + dx) % nx, :] @ w[:, t, :].T
+    return y if b is None else y + b
+
+
 def conv3_backward(x, w, dy):
     """(dx, dw, db) of conv3 for output gradient dy."""
     dx = np.zeros(x.shape)
@@ -52,6 +65,14 @@ def up2(x, w, b=None):
     return y if b is None else y + b
 
 
+def up2_at(x, w, b, nodes):
+    """up2(x, w, b) at the fine voxels nodes[k] = (z, y, x) only: shape (K, n_out)."""
+    a = (nodes[:, 0] & 1) * 4 + (nodes[:, 1] & 1) * 2 + (nodes[:, 2] & 1)
+    xs = x[nodes[:, 0] // 2, nodes[:, 1] // 2, nodes[:, 2] // 2, :]
+    y = np.einsum("kc,knc->kn", xs, np.transpose(w, (1, 0, 2))[a])
+    return y if b is None else y + b
+
+
 def up2_backward(x, w, dy):
     dx = np.zeros(x.shape)
     dw = np.zeros(w.shape)
@@ -67,6 +88,12 @@ def maxpool2(x):
     blocks = np.stack([x[az::2, ay::2, ax::2, :] for (az, ay, ax) in CORNERS], axis=0)
     arg = np.argmax(blocks, axis=0)  # first maximum in corner order
     return blocks.max(axis=0), arg.astype(np.uint8)
+
+
+def maxpool2_at(x, nodes):
+    """maxpool2(x)[0] at the coarse voxels nodes[k] = (z, y, x) only: shape (K, C)."""
+    z, y, x_ = 2 * nodes[:, 0], 2 * nodes[:, 1], 2 * nodes[:, 2]
+    return np.max(np.stack([x[z + az, y + ay, x_ + ax, :] for (az, ay, ax) in CORNERS]), axis=0)
 
 
 def maxpool2_backward(arg, dy):

@@ -149,3 +149,21 @@ def test_distance_is_zero_on_solid_and_one_lipschitz_along_links():
         sh = np.roll(d, shift=(-dz, -dy, -dx), axis=(0, 1, 2))
         assert np.all(np.abs(sh - d) <= np.sqrt(abs(dx) + abs(dy) + abs(dz)) + 1e-12)
     assert np.all(np.isinf(nn.distance(np.zeros((3, 3, 3), bool))))
+
+
+def test_layers_at_chosen_voxels_equal_the_whole_grid():
+    """conv3_at, up2_at and maxpool2_at are the whole-grid layers read at chosen voxels, wrap included."""
+    x = rng.normal(size=(6, 4, 8, 3))
+    w = rng.normal(size=(5, 27, 3))
+    b = rng.normal(size=5)
+    nodes = np.argwhere(np.ones(x.shape[:3], bool))
+    full = nn.conv3(x, w, b)
+    assert np.allclose(nn.conv3_at(x, w, b, nodes), full[nodes[:, 0], nodes[:, 1], nodes[:, 2]], rtol=1e-13,
+                       atol=1e-13)
+    wu = rng.normal(size=(2, 8, 3))
+    fine = nn.up2(x, wu, b[:2])
+    fn = np.argwhere(np.ones(fine.shape[:3], bool))
+    assert np.allclose(nn.up2_at(x, wu, b[:2], fn), fine[fn[:, 0], fn[:, 1], fn[:, 2]], rtol=1e-13, atol=1e-13)
+    pooled, _ = nn.maxpool2(x)
+    pn = np.argwhere(np.ones(pooled.shape[:3], bool))
+    assert np.array_equal(nn.maxpool2_at(x, pn), pooled[pn[:, 0], pn[:, 1], pn[:, 2]])
