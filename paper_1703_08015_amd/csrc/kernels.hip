@@ -77,8 +77,13 @@ __device__ __forceinline__ int lane_rank(uint64_t m) {
 }
 
 // ---- fused step -----------------------------------------------------------------
+// The two-copy D2Q9 BGK step asks for 8 waves per SIMD: left to itself the
+// compiler clusters the loads of a 16x16 tile into 76 VGPRs (6 waves), where
+// 56 registers with no extra instructions give all 8 (+5% measured; the
+// single-copy phases measured slower with 8 and keep the compiler's choice)
 template <class L, int AX, int AY, int AZ, int S, int WPB, bool INC, int PH, bool MRT>
 __global__ void __launch_bounds__(64 * WPB)
+    __attribute__((amdgpu_waves_per_eu(L::Q == 9 && !MRT && PH == kPhaseTwoCopy ? 8 : 1)))
     k_step(in_ptr<PH, void> src_, out_ptr<PH, void> dst_, TileArgs a, double omega_d) {
   using St = Store<S>;
   using T = typename St::T;

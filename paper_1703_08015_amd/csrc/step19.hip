@@ -176,11 +176,12 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
       e = select_lanes(from_fluid, e, ooff + (uint32_t)bb * on + rank);
       f[i] = St::load(src, (int64_t)e, a.f16_inv);
       if constexpr (PH == kAAGather) ea[i] = e;
-      // FP32 two-copy BGK: keep each load where its address is ready, so the
-      // wavefront's loads overlap its own remaining address work instead of
-      // waiting for all 19 addresses (+2-4% measured; FP64 is level and FP16,
-      // whose table reads then stop batching, loses half its rate)
-      if constexpr (S == LBM_F32_OFFSET && PH == kTwoCopy && !MRT) __builtin_amdgcn_sched_barrier(0);
+      // FP64 and FP32 two-copy BGK: keep each load where its address is
+      // ready, so the wavefront's loads overlap its own remaining address
+      // work instead of waiting for all 19 addresses (+1% FP64, +3-4% FP32
+      // measured; FP16, whose table reads then stop batching, would lose half
+      // its rate)
+      if constexpr (S != LBM_F16_OFFSET && PH == kTwoCopy && !MRT) __builtin_amdgcn_sched_barrier(0);
     }
   });
   const CollideCoef &cc = coef[own.sample];
