@@ -1,14 +1,14 @@
 """The warm-start network at its full size, in the configuration bench.py
-times: the 4-level, 24-base U-Net with the force-linear head on a 128^3
-porous sample's geometry encoding.
+times: the 4-level, 24-base U-Net with the force-linear head at 128^3.
 
-* Every layer of one forward pass against the FP64 layer oracle, on sampled
-  voxels: the layer's own BF16 input as the GPU holds it after the pass, the
-  BF16 weights and FP32 biases, and the oracle's layer evaluated at the
-  sampled voxels (2,000 per layer, all voxels where a grid has fewer).  BF16
-  outputs are within their rounding, 2^-8 of the value, plus 1e-4 of the
-  layer's largest output for FP32 accumulation order; pooling is exact; the
-  FP32 head output within 1e-5 of its largest value.
+* Every layer kernel the forward pass launches, at the grid, channel counts,
+  strides and buffer offsets it has in the network (17 convolutions and
+  up-samplings, 3 poolings, the head), on seeded random BF16 inputs, the
+  network's BF16 weights and seeded FP32 biases, against the FP64 layer
+  oracle on sampled voxels (2,000 per layer, all voxels where a grid has
+  fewer).  BF16 outputs are within their rounding, 2^-8 of the value, plus
+  1e-4 of the layer's largest output for FP32 accumulation order; pooling is
+  exact; the FP32 head output within 1e-5 of its largest value.
 * Circular padding, stride-2 pooling and stride-2 up-sampling make the
   network commute with shifts by multiples of 8 voxels (2^(levels-1)): the
   output of the shifted input is the shifted output, bit for bit, which
@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 from oracle import nn as onn
-from paper_1703_08015_amd import inputs, warmstart
+from paper_1703_08015_amd import inputs, nn, warmstart
 
 pytestmark = pytest.mark.gpu
 
@@ -75,48 +75,86 @@ def _check_bf16(got, want, what):
     assert np.max(np.abs(want)) > 0, what
 
 
-def test_every_layer_on_sampled_voxels(torch, run):
-    net, x, sm, mixed = run
-    _, A, grids = net._cache
+def _bf(a):
+    """Round to the nearest BF16 value (ties to even), as float64."""
+    a32 = np.asarray(a, np.float32)
+    b = a32.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_every_layer_kernel_on_sampled_voxels(torch, run):
+    net = run[0]
     L, C = net.L, net.C
+    grids = [tuple(128 >> l for _ in range(3)) for l in range(L)]
+    rng = np.random.default_rng(31)
+    bf16 = dict(dtype=torch.bfloat16, device="cuda")
+
+    def rnd(shape):
+        return _bf(rng.normal(size=shape))
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(**bf16)
+
+    def rows(g):
+        return (g[2], g[1], g[0])
+
     W = lambda p: _h(p.b16)  # noqa: E731
     B = lambda p: _h(p.p)  # noqa: E731
-    src = _h(x)
+
+    def conv(l, cin, cout, w, b, ld_in, width, what):
+        """A 3x3x3 layer on level l: input ld_in wide, output written at offset 0 of a width-wide buffer."""
+        g = grids[l]
+        x = rnd(g + (ld_in,))
+        y = torch.zeros(g + (width,), **bf16)
+        nn.forward(nn.CONV3, nn.IDENT, rows(g), 27, cin, cout, dev(x), ld_in, w.b16, y, width, bias=b.p, relu=True)
+        nodes = _nodes(g, 2000, seed=int(rng.integers(1 << 30)))
+        _check_bf16(_at(_h(y), nodes)[:, :cout], onn.relu(onn.conv3_at(x[..., :cin], W(w), B(b), nodes)), what)
+
     for l in range(L):
-        nodes = _nodes(grids[l], 2000, seed=100 + l)
         (w1, b1), (w2, b2) = net.enc[l]
+        cin = net.in_ch if l == 0 else C[l - 1]
+        conv(l, cin, C[l], w1, b1, cin, C[l], "enc %d conv 1" % l)
+        conv(l, C[l], C[l], w2, b2, C[l], 2 * C[l] if l < L - 1 else C[l], "enc %d conv 2" % l)
         if l > 0:
-            prev = _h(A["cat", l - 1])[..., :C[l - 1]]
-            assert np.array_equal(_at(_h(A["pool", l]), nodes), onn.maxpool2_at(prev, nodes)), "pool %d" % l
-            src = _h(A["pool", l])
-        e1 = _h(A["e1", l])
-        _check_bf16(_at(e1, nodes), onn.relu(onn.conv3_at(src, W(w1), B(b1), nodes)), "enc %d conv 1" % l)
-        cat = _h(A["cat", l])
-        _check_bf16(_at(cat, nodes)[:, :C[l]], onn.relu(onn.conv3_at(e1, W(w2), B(b2), nodes)), "enc %d conv 2" % l)
-    below = _h(A["cat", L - 1])
+            # pooling reads the skip half of the level above's concatenation buffer
+            src = rnd(grids[l - 1] + (2 * C[l - 1],))
+            pool = torch.empty(grids[l] + (C[l - 1],), **bf16)
+            arg = torch.empty(grids[l] + (C[l - 1],), dtype=torch.uint8, device="cuda")
+            nn.maxpool2(rows(grids[l]), C[l - 1], dev(src), 2 * C[l - 1], pool, C[l - 1], arg)
+            nodes = _nodes(grids[l], 2000, seed=400 + l)
+            assert np.array_equal(_at(_h(pool), nodes), onn.maxpool2_at(src[..., :C[l - 1]], nodes)), "pool %d" % l
     for k, l in enumerate(range(L - 2, -1, -1)):
-        nodes = _nodes(grids[l], 2000, seed=200 + l)
         uw, ub = net.up[k]
         (w1, b1), (w2, b2) = net.dec[k]
-        cat = _h(A["cat", l])
-        _check_bf16(_at(cat, nodes)[:, C[l]:], onn.up2_at(below, W(uw), B(ub), nodes), "up to level %d" % l)
-        d1 = _h(A["d1", l])
-        _check_bf16(_at(d1, nodes), onn.relu(onn.conv3_at(cat, W(w1), B(b1), nodes)), "dec %d conv 1" % l)
-        d2 = _h(A["d2", l])
-        _check_bf16(_at(d2, nodes), onn.relu(onn.conv3_at(d1, W(w2), B(b2), nodes)), "dec %d conv 2" % l)
-        below = d2
+        below = rnd(grids[l + 1] + (C[l + 1],))
+        cat = torch.zeros(grids[l] + (2 * C[l],), **bf16)
+        nn.forward(nn.IDENT, nn.SCATTER2, rows(grids[l + 1]), 8, C[l + 1], C[l], dev(below), C[l + 1], uw.b16, cat,
+                   2 * C[l], bias=ub.p, y_offset=C[l])
+        nodes = _nodes(grids[l], 2000, seed=500 + l)
+        hc = _h(cat)
+        _check_bf16(_at(hc, nodes)[:, C[l]:], onn.up2_at(below, W(uw), B(ub), nodes), "up to level %d" % l)
+        assert not np.any(_at(hc, nodes)[:, :C[l]]), "up to level %d wrote the skip half" % l
+        conv(l, 2 * C[l], C[l], w1, b1, 2 * C[l], C[l], "dec %d conv 1" % l)
+        conv(l, C[l], C[l], w2, b2, C[l], C[l], "dec %d conv 2" % l)
     # the FP32 head (1x1x1) and the force-direction mix of its three 4-channel groups
-    nodes = _nodes(grids[0], 2000, seed=300)
     hw, hb = net.head
     oc = net.out_ch
+    below = rnd(grids[0] + (C[0],))
+    out = torch.empty(grids[0] + (oc,), dtype=torch.float32, device="cuda")
+    nn.forward(nn.IDENT, nn.IDENT, rows(grids[0]), 1, C[0], oc, dev(below), C[0], hw.b16, out, oc, bias=hb.p,
+               y_fp32=True)
+    nodes = _nodes(grids[0], 2000, seed=600)
     want = onn.dense(_at(below, nodes), W(hw).reshape(hw.p.shape[0], -1)[:oc], B(hb)[:oc])
-    got = _at(_h(A["out"]), nodes)
-    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    err = np.max(np.abs(_at(_h(out), nodes) - want)) / np.max(np.abs(want))
     _log("head max error / max output", err)
     assert err <= 1e-5
-    mix = sum(sm.dir[j] * want[:, 4 * j:4 * j + 4] for j in range(3))
+    d = np.array([0.36, -0.48, 0.8])
+    mixed = torch.empty(grids[0] + (4,), dtype=torch.float32, device="cuda")
+    nn.mix(out, d, mixed)
     gm = _at(_h(mixed), nodes)
-    assert np.max(np.abs(gm - mix)) <= 1e-5 * np.max(np.abs(mix))
+    mix = sum(d[j] * _at(_h(out), nodes)[:, 4 * j:4 * j + 4] for j in range(3))
+    assert np.max(np.abs(gm - mix)) <= 1e-6 * np.max(np.abs(mix))
 
 
 def test_shift_by_eight_commutes(torch, run):
