@@ -145,6 +145,28 @@ constexpr int mrt_norm(int k) {
   return n;
 }
 
+// Every moment of the basis is a polynomial in c of one parity: an even row
+// takes the same value on c and -c, an odd row opposite values.  Returns
+// +1 (even), -1 (odd) or 0 (neither; no row of the bases is).
+template <class L>
+constexpr int mrt_parity(int k) {
+  bool even = true, odd = true;
+  for (int i = 0; i < L::Q; ++i) {
+    const int a = mrt_row<L>(k, i).value, b = mrt_row<L>(k, L::Opp[i]).value;
+    even = even && a == b;
+    odd = odd && a == -b;
+  }
+  return even ? 1 : odd ? -1 : 0;
+}
+
+// The p-th pair of opposite moving directions (i, opp(i)) with i < opp(i).
+template <class L>
+constexpr int pair_dir(int p) {
+  for (int i = 1, n = 0; i < L::Q; ++i)
+    if (i < L::Opp[i] && n++ == p) return i;
+  return -1;
+}
+
 // Per class: -s and 1 - s/2 (FP64 and FP32).  Shear stress: s = 1/tau;
 // conserved moments: s = 1 (the density's relaxation term vanishes and the
 // momentum's cancels against the half-force shift of u).
@@ -373,21 +395,46 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R j
     // Guo source: w m [3 (c - u).g + 9 (c.u)(c.g)]
     F[i] = (w * m) * std::fma(R(9) * cu, cg, R(3) * (cg - ug));
   });
+  // The transforms work on pair sums and differences: an even row reads
+  // d_i + d_opp(i) (and the rest direction), an odd row d_i - d_opp(i), so
+  // each row takes half the terms; the inverse collects the even and odd rows'
+  // contributions per pair and splits them back over the two directions.
+  constexpr int P = (Q - 1) / 2;
+  R ds[P], dd[P], fs[P], fd[P], ev[P], od[P];
+  static_for<P>([&](auto Pc) {
+    constexpr int p = decltype(Pc)::value;
+    constexpr int i = pair_dir<L>(p), j = L::Opp[i];
+    ds[p] = d[i] + d[j];
+    dd[p] = d[i] - d[j];
+    fs[p] = F[i] + F[j];
+    fd[p] = F[i] - F[j];
+    ev[p] = R(0);
+    od[p] = R(0);
+  });
+  R e0 = 0;
+  // x + c v for an integer coefficient c, with the unit cases as plain adds
+  auto madd = [](auto Cc, R v, R x) -> R {
+    constexpr int c = decltype(Cc)::value;
+    if constexpr (c == 1) return x + v;
+    else if constexpr (c == -1) return x - v;
+    else return std::fma(R(c), v, x);
+  };
   static_for<Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
+    constexpr int par = mrt_parity<L>(k);
+    static_assert(par != 0, "every moment of the basis is even or odd in c");
+    constexpr int c0 = mrt_row<L>(k, 0).value;  // zero in every odd row
     R dm = 0, fm = 0;
-    static_for<Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      constexpr int c = mrt_row<L>(k, i).value;
-      if constexpr (c == 1) {
-        dm = dm + d[i];
-        fm = fm + F[i];
-      } else if constexpr (c == -1) {
-        dm = dm - d[i];
-        fm = fm - F[i];
-      } else if constexpr (c != 0) {
-        dm = std::fma(R(c), d[i], dm);
-        fm = std::fma(R(c), F[i], fm);
+    if constexpr (c0 != 0) {
+      dm = madd(std::integral_constant<int, c0>{}, d[0], dm);
+      fm = madd(std::integral_constant<int, c0>{}, F[0], fm);
+    }
+    static_for<P>([&](auto Pc) {
+      constexpr int p = decltype(Pc)::value;
+      constexpr int c = mrt_row<L>(k, pair_dir<L>(p)).value;
+      if constexpr (c != 0) {
+        dm = madd(std::integral_constant<int, c>{}, par > 0 ? ds[p] : dd[p], dm);
+        fm = madd(std::integral_constant<int, c>{}, par > 0 ? fs[p] : fd[p], fm);
       }
     });
     constexpr int cl = mrt_row<L>(k, 0).cls;
@@ -401,16 +448,24 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R j
       mh = (R)mr.mhf[cl];
     }
     const R y = std::fma(ms, dm, mh * fm) * inv;
-    static_for<Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      constexpr int c = mrt_row<L>(k, i).value;
-      if constexpr (c == 1)
-        f[i] = f[i] + y;
-      else if constexpr (c == -1)
-        f[i] = f[i] - y;
-      else if constexpr (c != 0)
-        f[i] = std::fma(R(c), y, f[i]);
+    if constexpr (c0 != 0) e0 = madd(std::integral_constant<int, c0>{}, y, e0);
+    static_for<P>([&](auto Pc) {
+      constexpr int p = decltype(Pc)::value;
+      constexpr int c = mrt_row<L>(k, pair_dir<L>(p)).value;
+      if constexpr (c != 0) {
+        if constexpr (par > 0)
+          ev[p] = madd(std::integral_constant<int, c>{}, y, ev[p]);
+        else
+          od[p] = madd(std::integral_constant<int, c>{}, y, od[p]);
+      }
     });
+  });
+  f[0] = f[0] + e0;
+  static_for<P>([&](auto Pc) {
+    constexpr int p = decltype(Pc)::value;
+    constexpr int i = pair_dir<L>(p), j = L::Opp[i];
+    f[i] = f[i] + (ev[p] + od[p]);
+    f[j] = f[j] + (ev[p] - od[p]);
   });
 }
 
