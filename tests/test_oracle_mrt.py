@@ -49,6 +49,27 @@ def test_bases_are_orthogonal_with_published_norms():
         assert len(nu) == (2 if q == 9 else 5)
 
 
+def test_every_moment_is_even_or_odd_in_c():
+    """Each row of both bases takes equal values on opposite velocities (even moments: density, energies, stresses)
+    or opposite values (odd: momentum, heat fluxes, third-order terms), and the odd rows vanish on the rest
+    direction; so M f splits into pair sums and differences."""
+    for q in (9, 19):
+        M, _ = dense.mrt_matrix(q)
+        _, _, opp = dense.lattice(q)
+        even = [np.array_equal(M[k], M[k][opp]) for k in range(q)]
+        odd = [np.array_equal(M[k], -M[k][opp]) for k in range(q)]
+        assert all(e != o for e, o in zip(even, odd))
+        assert sum(odd) == (4 if q == 9 else 9)  # j and q along each axis, plus the three m rows in 3D
+        assert all(M[k][0] == 0 for k in range(q) if odd[k])
+        # the pair form reproduces M f
+        rng = np.random.default_rng(q)
+        f = rng.random(q)
+        pairs = [i for i in range(1, q) if i < opp[i]]
+        s, d = f[pairs] + f[opp[pairs]], f[pairs] - f[opp[pairs]]
+        mf = np.array([(M[k][0] * f[0] if even[k] else 0.0) + M[k][pairs] @ (s if even[k] else d) for k in range(q)])
+        assert np.allclose(mf, M @ f, rtol=1e-14, atol=1e-14)
+
+
 def _published_eq(q, rho, u, d):
     """Closed-form equilibrium moments of the two bases, with d the density of
     the velocity terms (rho or 1)."""
