@@ -95,7 +95,10 @@ __global__ void __launch_bounds__(64 * WPB)
   out_ptr<PH, T> dst = static_cast<T *>(dst_);
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t gw = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
+  // D2Q9 hands the XCDs chunks of 8 workgroups in turn (+2.5% FP64, +6% FP32
+  // measured on the 4096^2 channel against one contiguous range per XCD)
+  const int64_t blk = L::Q == 9 ? xcd_chunk(blockIdx.x, gridDim.x, 8) : xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t gw = blk * WPB + wv;
   const bool valid = gw < a.n_waves;
   const int64_t tile = gw / W;
   const int part = (int)(gw % W);
