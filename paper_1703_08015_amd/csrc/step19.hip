@@ -286,12 +286,12 @@ __global__ void __launch_bounds__(64 * WPB)
              const int32_t *__restrict__ count) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   // XCD assignment, chosen per form by measurement: chunks of 8 blocks for
-  // the two-copy FP64/FP32 BGK step, 16 for the FP64 single copy, one
-  // contiguous range per XCD for everything else (FP16, MRT, the FP32 single
-  // copy and the persistent grid)
-  constexpr int kChunk = (MRT || MODE == kPersistent) ? 0
-                         : PH == kTwoCopy             ? (S == LBM_F16_OFFSET ? 0 : 8)
-                                                      : (S == LBM_F64 ? 16 : 0);
+  // the two-copy FP64/FP32 step (BGK and MRT), 16 for the FP64 BGK single
+  // copy, one contiguous range per XCD for everything else (FP16, the other
+  // single-copy forms and the persistent grid)
+  constexpr int kChunk = MODE == kPersistent ? 0
+                         : PH == kTwoCopy    ? (S == LBM_F16_OFFSET ? 0 : 8)
+                                             : (S == LBM_F64 && !MRT ? 16 : 0);
   const int64_t blk = kChunk ? xcd_chunk(blockIdx.x, gridDim.x, kChunk) : xcd_remap(blockIdx.x, gridDim.x);
   const int64_t gw = blk * WPB + wv;
   if constexpr (MODE == kDirect) {
