@@ -92,7 +92,8 @@ def step_kernel_key(args):
                                                   ",single-copy" if args.pattern == "single-copy" else "",
                                                   ",mrt" if args.collision == "mrt" else "")
         return kernel, "%s_%d_%s_generic_%s" % (args.geometry, args.n, args.storage, args.order)
-    kernel = "%s<D3Q19,4x4x4,%s%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
+    kernel = "%s<D3Q19,4x4x4,%s%s%s%s%s>" % ("k_step" if args.kernel == "generic" else "k_step19", args.storage,
+                                             ",shuffle" if args.kernel == "shuffle" else "",
                                            ",incompressible" if inc else "",
                                            ",single-copy" if args.pattern == "single-copy" else "",
                                            ",mrt" if args.collision == "mrt" else "")
@@ -495,7 +496,7 @@ def main():
     ap.add_argument("--g", type=float, default=1e-6)
     ap.add_argument("--tiles-per-block", type=int, default=0)
     ap.add_argument("--order", default="morton", choices=["morton", "rowmajor"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "scalar"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "scalar", "shuffle"])
     ap.add_argument("--store", default="auto", choices=["auto", "regular", "nontemporal"])
     ap.add_argument("--f16-scale-log2", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=160)

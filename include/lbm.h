@@ -74,6 +74,10 @@ typedef struct {
   double phi;            /* porosity, Eq. (11) */
   double phi_t;          /* average tile porosity, Eq. (17) */
   double tiles_ratio;    /* N_tiles / N_ftiles (Sec. 3.1.1.1) */
+  double alpha_m;        /* alpha_M, the input of Eqs. (27)-(32) (Sec. 3.1.1.2): the share of the faces of
+                            non-empty tiles across which the neighbour tile is non-empty (a face buffer of
+                            the ghost-buffer method is needed only there), over the axes along which the
+                            lattice has more than one node; 0 without non-empty tiles */
 } lbm_tiles_info_t;
 
 /* Solver parameters. */
@@ -152,10 +156,17 @@ typedef struct {
 #define LBM_ORDER_ROWMAJOR 1
 
 /* Step kernel: AUTO picks the scalar-mask D3Q19 kernel for 4x4x4 tiles and
- * the generic kernel (LDS-staged neighbour records) otherwise. */
+ * the generic kernel (LDS-staged neighbour records) otherwise.  SHUFFLE is
+ * the scalar-mask kernel in its shuffle form (two-copy step, 4x4x4 tiles):
+ * each lane loads its own node's values coalesced, sources inside the tile
+ * come from other lanes of the wavefront (DPP row shifts, ds_bpermute), and
+ * only sources in neighbour tiles are gathered from memory (the in-tile
+ * streaming of the paper's Fig. 5 done with wavefront shuffles instead of
+ * shared memory).  Same results, bit for bit, as SCALAR_MASK. */
 #define LBM_KERNEL_AUTO 0
 #define LBM_KERNEL_GENERIC 1
 #define LBM_KERNEL_SCALAR_MASK 2
+#define LBM_KERNEL_SHUFFLE 3
 
 /* Velocity set and weights of a lattice (q = 9 or 19): c[3*q] (x, y, z per
  * direction), w[q], opp[q].  Standard D2Q9 / D3Q19 sets; the paper's Fig. 1
@@ -302,6 +313,21 @@ int64_t lbm_step_count(const lbm_solver *s);
  * for bad arguments, LBM_ERR_NOMEM if host memory runs out. */
 int lbm_components(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic, int32_t axis,
                    int32_t *labels, int32_t *count);
+
+/* lbm_components on the device, with the same labels and count: solid
+ * device uint8 [nz][ny][nx]; labels device int32 [nz][ny][nx] (out: -1 on
+ * solid nodes, components numbered from 0 in order of first appearance, x
+ * fastest); scratch device int32 of lbm_components_device_scratch(shape)
+ * entries (overwritten; must not overlap labels); *count host, written before
+ * return.  Lock-free union-find over the links on the given stream, then a
+ * fixed-order numbering of the roots; synchronises the stream to return the
+ * count.  LBM_ERR_ARG / LBM_ERR_UNSUPPORTED for bad arguments, LBM_ERR_HIP if
+ * a launch fails. */
+int lbm_components_device(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
+                          int32_t axis, int32_t *labels, int32_t *count, int32_t *scratch, void *stream);
+/* Scratch entries (int32) lbm_components_device needs for a shape; -1 for a
+ * bad shape. */
+int64_t lbm_components_device_scratch(const int32_t shape[3]);
 
 /* Give a starting state (rho, u) for lbm_init the invariants of a start
  * from rest.

@@ -17,7 +17,12 @@ Readings where the paper is silent:
     for dx, dy, dz in {-1, 0, 1}, wrapped on periodic axes, -1 for a position
     outside a non-periodic axis or an empty tile;
   * node l = lx + ax*(ly + ay*lz) of a tile is bit (l % 64) of fluid word
-    l // 64 (set = non-solid).
+    l // 64 (set = non-solid);
+  * alpha_M, "the ratio of allocated ghost buffers to all possible ghost
+    buffers" (Sec. 3.1.1.2), counts the faces of non-empty tiles: a face
+    buffer is needed where the tile across the face is non-empty, and every
+    face of a non-empty tile is a possible one.  Faces are those of the axes
+    along which the lattice has more than one node.
 """
 import numpy as np
 
@@ -83,6 +88,13 @@ def tile(mask, tile_edges, periodic):
         sub = bits[:, 64 * w:64 * (w + 1)].astype(np.uint64)
         fl[:, w] = (sub * weights).sum(axis=1, dtype=np.uint64)
 
+    # alpha_M: non-empty face neighbours (slots 13 -+ 1, 3, 9 of the row)
+    faces = shared = 0
+    for ax, step in ((0, 1), (1, 3), (2, 9)):
+        if npad[ax] > 1:
+            shared += int((nbr[:, 13 - step] >= 0).sum() + (nbr[:, 13 + step] >= 0).sum())
+            faces += 2 * nft
+
     n_nodes = n[0] * n[1] * n[2]
     n_f = int((~mask).sum())
     return dict(
@@ -91,4 +103,5 @@ def tile(mask, tile_edges, periodic):
         n_tiles=int(T[0] * T[1] * T[2]), n_ftiles=int(nft), n_fluid=n_f, n_nodes=n_nodes,
         phi=n_f / n_nodes, phi_t=(n_f / (nft * ntn)) if nft else 0.0,
         tiles_ratio=(T[0] * T[1] * T[2] / nft) if nft else float("inf"),
+        alpha_m=(shared / faces) if faces else 0.0,
     )

@@ -211,6 +211,11 @@ struct Store<LBM_F64> {
   __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
   __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
   __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float) { __builtin_nontemporal_store(v, p + i); }
+  // the stored bits as loaded, and their value (the shuffle step moves raw
+  // values between lanes and converts each once)
+  using Raw = double;
+  __device__ static __forceinline__ Raw load_raw(const T *p, int64_t i) { return p[i]; }
+  __device__ static __forceinline__ R value(Raw r, float) { return r; }
 };
 
 template <>
@@ -221,6 +226,9 @@ struct Store<LBM_F32_OFFSET> {
   __device__ static __forceinline__ R load(const T *p, int64_t i, float) { return p[i]; }
   __device__ static __forceinline__ void store(T *p, int64_t i, R v, float) { p[i] = v; }
   __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float) { __builtin_nontemporal_store(v, p + i); }
+  using Raw = float;
+  __device__ static __forceinline__ Raw load_raw(const T *p, int64_t i) { return p[i]; }
+  __device__ static __forceinline__ R value(Raw r, float) { return r; }
 };
 
 template <>
@@ -236,6 +244,14 @@ struct Store<LBM_F16_OFFSET> {
   __device__ static __forceinline__ void store_nt(T *p, int64_t i, R v, float scale) {
     const __half h = __float2half_rn(v * scale);
     __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, h), reinterpret_cast<uint16_t *>(p) + i);
+  }
+  // binary16 bits in the low half of a 32-bit register
+  using Raw = uint32_t;
+  __device__ static __forceinline__ Raw load_raw(const T *p, int64_t i) {
+    return reinterpret_cast<const uint16_t *>(p)[i];
+  }
+  __device__ static __forceinline__ R value(Raw r, float inv) {
+    return __half2float(__builtin_bit_cast(__half, (uint16_t)r)) * inv;
   }
 };
 

@@ -202,3 +202,210 @@ extern "C" int lbm_project_invariants(int32_t q, const int32_t shape[3], uint32_
   if (e != hipSuccess) return set_error(LBM_ERR_HIP, "lbm_project_invariants: %s", hipGetErrorString(e));
   return LBM_OK;
 }
+
+// ---- connected components on the device ---------------------------------------
+// The same labels as the host lbm_components, for a warm start that must
+// not wait for the host.  Lock-free union-find over the links: every
+// pointer goes from a node to a node of smaller index, a union hooks the
+// larger of two roots under the smaller with a compare-and-swap (retrying
+// from the new parent if the root moved meanwhile), and finds halve their
+// paths.  Because every parent index is smaller than its node's, every loop
+// ends: a find walks strictly decreasing indices and a failed hook lowers
+// the larger root.  The root of a component is then its smallest node, so
+// numbering roots in scan order (an exclusive prefix sum of root flags)
+// reproduces the host's numbering by first appearance.
+namespace {
+
+constexpr int kScanBlock = 1024;  // threads of the scan kernels
+constexpr int kScanItems = 4;     // items per thread
+
+__device__ __forceinline__ int32_t ld_parent(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t cc_find(int32_t *parent, int32_t v) {
+  while (true) {
+    const int32_t p = ld_parent(parent + v);
+    if (p == v) return v;
+    const int32_t gp = ld_parent(parent + p);
+    if (gp == p) return p;
+    __hip_atomic_store(parent + v, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // an ancestor of v
+    v = gp;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cc_init(int64_t n, const uint8_t *solid, int32_t *parent) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock)
+    parent[e] = solid[e] ? -1 : (int32_t)e;
+}
+
+struct CcGrid {
+  int nx, ny, nz;
+};
+
+// One thread per node: union with the non-solid node one link away, for one
+// link of each opposite pair (only links with c_axis != 0 when axis >= 0).
+template <class L>
+__global__ void __launch_bounds__(kBlock) k_cc_union(CcGrid g, uint32_t periodic, int axis, const uint8_t *solid,
+                                                     int32_t *parent) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n || solid[e]) return;
+  const int x = (int)(e % g.nx), y = (int)((e / g.nx) % g.ny), z = (int)(e / ((int64_t)g.nx * g.ny));
+  lbm::static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    if constexpr ((cx != 0 || cy != 0 || cz != 0) && i < L::Opp[i]) {
+      const int c[3] = {cx, cy, cz};
+      if (axis >= 0 && c[axis] == 0) return;
+      int t[3] = {x + cx, y + cy, z + cz};
+      const int ext[3] = {g.nx, g.ny, g.nz};
+      for (int a = 0; a < 3; ++a) {
+        if (t[a] >= 0 && t[a] < ext[a]) continue;
+        if (!((periodic >> a) & 1u)) return;
+        t[a] = t[a] < 0 ? t[a] + ext[a] : t[a] - ext[a];
+      }
+      const int64_t f = (int64_t)t[0] + (int64_t)g.nx * ((int64_t)t[1] + (int64_t)g.ny * t[2]);
+      if (solid[f]) return;
+      int32_t a = cc_find(parent, (int32_t)e), b = cc_find(parent, (int32_t)f);
+      while (a != b) {
+        if (a > b) {
+          const int32_t s = a;
+          a = b;
+          b = s;
+        }
+        const int32_t old = atomicCAS(parent + b, b, a);
+        if (old == b) break;  // b now hangs under a
+        b = cc_find(parent, old);
+        a = cc_find(parent, a);
+      }
+    }
+  });
+}
+
+// parent <- root; flag = 1 on roots (in the scan buffer).  The walk to the
+// root only reads: the single write per node is its root, so a concurrent
+// walk through that node sees an ancestor either way, and every node ends
+// holding its root.
+__global__ void __launch_bounds__(kBlock) k_cc_flatten(int64_t n, int32_t *parent, int32_t *flag) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t p = parent[e];
+    if (p < 0) {
+      flag[e] = 0;
+      continue;
+    }
+    int32_t r = (int32_t)e;
+    for (int32_t up = p; up != r; up = ld_parent(parent + up)) r = up;
+    flag[e] = r == (int32_t)e;
+    __hip_atomic_store(parent + e, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Exclusive prefix sum of v[0, n) in place, kScanBlock * kScanItems items per
+// block; the block totals go to sums[blockIdx.x].
+__global__ void __launch_bounds__(kScanBlock) k_scan_block(int64_t n, int32_t *v, int32_t *sums) {
+  __shared__ int32_t s[kScanBlock];
+  const int64_t base = ((int64_t)blockIdx.x * kScanBlock + threadIdx.x) * kScanItems;
+  int32_t item[kScanItems], run = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    item[k] = base + k < n ? v[base + k] : 0;
+    run += item[k];
+  }
+  s[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {  // inclusive Hillis-Steele scan of the thread totals
+    const int32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t acc = s[threadIdx.x] - run;
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) v[base + k] = acc;
+    acc += item[k];
+  }
+  if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = s[threadIdx.x];
+}
+
+// Exclusive scan of the block totals (one block, any count); total to sums[nb].
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(int64_t nb, int32_t *sums) {
+  __shared__ int32_t s[kScanBlock];
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanBlock) {
+    const int64_t b = b0 + threadIdx.x;
+    const int32_t x = b < nb ? sums[b] : 0;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+      const int32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (b < nb) sums[b] = carry + s[threadIdx.x] - x;
+    const int32_t total = s[kScanBlock - 1];
+    __syncthreads();
+    carry += total;
+  }
+  if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+// labels = rank of the node's root among the roots (the root's flag slot
+// holds it once offset by its block's total); -1 on solid nodes
+__global__ void __launch_bounds__(kBlock) k_cc_label(int64_t n, const int32_t *rank, const int32_t *sums,
+                                                     int32_t *parent_to_label) {
+  constexpr int64_t per = (int64_t)kScanBlock * kScanItems;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+    const int32_t r = parent_to_label[e];
+    parent_to_label[e] = r < 0 ? -1 : rank[r] + sums[r / per];
+  }
+}
+
+unsigned cc_grid(int64_t n) {
+  const int64_t b = (n + kBlock - 1) / kBlock;
+  return (unsigned)(b < 16384 ? (b > 0 ? b : 1) : 16384);
+}
+
+}  // namespace
+
+extern "C" int64_t lbm_components_device_scratch(const int32_t shape[3]) {
+  if (!shape || shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0) return -1;
+  const int64_t n = (int64_t)shape[0] * shape[1] * shape[2];
+  const int64_t per = (int64_t)kScanBlock * kScanItems;
+  return n + (n + per - 1) / per + 1;
+}
+
+extern "C" int lbm_components_device(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
+                                     int32_t axis, int32_t *labels, int32_t *count, int32_t *scratch,
+                                     void *stream) {
+  if (!solid || !shape || !labels || !count || !scratch)
+    return set_error(LBM_ERR_ARG, "lbm_components_device: NULL argument");
+  if (q != 9 && q != 19) return set_error(LBM_ERR_UNSUPPORTED, "lbm_components_device: q = %d", q);
+  if (shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0)
+    return set_error(LBM_ERR_ARG, "lbm_components_device: shape %d x %d x %d", shape[0], shape[1], shape[2]);
+  if (q == 9 && shape[2] != 1) return set_error(LBM_ERR_ARG, "lbm_components_device: D2Q9 needs shape[2] = 1");
+  if (periodic > 7u) return set_error(LBM_ERR_ARG, "lbm_components_device: periodic bits %u", periodic);
+  if (axis < -1 || axis >= (q == 9 ? 2 : 3))
+    return set_error(LBM_ERR_ARG, "lbm_components_device: axis %d for q = %d", axis, q);
+  const int64_t n = (int64_t)shape[0] * shape[1] * shape[2];
+  if (n > INT32_MAX) return set_error(LBM_ERR_ARG, "lbm_components_device: %lld nodes exceed int32 labels", (long long)n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const CcGrid g{shape[0], shape[1], shape[2]};
+  const int64_t per = (int64_t)kScanBlock * kScanItems, nb = (n + per - 1) / per;
+  int32_t *flag = scratch, *sums = scratch + n;
+  hipLaunchKernelGGL(k_cc_init, dim3(cc_grid(n)), dim3(kBlock), 0, s, n, solid, labels);
+  const unsigned all = (unsigned)((n + kBlock - 1) / kBlock);
+  if (q == 19)
+    hipLaunchKernelGGL(k_cc_union<lbm::D3Q19>, dim3(all), dim3(kBlock), 0, s, g, periodic, axis, solid, labels);
+  else
+    hipLaunchKernelGGL(k_cc_union<lbm::D2Q9>, dim3(all), dim3(kBlock), 0, s, g, periodic, axis, solid, labels);
+  hipLaunchKernelGGL(k_cc_flatten, dim3(cc_grid(n)), dim3(kBlock), 0, s, n, labels, flag);
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanBlock), 0, s, n, flag, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, nb, sums);
+  hipLaunchKernelGGL(k_cc_label, dim3(cc_grid(n)), dim3(kBlock), 0, s, n, flag, sums, labels);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(count, sums + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(LBM_ERR_HIP, "lbm_components_device: %s", hipGetErrorString(e));
+  return LBM_OK;
+}

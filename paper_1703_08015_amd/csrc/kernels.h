@@ -38,13 +38,15 @@ bool step19_supported(const Variant &v);
 // index of every lane region (device.h).
 // mode 0: wavefront w -> tile w; 1: -> list[w] for w < *count; 2: persistent
 // grid of blocks_persistent workgroups striding over list[0 .. *count).
-hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a,
+// shuffle: the two-copy step in its shuffle form (own values loaded
+// coalesced, in-tile sources taken from other lanes; step19.hip).
+hipError_t launch_step19(const Variant &v, int phase, bool shuffle, const void *src, void *dst, const TileArgs &a,
                          const NbRec *nrec, const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef,
                          bool nontemporal, const int32_t *list, const int32_t *count, int mode,
                          int64_t blocks_persistent, hipStream_t s);
 // Workgroups of the persistent step resident at once (for both single-copy
 // phases when single_copy).
-hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, int64_t *blocks);
+hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, bool shuffle, int64_t *blocks);
 hipError_t launch_init(const Variant &v, void *dst, const TileArgs &a, const double *rho, const double *u,
                        hipStream_t s);
 hipError_t launch_moments(const Variant &v, const void *src, const TileArgs &a, double *rho, double *u,

@@ -105,7 +105,7 @@ int check_params(const lbm_tiles *t, const lbm_params *p, lbm::Variant *v) {
     return set_error(LBM_ERR_ARG, "f16_scale_log2 = %d outside 0..24", p->f16_scale_log2);
   if (p->tile_order != LBM_ORDER_MORTON && p->tile_order != LBM_ORDER_ROWMAJOR)
     return set_error(LBM_ERR_ARG, "tile_order = %d", p->tile_order);
-  if (p->step_kernel < LBM_KERNEL_AUTO || p->step_kernel > LBM_KERNEL_SCALAR_MASK)
+  if (p->step_kernel < LBM_KERNEL_AUTO || p->step_kernel > LBM_KERNEL_SHUFFLE)
     return set_error(LBM_ERR_ARG, "step_kernel = %d", p->step_kernel);
   if (p->store_policy < LBM_STORE_AUTO || p->store_policy > LBM_STORE_NONTEMPORAL)
     return set_error(LBM_ERR_ARG, "store_policy = %d", p->store_policy);
@@ -331,6 +331,7 @@ struct lbm_solver {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool scalar_mask = false;  // which step kernel runs
+  bool shuffle = false;      // the scalar-mask kernel in its shuffle form
   double *part = nullptr, *chunk = nullptr, *out = nullptr, *uref = nullptr;
   std::vector<double> out_h;
 };
@@ -433,12 +434,18 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
     return set_error(LBM_ERR_NOMEM, "lbm_create: out of host memory");
   }
   const bool fits32 = P.entries < (int64_t(1) << 32);
-  if (p->step_kernel == LBM_KERNEL_SCALAR_MASK && !(lbm::step19_supported(v) && fits32)) {
+  if ((p->step_kernel == LBM_KERNEL_SCALAR_MASK || p->step_kernel == LBM_KERNEL_SHUFFLE) &&
+      !(lbm::step19_supported(v) && fits32)) {
     delete s;
-    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the scalar-mask kernel needs D3Q19, 4x4x4 tiles and "
-                                          "fewer than 2^32 PDF entries per copy");
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the scalar-mask and shuffle kernels need D3Q19, 4x4x4 "
+                                          "tiles and fewer than 2^32 PDF entries per copy");
+  }
+  if (p->step_kernel == LBM_KERNEL_SHUFFLE && p->pattern != LBM_PATTERN_TWO_COPY) {
+    delete s;
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the shuffle kernel is a two-copy step");
   }
   s->scalar_mask = p->step_kernel != LBM_KERNEL_GENERIC && lbm::step19_supported(v) && fits32;
+  s->shuffle = p->step_kernel == LBM_KERNEL_SHUFFLE;
   if (p->persistent && !s->scalar_mask) {
     delete s;
     return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the persistent step needs the scalar-mask D3Q19 kernel");
@@ -486,7 +493,7 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if (e == hipSuccess) e = up(P.list, s->list_h.data(), s->list_h.size() * sizeof(int32_t));
   if (e == hipSuccess) e = up(P.count, &s->count_h, sizeof(int32_t));
   if (e == hipSuccess && s->scalar_mask && p->persistent)
-    e = lbm::step19_persistent_blocks(v, s->single_copy, &s->persistent_blocks);
+    e = lbm::step19_persistent_blocks(v, s->single_copy, s->shuffle, &s->persistent_blocks);
   if (e == hipSuccess) e = up(P.nbase, P.nbase_h.data(), (size_t)nft * sizeof(int64_t));
   if (e == hipSuccess) e = up(P.samples, P.samples_h.data(), P.samples_h.size() * sizeof(lbm::SampleRec));
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host tables may be freed after return
@@ -671,7 +678,7 @@ static hipError_t enqueue_step(lbm_solver *s, int from, hipStream_t st) {
   }
   if (s->scalar_mask) {
     const int mode = s->p.persistent ? 2 : (s->all_active ? 0 : 1);
-    return lbm::launch_step19(s->var, phase, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d,
+    return lbm::launch_step19(s->var, phase, s->shuffle, s->buf[from], s->buf[from ^ 1], s->args, s->nrec_d, s->nrow_d,
                               s->rbase_d, s->coef_d, s->p.store_policy != LBM_STORE_REGULAR, s->list_d, s->count_d,
                               mode, s->persistent_blocks, st);
   }

@@ -17,6 +17,16 @@
 // node count, fluid mask) come through scalar loads; nothing is staged in LDS
 // and there is no barrier.
 //
+// Shuffle form (two-copy step only): every lane first loads its own node's
+// 19 post-collision values with coalesced loads (the tile's direction blocks
+// are contiguous in rank order).  A source inside the tile is then another
+// lane of the same wavefront, so lane l takes f*_i(l - c_i) from lane
+// l - d_i: a DPP row shift when c_i lies in a z-layer of 16 lanes, a
+// ds_bpermute otherwise.  Only the lanes whose source lies in a neighbour
+// tile still gather from memory, with the region arithmetic above restricted
+// to the neighbour regions, and the half-way bounce-back takes the lane's own
+// value of opp(i) from a register.
+//
 // Single-copy form (the in-place "AA" pattern, one PDF buffer): phase 1
 // gathers f_i(x) from the post-collision value f*_i(x - c_i), which the
 // previous step stored in the source node's slot opp(i) (its own slot i on a
@@ -84,6 +94,39 @@ __device__ __forceinline__ uint32_t select_lanes(uint64_t lanes, uint32_t if_set
   return r;
 }
 
+// Lane l receives x from lane l - d of the wavefront, d = cx + 4 cy + 16 cz
+// the in-tile offset of direction c.  A direction within one z-layer (the 16
+// lanes of a DPP row) is a row shift; one that crosses layers goes through
+// ds_bpermute.  Lanes whose source l - d lies outside the tile receive an
+// unspecified value (every such lane takes a neighbour's value instead).
+template <int CX, int CY, int CZ>
+__device__ __forceinline__ uint32_t lane_shift32(uint32_t x, int lane) {
+  constexpr int d = CX + 4 * CY + 16 * CZ;
+  if constexpr (d == 0) {
+    return x;
+  } else if constexpr (CZ == 0) {
+    constexpr int ctrl = d > 0 ? 0x110 + d : 0x100 - d;  // row_shr:d / row_shl:-d
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, ctrl, 0xf, 0xf, true);
+  } else {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(((lane - d) & 63) << 2, (int)x);
+  }
+}
+
+template <int CX, int CY, int CZ, class V>
+__device__ __forceinline__ V lane_shift(V x, int lane) {
+  if constexpr (sizeof(V) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = lane_shift32<CX, CY, CZ>((uint32_t)b, lane);
+    const uint64_t hi = lane_shift32<CX, CY, CZ>((uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(V, lo | hi << 32);
+  } else {
+    return __builtin_bit_cast(V, lane_shift32<CX, CY, CZ>(__builtin_bit_cast(uint32_t, x), lane));
+  }
+}
+
+// lanes set in the scalar mask (used as a lane predicate)
+__device__ __forceinline__ bool lane_in(uint64_t lanes) { return __builtin_amdgcn_inverse_ballot_w64(lanes); }
+
 // The 18 neighbour slots a D3Q19 tile pulls from (6 faces, 12 edges; the
 // 3x3x3 index k = (dx+1) + 3(dy+1) + 9(dz+1)), in the order of the compact
 // neighbour row uploaded for this kernel.
@@ -97,8 +140,9 @@ constexpr int slot_of(int k) {
 constexpr int kTwoCopy = kPhaseTwoCopy, kAAGather = kPhaseAAGather, kAALocal = kPhaseAALocal;
 
 // One 4x4x4 tile: gather, collide, store.  Lanes of solid nodes return
-// early; every value the wavefront branches on is uniform.
-template <int S, bool NT, bool INC, int PH, bool MRT>
+// early (in the shuffle form SH after the shuffles); every value the
+// wavefront branches on is uniform.
+template <int S, bool NT, bool INC, int PH, bool MRT, bool SH>
 __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_, out_ptr<PH, void> dst_,
                                             const TileArgs &a, const NbRec *__restrict__ nrec,
                                             const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -122,7 +166,9 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
       nb[j] = *reinterpret_cast<const NbRec *>(reinterpret_cast<const char *>(nrec) + nrow[tile * 20 + j]);
     });
   const uint64_t M = own.mask;
-  if (!((M >> lane) & 1ull)) return;
+  static_assert(!SH || PH == kTwoCopy, "the shuffle form is a two-copy step");
+  if constexpr (!SH)
+    if (!((M >> lane) & 1ull)) return;
   const uint32_t ooff = own.off, on = own.n;
   const uint32_t rank = mbcnt(M, 0u);
   // FP16 reads each lane region's base entry from the planner's table; the
@@ -133,6 +179,54 @@ __device__ __forceinline__ void step19_tile(int64_t tile, in_ptr<PH, void> src_,
 
   R f[19];
   uint32_t ea[PH == kAAGather ? 19 : 1];  // entries read, rewritten by the single-copy gather
+  if constexpr (SH) {
+    using Raw = typename St::Raw;
+    // own values, coalesced; a solid lane reads entry 0 of the tile (its value is never used)
+    const uint32_t eo = lane_in(M) ? rank : 0u;
+    Raw v[19], gv[19];
+    static_for<19>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      v[i] = St::load_raw(src, (int64_t)(ooff + (uint32_t)i * on + eo));
+    });
+    gv[0] = v[0];
+    static_for<18>([&](auto Im) {
+      constexpr int i = decltype(Im)::value + 1;
+      constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+      constexpr int d0 = cx + 4 * cy + 16 * cz;
+      constexpr uint64_t R0 = region(cx, cy, cz, 0, 0, 0);
+      Raw t = lane_shift<cx, cy, cz>(v[i], lane);
+      uint64_t from_fluid = shifted<d0>(M) & R0, halo = 0;
+      uint32_t e = ooff;  // lanes outside every neighbour region keep a valid, unused entry
+      static_for<8>([&](auto Wc) {
+        constexpr int w = decltype(Wc)::value;
+        constexpr int wx = w & 1, wy = (w >> 1) & 1, wz = (w >> 2) & 1;
+        if constexpr (w != 0 && (!wx || cx) && (!wy || cy) && (!wz || cz)) {
+          constexpr uint64_t Rr = region(cx, cy, cz, wx, wy, wz);
+          constexpr int dr = d0 - (wx ? 4 * cx : 0) - (wy ? 16 * cy : 0) - (wz ? 64 * cz : 0);
+          constexpr int k = 13 + (wx ? -cx : 0) + 3 * (wy ? -cy : 0) + 9 * (wz ? -cz : 0);
+          const NbRec &r = nb[slot_of(k)];
+          const uint64_t Xr = shifted<dr>(r.mask);
+          halo |= Xr & Rr;
+          uint32_t base;
+          if constexpr (kTable)
+            base = rb[region_index(i, w)];
+          else
+            base = r.off + (uint32_t)i * r.n + dropped<dr>(r.mask);
+          e = select_lanes(Rr, mbcnt(Xr, base), e);
+        }
+      });
+      from_fluid |= halo;
+      // only lanes whose source is a non-solid node of a neighbour tile load
+      if (lane_in(halo)) t = St::load_raw(src, (int64_t)e);
+      // half-way bounce-back: the lane's own post-collision value opp(i)
+      gv[i] = lane_in(from_fluid) ? t : v[L::Opp[i]];
+    });
+    if (!lane_in(M)) return;
+    static_for<19>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      f[i] = St::value(gv[i], a.f16_inv);
+    });
+  } else
   static_for<19>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
@@ -278,7 +372,7 @@ enum { kDirect = 0, kList = 1, kPersistent = 2 };
 // list[w] if w < *count.  kPersistent: a fixed grid of G wavefronts strides
 // over list[0 .. *count).  The count lives in device memory, so a captured
 // graph stays valid when the active set changes.
-template <int S, int WPB, bool NT, bool INC, int PH, bool MRT, int MODE>
+template <int S, int WPB, bool NT, bool INC, int PH, bool MRT, int MODE, bool SH>
 __global__ void __launch_bounds__(64 * WPB)
     k_step19(in_ptr<PH, void> src, out_ptr<PH, void> dst, TileArgs a, const NbRec *__restrict__ nrec,
              const uint32_t *__restrict__ nrow, const uint32_t *__restrict__ rbase,
@@ -296,14 +390,14 @@ __global__ void __launch_bounds__(64 * WPB)
   const int64_t gw = blk * WPB + wv;
   if constexpr (MODE == kDirect) {
     if (gw >= a.n_waves) return;
-    step19_tile<S, NT, INC, PH, MRT>(gw, src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH, MRT, SH>(gw, src, dst, a, nrec, nrow, rbase, coef);
   } else if constexpr (MODE == kList) {
     if (gw >= (int64_t)*count) return;
-    step19_tile<S, NT, INC, PH, MRT>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
+    step19_tile<S, NT, INC, PH, MRT, SH>(list[gw], src, dst, a, nrec, nrow, rbase, coef);
   } else {
     const int64_t n = *count, G = (int64_t)gridDim.x * WPB;
     for (int64_t k = gw; k < n; k += G)
-      step19_tile<S, NT, INC, PH, MRT>(list[k], src, dst, a, nrec, nrow, rbase, coef);
+      step19_tile<S, NT, INC, PH, MRT, SH>(list[k], src, dst, a, nrec, nrow, rbase, coef);
   }
 }
 
@@ -312,20 +406,23 @@ using IC = std::integral_constant<int, V>;
 template <bool V>
 using BC = std::integral_constant<bool, V>;
 
-// Calls f(storage, waves per block, model, phase, MRT) with compile-time constants.
+// Calls f(storage, waves per block, model, phase, MRT, shuffle form) with
+// compile-time constants.  The shuffle form exists for the two-copy step.
 template <class F>
-hipError_t with_variant(const Variant &v, int phase, F &&f) {
+hipError_t with_variant(const Variant &v, int phase, bool shuffle, F &&f) {
   // MRT is built for 4 waves per workgroup only (the planner rejects others)
-  auto by_collision = [&](auto s, auto w, auto inc, auto ph) -> hipError_t {
+  auto by_collision = [&](auto s, auto w, auto inc, auto ph, auto sh) -> hipError_t {
     if constexpr (decltype(w)::value == 4)
-      if (v.collision == LBM_COLLISION_MRT) return f(s, w, inc, ph, BC<true>{});
-    return f(s, w, inc, ph, BC<false>{});
+      if (v.collision == LBM_COLLISION_MRT) return f(s, w, inc, ph, BC<true>{}, sh);
+    return f(s, w, inc, ph, BC<false>{}, sh);
   };
   auto by_phase = [&](auto s, auto w, auto inc) -> hipError_t {
     switch (phase) {
-      case kAAGather: return by_collision(s, w, inc, IC<kAAGather>{});
-      case kAALocal: return by_collision(s, w, inc, IC<kAALocal>{});
-      default: return by_collision(s, w, inc, IC<kTwoCopy>{});
+      case kAAGather: return by_collision(s, w, inc, IC<kAAGather>{}, BC<false>{});
+      case kAALocal: return by_collision(s, w, inc, IC<kAALocal>{}, BC<false>{});
+      default:
+        return shuffle ? by_collision(s, w, inc, IC<kTwoCopy>{}, BC<true>{})
+                       : by_collision(s, w, inc, IC<kTwoCopy>{}, BC<false>{});
     }
   };
   auto by_model = [&](auto s, auto w) -> hipError_t {
@@ -350,17 +447,18 @@ hipError_t with_variant(const Variant &v, int phase, F &&f) {
 
 bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
 
-hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst, const TileArgs &a,
+hipError_t launch_step19(const Variant &v, int phase, bool shuffle, const void *src, void *dst, const TileArgs &a,
                          const NbRec *nrec, const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef,
                          bool nontemporal, const int32_t *list, const int32_t *count, int mode,
                          int64_t blocks_persistent, hipStream_t s) {
   if (a.n_waves == 0) return hipSuccess;
   if ((phase == kTwoCopy) == (src == dst)) return hipErrorInvalidValue;  // in place exactly for the single copy
+  if (shuffle && phase != kTwoCopy) return hipErrorInvalidValue;
   const unsigned blocks =
       mode == kPersistent ? (unsigned)blocks_persistent : (unsigned)((a.n_waves + v.wpb - 1) / v.wpb);
-  return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc, auto mc) -> hipError_t {
+  return with_variant(v, phase, shuffle, [&](auto sc, auto wc, auto ic, auto pc, auto mc, auto hc) -> hipError_t {
     constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
-    constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value;
+    constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value, SH = decltype(hc)::value;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), 0, s, src, dst, a, nrec, nrow, rbase, coef, list, count);
       return hipGetLastError();
@@ -368,9 +466,9 @@ hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst
     auto by_mode = [&](auto nt) {
       constexpr bool NT = decltype(nt)::value;
       switch (mode) {
-        case kDirect: return go(k_step19<S, W, NT, INC, PH, MRT, kDirect>);
-        case kList: return go(k_step19<S, W, NT, INC, PH, MRT, kList>);
-        default: return go(k_step19<S, W, NT, INC, PH, MRT, kPersistent>);
+        case kDirect: return go(k_step19<S, W, NT, INC, PH, MRT, kDirect, SH>);
+        case kList: return go(k_step19<S, W, NT, INC, PH, MRT, kList, SH>);
+        default: return go(k_step19<S, W, NT, INC, PH, MRT, kPersistent, SH>);
       }
     };
     // MRT is built with non-temporal stores only (the planner rejects others)
@@ -380,18 +478,18 @@ hipError_t launch_step19(const Variant &v, int phase, const void *src, void *dst
 }
 
 // Workgroups of the persistent step that fit on the device at once.
-hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, int64_t *blocks) {
+hipError_t step19_persistent_blocks(const Variant &v, bool single_copy, bool shuffle, int64_t *blocks) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   // the grid must fit for every phase the solver alternates between
   auto fit = [&](int phase) -> hipError_t {
-    return with_variant(v, phase, [&](auto sc, auto wc, auto ic, auto pc, auto mc) -> hipError_t {
+    return with_variant(v, phase, shuffle, [&](auto sc, auto wc, auto ic, auto pc, auto mc, auto hc) -> hipError_t {
       constexpr int S = decltype(sc)::value, W = decltype(wc)::value, PH = decltype(pc)::value;
-      constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value;
+      constexpr bool INC = decltype(ic)::value, MRT = decltype(mc)::value, SH = decltype(hc)::value;
       int k = 0;
       const hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &k, k_step19<S, W, true, INC, PH, MRT, kPersistent>, 64 * W, 0);
+          &k, k_step19<S, W, true, INC, PH, MRT, kPersistent, SH>, 64 * W, 0);
       per = per < 0 ? k : (k < per ? k : per);
       return r;
     });

@@ -176,6 +176,22 @@ extern "C" int lbm_tiles_info(const lbm_tiles *t, lbm_tiles_info_t *out) {
   const double ntn = (double)t->tile[0] * t->tile[1] * t->tile[2];
   out->phi_t = t->n_ftiles ? (double)t->n_fluid / ((double)t->n_ftiles * ntn) : 0.0;
   out->tiles_ratio = t->n_ftiles ? (double)t->n_tiles / (double)t->n_ftiles : 0.0;
+  // alpha_M (Sec. 3.1.1.2): faces of non-empty tiles across which the
+  // neighbour tile is non-empty, over all faces of non-empty tiles; the faces
+  // counted are those of the axes along which the lattice has more than one
+  // node (two per axis)
+  int64_t faces = 0, shared = 0;
+  for (const lbm::Sample &S : t->samples) {
+    for (int a = 0; a < 3; ++a) {
+      if (S.grid[a] <= 1) continue;
+      const int step = a == 0 ? 1 : a == 1 ? 3 : 9;
+      for (int64_t k = S.tile0; k < S.tile0 + S.n_ftiles; ++k) {
+        shared += (t->nbr[(size_t)(k * 27 + 13 - step)] >= 0) + (t->nbr[(size_t)(k * 27 + 13 + step)] >= 0);
+        faces += 2;
+      }
+    }
+  }
+  out->alpha_m = faces ? (double)shared / (double)faces : 0.0;
   return LBM_OK;
 }
 

@@ -26,7 +26,7 @@ LBM_ERR_NOMEM = -7
 
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 ORDER = {"morton": 0, "rowmajor": 1}
-KERNEL = {"auto": 0, "generic": 1, "scalar": 2}
+KERNEL = {"auto": 0, "generic": 1, "scalar": 2, "shuffle": 3}
 STORE_POLICY = {"auto": 0, "regular": 1, "nontemporal": 2}
 MODEL = {"quasi-compressible": 0, "quasi": 0, "incompressible": 1}
 PATTERN = {"two-copy": 0, "single-copy": 1}
@@ -46,7 +46,7 @@ class TilesInfo(ctypes.Structure):
         ("n_samples", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("n_tiles", ctypes.c_int64), ("n_ftiles", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
         ("n_nodes", ctypes.c_int64), ("phi", ctypes.c_double), ("phi_t", ctypes.c_double),
-        ("tiles_ratio", ctypes.c_double),
+        ("tiles_ratio", ctypes.c_double), ("alpha_m", ctypes.c_double),
     ]
 
 
@@ -104,6 +104,8 @@ def lib():
             "lbm_pdfs_import": (ctypes.c_int, [P, P]),
             "lbm_step_count": (I64, [P]),
             "lbm_components": (ctypes.c_int, [I32, P, P, U32, I32, P, P]),
+            "lbm_components_device": (ctypes.c_int, [I32, P, P, U32, I32, P, P, P, P]),
+            "lbm_components_device_scratch": (I64, [P]),
             "lbm_project_invariants": (ctypes.c_int, [I32, P, U32, P, I32, ctypes.c_double, I32, P, P, P, P]),
             "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "lbm_last_error": (ctypes.c_char_p, []),
@@ -156,22 +158,49 @@ def components(solid, lattice=19, axis=-1, periodic=(1, 1, 1)):
     return labels, int(count.value)
 
 
+def components_device(solid, lattice=19, axis=-1, periodic=(1, 1, 1), stream=None):
+    """Device labels (torch int32, -1 on solid) and count of the fluid
+    components of a device uint8 (nz, ny, nx) mask: lbm_components_device,
+    the same labels as components()."""
+    import torch
+    m = solid if solid.dim() == 3 else solid.reshape((1,) + tuple(solid.shape))
+    if m.dtype != torch.uint8 or not m.is_contiguous() or not m.is_cuda:
+        raise ValueError("solid must be a contiguous uint8 CUDA tensor")
+    shape = np.array([m.shape[2], m.shape[1], m.shape[0]], np.int32)
+    n_scratch = lib().lbm_components_device_scratch(_np_ptr(shape))
+    labels = torch.empty(tuple(m.shape), dtype=torch.int32, device=m.device)
+    scratch = torch.empty(max(int(n_scratch), 1), dtype=torch.int32, device=m.device)
+    count = ctypes.c_int32()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().lbm_components_device(int(lattice), ctypes.c_void_p(m.data_ptr()), _np_ptr(shape),
+                                       _periodic_bits(periodic), int(axis), ctypes.c_void_p(labels.data_ptr()),
+                                       ctypes.byref(count), ctypes.c_void_p(scratch.data_ptr()),
+                                       ctypes.c_void_p(s.cuda_stream)), "lbm_components_device")
+    return labels, int(count.value)
+
+
 class Invariants:
     """Component labels of one geometry on the GPU and the scratch for
-    lbm_project_invariants."""
+    lbm_project_invariants.  solid: a host mask (labelled on the host) or a
+    device uint8 tensor (labelled on the device, lbm_components_device)."""
 
     def __init__(self, solid, lattice=19, periodic=(1, 1, 1), device="cuda"):
         import torch
-        m = np.asarray(solid)
-        if m.ndim == 2:
-            m = m[None]
         self.lattice = int(lattice)
-        self.shape = tuple(m.shape)
         self.periodic = _periodic_bits(periodic)
-        lab, self.count = components(m, self.lattice, -1, self.periodic)
-        self.labels = torch.from_numpy(lab).to(device)
+        if isinstance(solid, torch.Tensor):
+            m = solid if solid.dim() == 3 else solid.reshape((1,) + tuple(solid.shape))
+            self.shape = tuple(m.shape)
+            self.labels, self.count = components_device(m, self.lattice, -1, self.periodic)
+        else:
+            m = np.asarray(solid)
+            if m.ndim == 2:
+                m = m[None]
+            self.shape = tuple(m.shape)
+            lab, self.count = components(m, self.lattice, -1, self.periodic)
+            self.labels = torch.from_numpy(lab).to(device)
         n = int(np.prod(self.shape))
-        self.scratch = torch.empty(2 * self.count + 6 * n, dtype=torch.float64, device=device)
+        self.scratch = torch.empty(2 * self.count + 6 * n, dtype=torch.float64, device=self.labels.device)
 
     def project(self, rho, u, rho0=1.0, iterations=8, stream=None):
         """In place on device FP64 rho (nz, ny, nx) and u (3, nz, ny, nx)."""
@@ -221,7 +250,7 @@ class Tiles:
         return dict(shape=tuple(i.shape), grid=tuple(i.grid), tile=tuple(i.tile), tgrid=tuple(i.tgrid),
                     periodic=i.periodic, words=i.words, n_samples=i.n_samples, n_tiles=i.n_tiles,
                     n_ftiles=i.n_ftiles, n_fluid=i.n_fluid, n_nodes=i.n_nodes, phi=i.phi, phi_t=i.phi_t,
-                    tiles_ratio=i.tiles_ratio)
+                    tiles_ratio=i.tiles_ratio, alpha_m=i.alpha_m)
 
     def export(self):
         i = self.info

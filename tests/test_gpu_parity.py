@@ -2,8 +2,8 @@
 
 Bars: bit-exact where no arithmetic happens (pure streaming with tau = +inf
 and g = 0, checkpoint export/import, the tiling), FP64 PDFs within 1e-12
-relative after 1000 steps, FP64 reductions against math.fsum of the oracle's
-fields.  Shapes span several tiles with ragged (padded) edges.
+relative after 1000 steps (also on a crop of the benchmark geometry), FP64
+reductions against math.fsum of the oracle's fields after the same steps.  Shapes span several tiles with ragged (padded) edges.
 """
 import math
 import os
@@ -173,6 +173,91 @@ def test_reduce_and_residual(torch):
     assert math.isclose(s.residual()[0], want2, rel_tol=1e-12)
     # fixed-order reductions repeat exactly
     assert np.array_equal(s.reduce(), s.reduce())
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_reduce_and_residual_vs_oracle(torch, storage):
+    """lbm_reduce and lbm_residual against math.fsum of the oracle's own
+    fields after the same 10 steps (mass and momentum per Eq. 5, residual over
+    the non-solid nodes), with nothing taken from the GPU's moments.
+
+    FP64: the states agree to the parity bar, so the sums agree to 1e-13
+    (mass) and 1e-11 (momentum).  FP32 offsets: each stored offset rounds to
+    2^-24 of its magnitude; over q = 19 values, 10 steps and N_f nodes the
+    worst case, all errors of one sign, moves the mass by
+    N_f * 10 * 19 * 2^-23 * max|f - w rho0| (a factor 2 for the FP32
+    arithmetic), and the momentum by as much; the residual, a ratio of norms
+    of velocity differences of about 1e-2, is held to 1e-4 relative."""
+    mask = inputs.spheres_3d(24, 0.4, rmin=2, rmax=5, seed=12)[0]
+    g = (1e-5, 0.0, -2e-6)
+    tau, steps = 0.75, 10
+    t = _tiles(mask, 19)
+    s = lbm.Solver(t, lattice=19, tau=tau, g=g, storage=storage)
+    rho, u = inputs.random_macro(mask, seed=13)
+    s.init(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    s.step(steps)
+    tot = s.reduce()[0]
+    res = s.residual()[0]
+    f0 = dense.init(19, mask, rho=rho, u=u)
+    f1 = dense.step(19, mask, f0, tau, list(g), steps, periodic=7)
+    r0, u0 = dense.moments(19, mask, f0, g)
+    r1, u1 = dense.moments(19, mask, f1, g)
+    fl = ~mask
+    mass = math.fsum(r1[fl])
+    mom = [math.fsum((r1 * u1[k])[fl]) for k in range(3)]
+    want_res = math.sqrt(math.fsum(((u1 - u0)[:, fl] ** 2).ravel()) / math.fsum((u1[:, fl] ** 2).ravel()))
+    if storage == "f64":
+        bar_m, bar_p, bar_r = 1e-13 * mass, 1e-11 * max(abs(v) for v in mom), 1e-12
+    else:
+        _, w, _ = dense.lattice(19)
+        dmax = float(np.max(np.abs(f0 - w[:, None, None, None])[:, fl]))
+        bar_m = bar_p = int(fl.sum()) * steps * 19 * 2.0 ** -23 * dmax
+        bar_r = 1e-4
+    _log("reduce vs oracle", storage, "mass", tot[0] - mass, "bar", bar_m,
+         "momentum", [tot[1 + k] - mom[k] for k in range(3)], "bar", bar_p, "residual", res, want_res)
+    assert abs(tot[0] - mass) <= bar_m
+    for k in range(3):
+        assert abs(tot[1 + k] - mom[k]) <= bar_p
+    assert abs(res - want_res) <= bar_r * want_res
+
+
+def _sphere256_crop():
+    """A 64^3 crop of the 256^3 porosity-0.3 sphere packing (seed 0, radii
+    4-12) that the step benchmark runs, with every axis closed: positions
+    outside the crop count as solid."""
+    mask, _ = inputs.spheres_3d(256, 0.3, 4.0, 12.0, seed=0)
+    return np.ascontiguousarray(mask[:64, :64, :64])
+
+
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
+def test_fp64_1000_steps_sphere256_crop(torch, kernel):
+    """FP64 PDFs within 1e-12 of the oracle after 1000 steps on a crop of the
+    benchmark geometry (tau 0.7, g 1e-6 along x, from rest)."""
+    mask = _sphere256_crop()
+    g = (1e-6, 0.0, 0.0)
+    _log("sphere256 crop fp64", kernel, "porosity", float((~mask).mean()))
+    f, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (0, 0, 0), kernel=kernel)
+    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=0, nthreads=8)
+    fl = ~mask
+    err = np.max(np.abs(f - want)[:, fl] / np.abs(want)[:, fl])
+    _log("sphere256 crop fp64", kernel, "max rel PDF error", err)
+    assert err <= 1e-12
+    _, uw = dense.moments(19, mask, want, g)
+    assert _rel(v, uw) <= 1e-9
+
+
+def test_f32_1000_steps_sphere256_crop(torch):
+    """FP32 offsets on the same crop: velocity rel-L2 against the FP64 oracle
+    within the 2e-5 bar of the offset forms."""
+    mask = _sphere256_crop()
+    g = (1e-6, 0.0, 0.0)
+    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (0, 0, 0), storage="f32")
+    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=0, nthreads=8)
+    _, uw = dense.moments(19, mask, want, g)
+    fl = ~mask
+    err = np.linalg.norm((v - uw)[:, fl]) / np.linalg.norm(uw[:, fl])
+    _log("sphere256 crop f32 velocity rel-L2", err)
+    assert err <= 2e-5
 
 
 def test_checkpoint_resume_bitexact(torch):

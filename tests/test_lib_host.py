@@ -48,6 +48,7 @@ def test_tiles_bitexact_vs_oracle(name, mask, tile, periodic):
     i = t.info
     assert i["n_ftiles"] == o["n_ftiles"] and i["n_fluid"] == o["n_fluid"] and i["n_tiles"] == o["n_tiles"]
     assert i["phi"] == o["phi"] and math.isclose(i["phi_t"], o["phi_t"], rel_tol=1e-15)
+    assert i["alpha_m"] == o["alpha_m"]
     assert tuple(i["grid"]) == tuple(o["grid"])
 
 
@@ -77,6 +78,7 @@ def test_tiles_random_masks_bitexact(data):
     for k in ("tile_map", "tile_coord", "nbr", "fluid"):
         assert np.array_equal(e[k], o[k]), k
     assert t.info["n_fluid"] == o["n_fluid"] and t.info["n_ftiles"] == o["n_ftiles"]
+    assert t.info["alpha_m"] == o["alpha_m"]
 
 
 def test_tiles_concat_offsets_rows():

@@ -96,6 +96,53 @@ def test_tiles_match_brute_force(a, periodic, shape, seed):
     assert nf == int((~mask).sum()) == t["n_fluid"]
 
 
+@pytest.mark.parametrize("a,periodic,shape", CASES)
+def test_alpha_m_brute_force(a, periodic, shape):
+    """alpha_M from tile coordinates alone: for each non-empty tile and each
+    face along an axis with more than one node, whether the tile across the
+    face (wrapped on periodic axes) holds a non-solid node."""
+    rng = np.random.default_rng(3)
+    nx, ny, nz = shape
+    mask = rng.random((nz, ny, nx)) < 0.6
+    t = tiles.tile(mask, a, periodic)
+    tmap, coord, _, _ = brute_tiles(mask, a, periodic)
+    n = (nx, ny, nz)
+    T = [-(-n[k] // a[k]) for k in range(3)]
+    occupied = set(tuple(coord[3 * j:3 * j + 3]) for j in range(len(coord) // 3))
+    faces = shared = 0
+    for c in occupied:
+        for ax in range(3):
+            if T[ax] * a[ax] <= 1:
+                continue
+            for s in (-1, 1):
+                faces += 1
+                o = list(c)
+                o[ax] += s
+                if periodic[ax]:
+                    o[ax] %= T[ax]
+                elif not 0 <= o[ax] < T[ax]:
+                    continue
+                shared += tuple(o) in occupied
+    assert t["alpha_m"] == shared / faces
+
+
+def test_alpha_m_closed_forms():
+    """A fluid box closed on every axis with T tiles per axis: 1 - 1/T (the
+    2 of the 2T faces per tile row that lie on the box); periodic: 1; an
+    isolated tile: 0; a 2D lattice counts the x and y faces only."""
+    for T in (1, 2, 3, 5):
+        t = tiles.tile(np.zeros((4 * T,) * 3, bool), (4, 4, 4), (0, 0, 0))
+        assert t["alpha_m"] == pytest.approx(1.0 - 1.0 / T, abs=1e-15)
+    assert tiles.tile(np.zeros((8, 12, 16), bool), (4, 4, 4), (1, 1, 1))["alpha_m"] == 1.0
+    m = np.ones((12, 12, 12), bool)
+    m[5, 6, 4] = False
+    assert tiles.tile(m, (4, 4, 4), (1, 1, 1))["alpha_m"] == 0.0
+    # 2D: 3 x 2 tiles of 16 x 16, periodic in x, closed in y: both x faces of
+    # every tile are shared, one of its two y faces
+    t = tiles.tile(np.zeros((1, 32, 48), bool), (16, 16, 1), (1, 0, 0))
+    assert t["alpha_m"] == pytest.approx((6 * 2 + 6 * 1) / (6 * 4), abs=1e-15)
+
+
 def test_tiles_edge_cases():
     a = (4, 4, 4)
     # all solid: no tiles
