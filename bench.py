@@ -135,8 +135,9 @@ def record_traffic(args, argv):
             return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if r["Kernel_Name"] == name]
 
     true_kib = args.copy_gib * (1 << 20)
-    fc, wc = values(fetch_dir, "vectorized_elementwise_kernel"), values(write_dir, "vectorized_elementwise_kernel")
-    fc = sorted(fc)[1:]  # drop the fill, which fetches (almost) nothing
+    fc, wc = values(fetch_dir, COPY_KERNEL), values(write_dir, COPY_KERNEL)
+    if not fc or not wc:
+        raise SystemExit("no %s dispatches in the counter runs" % COPY_KERNEL)
     f_scale, w_scale = true_kib / (sum(fc) / len(fc)), true_kib / (sum(wc) / len(wc))
     fk, wk = values(fetch_dir, csv_name), values(write_dir, csv_name)
     if not fk or not wk:
@@ -167,14 +168,32 @@ def record_traffic(args, argv):
 
 
 def _cpu_model():
+    """The host CPU as /proc/cpuinfo reports it: the model name plus the x86
+    family / model / stepping numbers (a virtualised host may print only the
+    vendor's brand in the name), and lscpu's model name if it differs."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
     except OSError:
+        return "unknown"
+    name = info.get("model name", "unknown")
+    out = "%s (family %s, model %s, stepping %s, %s MHz)" % (name, info.get("cpu family", "?"), info.get("model", "?"),
+                                                           info.get("stepping", "?"), info.get("cpu MHz", "?"))
+    try:
+        import subprocess
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            if line.startswith("Model name:"):
+                ls = line.split(":", 1)[1].strip()
+                if ls and ls != name:
+                    out += "; lscpu: " + ls
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    return out
 
 
 def cpu_baseline(mask, args):
@@ -207,26 +226,33 @@ def cpu_baseline(mask, args):
             "single_thread_mlups": nf * one / dt1 / 1e6, "single_thread_steps": one, "cpu_model": _cpu_model()}
 
 
-def copy_reference(torch, gib, reps=20):
-    """Achievable HBM bandwidth of a plain elementwise device copy (dst = src * 1)
-    of known size; the same kernel calibrates the rocprofv3 byte counters."""
+COPY_KERNEL = "k_copy16"  # lbm_device_copy's kernel, as rocprofv3 -T names it
+
+
+def copy_reference(torch, lbm, gib, reps=10):
+    """Achievable HBM bandwidth of the library's own device copy
+    (lbm_device_copy: 16-byte non-temporal loads and stores, a fixed grid per
+    compute unit) over buffers of ``gib`` GiB each, timed with HIP events on
+    the current stream; the same kernel calibrates the rocprofv3 byte
+    counters."""
     n = int(gib * (1 << 30)) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
-        torch.mul(src, 1.0, out=dst)
+        lbm.device_copy(dst, src)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
-        torch.mul(src, 1.0, out=dst)
+        lbm.device_copy(dst, src)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    assert bool((dst[:: max(n // 4096, 1)] == 1.0).all()), "device copy lost data"
     del src, dst
     torch.cuda.empty_cache()
-    return {"bytes_read": 8 * n, "bytes_written": 8 * n, "ms": round(ms, 4),
+    return {"kernel": "lbm_device_copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "ms": round(ms, 4),
             "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}
 
 
@@ -419,15 +445,18 @@ def mode_unet(args, torch, lbm):
 
 
 def mode_warmstart(args, torch, lbm):
-    """Train the U-Net on steady states of the porous-cube batch (edges that
-    are multiples of 8), then compare warm and cold starts to the same
-    residual on held-out 128^3 porous samples."""
+    """Train the U-Net on steady states of the porous-cube batch (every cube;
+    those whose edge is not a multiple of 8 tiled twice per axis, an exact
+    periodic image), then compare warm and cold starts to the same residual
+    on held-out 128^3 porous samples, and measure steps against the error of
+    the starting fields on the first few of them."""
     from paper_1703_08015_amd import inputs, warmstart
     t0 = time.perf_counter()
-    specs = [sp for sp in inputs.batch_specs(args.batch, seed=args.seed + 1000) if sp["edge"] % 8 == 0]
+    specs = inputs.batch_specs(args.batch, seed=args.seed + 1000)
     masks = [inputs.porous_cube(sp)[0] for sp in specs]
     data, steps, _ = warmstart.steady_dataset(torch, masks, [sp["g"] for sp in specs], tau=args.tau,
                                               progress=_progress("data"))
+    data = [warmstart.training_view(torch, sm) for sm in data]
     t_data = time.perf_counter() - t0
     out_scale = warmstart.make_targets(torch, data, args.tau)
     net = warmstart.make_net(levels=4, base=24, seed=args.seed, out_scale=out_scale)
@@ -456,6 +485,12 @@ def mode_warmstart(args, torch, lbm):
                  r["prediction_u_rel_l2"], r["warm_vs_cold_u_rel_l2"], r["warm_vs_cold_f64_u_rel_l2"],
                  " (fell back)" if r["fell_back"] else ""), file=sys.stderr, flush=True)
         rows.append(r)
+    curves = []
+    for k, sm in enumerate(tests[:args.curve_samples]):
+        cold, pts = warmstart.error_curve(torch, net, sm, args.tau)
+        print("[curve] sample %d cold %d steps; %s" % (k, cold["cold_steps"], ", ".join(
+            "err %.3g -> %d steps" % (p["start_u_rel_l2"], p["steps"]) for p in pts)), file=sys.stderr, flush=True)
+        curves.append(dict(sample=k, **cold, points=pts))
     cold_s = sum(r["cold_s"] for r in rows)
     warm_s = sum(r["warm_s"] for r in rows)
     return {"metric": "time to steady state, warm vs cold start", "unit": "s", "higher_is_better": False,
@@ -464,21 +499,22 @@ def mode_warmstart(args, torch, lbm):
                                    "|g| 1e-6 random direction), tau %.2f, FP32 LBM to residual %g" %
                                    (args.test_samples, args.tau, args.tol),
                        "network": "U-Net 4 levels, 24 base channels, %d parameters" % net.n_params(),
-                       "training": "%d porous cubes (edges 32..96, multiples of 8), %d epochs, Adam lr %g" %
-                                   (len(specs), args.epochs, args.lr)},
+                       "training": "%d porous cubes (edges 32..96; edges not a multiple of 8 tiled twice per "
+                                   "axis), %d epochs, Adam lr %g" % (len(specs), args.epochs, args.lr)},
             "cold_seconds": round(cold_s, 3), "warm_seconds_incl_inference": round(warm_s, 3),
             "speedup": round(cold_s / warm_s, 3) if warm_s > 0 else None,
             "cold_f64_seconds": round(sum(r["cold_f64_s"] for r in rows), 3),
             "speedup_vs_cold_f64": round(sum(r["cold_f64_s"] for r in rows) / warm_s, 3) if warm_s > 0 else None,
             "warm_vs_cold_f64_u_rel_l2_max": float(np.max([r["warm_vs_cold_f64_u_rel_l2"] for r in rows])),
-            "labels_seconds": round(sum(r["labels_s"] for r in rows), 3),
+            "labels_seconds_in_warm": round(sum(r["labels_s"] for r in rows), 3),
+            "inference_seconds_in_warm": round(sum(r["inference_s"] for r in rows), 3),
             "cold_steps_mean": float(np.mean([r["cold_steps"] for r in rows])),
             "warm_steps_mean": float(np.mean([r["warm_steps"] for r in rows])),
             "prediction_u_rel_l2_mean": float(np.mean([r["prediction_u_rel_l2"] for r in rows])),
             "warm_vs_cold_u_rel_l2_max": float(np.max([r["warm_vs_cold_u_rel_l2"] for r in rows])),
             "fallbacks": int(sum(r["fell_back"] for r in rows)),
             "train_loss_first_last": [hist[0], hist[-1]], "data_seconds": round(t_data, 1),
-            "train_seconds": round(t_train, 1), "rows": rows}
+            "train_seconds": round(t_train, 1), "rows": rows, "error_curves": curves}
 
 
 def main():
@@ -512,12 +548,14 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--test-samples", type=int, default=16)
+    ap.add_argument("--curve-samples", type=int, default=4,
+                    help="warmstart mode: held-out samples on which steps are measured against the start error")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--max-steps", type=int, default=200000)
     ap.add_argument("--vessel-steps", type=int, default=5000)
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--copy-gib", type=float, default=1.0,
+    ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="size of the device copy reference (read + write each this many GiB); 0 = skip")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="host only: store the step kernel's HBM bytes from two rocprofv3 --pmc runs "
@@ -558,7 +596,6 @@ def main():
         res["n_gpus"] = 1
         print(json.dumps(res), flush=True)
         return
-    copy_ref = copy_reference(torch, args.copy_gib) if args.copy_gib > 0 else None
     mask, phi, desc = workload(args)
     g, per, lid, q, tile = step_setup(args)
     tiles = lbm.Tiles(mask, tile, per)
@@ -569,6 +606,8 @@ def main():
                         pattern=args.pattern, collision=args.collision)
     if lid is not None:
         solver.set_lid(*lid)
+    # the copy reference runs right before the step's warm-up, on the same device state
+    copy_ref = copy_reference(torch, lbm, args.copy_gib) if args.copy_gib > 0 else None
     solver.init()
     solver.step(args.warmup)
     torch.cuda.synchronize()

@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbm.so")
 
-SOURCES = ["tiles.cpp", "solver.cpp", "components.cpp", "kernels.hip", "step19.hip", "nn.hip", "invariants.hip"]
+SOURCES = ["tiles.cpp", "solver.cpp", "components.cpp", "kernels.hip", "step19.hip", "nn.hip", "invariants.hip",
+           "bandwidth.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

@@ -107,6 +107,7 @@ def lib():
             "lbm_components_device": (ctypes.c_int, [I32, P, P, U32, I32, P, P, P, P]),
             "lbm_components_device_scratch": (I64, [P]),
             "lbm_project_invariants": (ctypes.c_int, [I32, P, U32, P, I32, ctypes.c_double, I32, P, P, P, P]),
+            "lbm_device_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
             "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "lbm_last_error": (ctypes.c_char_p, []),
         }
@@ -156,6 +157,17 @@ def components(solid, lattice=19, axis=-1, periodic=(1, 1, 1)):
     _check(lib().lbm_components(int(lattice), _np_ptr(m), _np_ptr(shape), _periodic_bits(periodic), int(axis),
                                 _np_ptr(labels), ctypes.byref(count)), "lbm_components")
     return labels, int(count.value)
+
+
+def device_copy(dst, src, stream=None):
+    """lbm_device_copy of src into dst (torch CUDA tensors of equal byte size)."""
+    import torch
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("device_copy: sizes differ")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().lbm_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nb,
+                                 ctypes.c_void_p(s.cuda_stream)), "lbm_device_copy")
 
 
 def components_device(solid, lattice=19, axis=-1, periodic=(1, 1, 1), stream=None):

@@ -43,9 +43,10 @@ class Sample:
 
     @property
     def invariants(self):
-        """Component labels of the geometry on the GPU (built on first use)."""
+        """Component labels of the geometry, computed on the GPU from the
+        device mask (lbm_components_device) on first use."""
         if self._inv is None:
-            self._inv = lbm.Invariants(self._mask, 19)
+            self._inv = lbm.Invariants(self.solid, 19)
         return self._inv
 
 
@@ -69,6 +70,22 @@ def steady_dataset(torch, masks, gs, tau=0.8, storage="f32", tol=1e-6, check_eve
         o += n
     del s
     return out, steps, res
+
+
+def training_view(torch, sample, multiple=8):
+    """The sample as the network trains on it: every edge must be a multiple
+    of 2^(levels-1) = 8.  A periodic cube whose edge is not is tiled twice
+    along each axis; the doubled box is periodic too and, since the discrete
+    step commutes with translations, its steady state from rest is exactly
+    the tiled steady state, so geometry and target stay consistent."""
+    if all(n % multiple == 0 for n in sample.shape):
+        return sample
+    if any((2 * n) % multiple for n in sample.shape):
+        raise ValueError("edges %s cannot be doubled to multiples of %d" % (sample.shape, multiple))
+    mask = np.tile(sample._mask, (2, 2, 2))
+    rho = sample.rho.repeat(2, 2, 2)
+    u = sample.u.repeat(1, 2, 2, 2)
+    return Sample(torch, mask, sample.g, rho, u)
 
 
 def make_targets(torch, samples, tau, rho0=1.0, out_scale=None):
@@ -175,9 +192,11 @@ def predict_fields(torch, net, sample, tau, rho0=1.0, project=True):
     return rho, u
 
 
-def solve(torch, sample, tau, init=None, storage="f32", tol=1e-6, check_every=100, max_steps=200000):
+def solve(torch, sample, tau, init=None, storage="f32", tol=1e-6, check_every=100, max_steps=200000,
+          with_rho=False):
     """Run one geometry to steady state from rest (init None) or from given
-    (rho, u); returns (steps, seconds, final u, fell_back)."""
+    (rho, u); returns (steps, seconds, final u, fell_back), and the final rho
+    after them if with_rho."""
     tiles = lbm.Tiles(sample.solid.cpu().numpy().astype(bool))
     s = lbm.Solver(tiles, lattice=19, storage=storage, tau=tau, g=tuple(sample.g), graph_steps=check_every)
     torch.cuda.synchronize()
@@ -202,10 +221,11 @@ def solve(torch, sample, tau, init=None, storage="f32", tol=1e-6, check_every=10
     steps, res = s.run_to_steady(tol=tol, check_every=check_every, max_steps=max_steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    _, u = s.moments()
+    rho, u = s.moments()
     taken = int(s.step_count)
     del s
-    return taken if steps[0] > 0 else -1, wall, u, fell_back
+    out = (taken if steps[0] > 0 else -1, wall, u, fell_back)
+    return out + (rho,) if with_rho else out
 
 
 def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100, project=True, fp64_cold=False):
@@ -219,14 +239,17 @@ def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100,
         if fp64_cold:
             s64, t64, u64, _ = solve(torch, sm, tau, None, "f64", tol, check_every)
             extra = dict(cold_f64_steps=s64, cold_f64_s=t64, u64=u64)
-        # component labels are geometry preprocessing (host), like the tiling
-        # that neither path times
-        t_lab = time.perf_counter()
-        sm.invariants
-        t_lab = time.perf_counter() - t_lab
-        sm.x = None  # the geometry input is part of inference
+        # everything only the warm path needs is timed with it: the geometry
+        # input, the forward pass, the component labels (on the GPU) and the
+        # projection; the tiling, which both paths need, is timed by neither
+        sm.x = None
+        sm._inv = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        if project:
+            sm.invariants
+        torch.cuda.synchronize()
+        t_lab = time.perf_counter() - t0
         init = predict_fields(torch, net, sm, tau, project=project)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
@@ -235,8 +258,8 @@ def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100,
         warm_steps, warm_s, u_warm, fb = solve(torch, sm, tau, init, storage, tol, check_every)
         agree = float(((u_warm[:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
         row = dict(cold_steps=cold_steps, cold_s=cold_s, warm_steps=warm_steps, warm_s=warm_s + t_inf,
-                   inference_s=t_inf, labels_s=t_lab, prediction_u_rel_l2=pred_err, warm_vs_cold_u_rel_l2=agree,
-                   fell_back=fb)
+                   inference_s=t_inf, labels_s=t_lab, solve_s=warm_s, prediction_u_rel_l2=pred_err,
+                   warm_vs_cold_u_rel_l2=agree, fell_back=fb)
         if extra:
             u64 = extra.pop("u64")
             row.update(extra)
@@ -244,3 +267,27 @@ def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100,
                                                      (u64[:, fl] ** 2).sum().sqrt())
         rows.append(row)
     return rows
+
+
+def error_curve(torch, net, sample, tau, scales=(0.0, 0.03, 0.1, 0.3, 1.0), storage="f32", tol=1e-6,
+                check_every=100):
+    """Steps to steady state against the error of the starting fields.  The
+    exact steady fields (rho*, u*) of a cold run are moved towards the
+    network's prediction, (rho*, u*) + s (prediction - (rho*, u*)) for each
+    scale s, projected onto the invariants of rest and solved from there:
+    s = 1 is the network itself, s = 0 the best any f_eq start can do.
+    Returns the cold run and one row per scale."""
+    cold_steps, cold_s, u_ref, _, rho_ref = solve(torch, sample, tau, None, storage, tol, check_every,
+                                                  with_rho=True)
+    rho_p, u_p = predict_fields(torch, net, sample, tau, project=False)
+    fl = sample.solid == 0
+    norm = float((u_ref[:, fl] ** 2).sum().sqrt())
+    rows = []
+    for sc in scales:
+        rho = rho_ref + sc * (rho_p - rho_ref)
+        u = u_ref + sc * (u_p - u_ref)
+        err = float(((u - u_ref)[:, fl] ** 2).sum().sqrt()) / norm
+        sample.invariants.project(rho, u, 1.0)
+        steps, secs, _, fb = solve(torch, sample, tau, (rho, u), storage, tol, check_every)
+        rows.append(dict(scale=sc, start_u_rel_l2=err, steps=steps, seconds=secs, fell_back=fb))
+    return dict(cold_steps=cold_steps, cold_s=cold_s), rows
