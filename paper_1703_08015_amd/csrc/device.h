@@ -371,6 +371,59 @@ __device__ __forceinline__ R cdot(R x, R y, R z) {
   return r;
 }
 
+// Moments of the Guo source F_i = w_i m [3 (c_i - u).g + 9 (c_i.u)(c_i.g)]
+// in closed form: for a row P_k of the basis,
+//   sum_i P_k(c_i) F_i = m [3 sum_a A_a g_a - 3 B (u.g) + 9 sum_ab C_ab u_a g_b]
+// with the lattice sums B = sum_i w_i P_k(c_i), A_a = sum_i w_i P_k(c_i) c_ia
+// and C_ab = sum_i w_i P_k(c_i) c_ia c_ib (compile-time constants, most of
+// them zero), so the source never has to be formed per direction.
+template <class L>
+constexpr double mrt_src_B(int k) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::Wt[i] * mrt_row<L>(k, i).value;
+  return s;
+}
+template <class L>
+constexpr double mrt_src_A(int k, int a) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::Wt[i] * mrt_row<L>(k, i).value * L::C[i][a];
+  return s;
+}
+template <class L>
+constexpr double mrt_src_C(int k, int a, int b) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::Wt[i] * mrt_row<L>(k, i).value * L::C[i][a] * L::C[i][b];
+  return s;
+}
+
+template <class L, int K, class R>
+__device__ __forceinline__ R mrt_source_moment(R m, const R (&u)[3], const R (&g)[3], R ug) {
+  R acc = R(0);
+  bool any = false;
+  auto add = [&](R term) {
+    acc = any ? acc + term : term;
+    any = true;
+  };
+  static_for<3>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    constexpr double ca = 3.0 * mrt_src_A<L>(K, a);
+    if constexpr (ca != 0.0) add(R(ca) * g[a]);
+  });
+  {
+    constexpr double cb = -3.0 * mrt_src_B<L>(K);
+    if constexpr (cb != 0.0) add(R(cb) * ug);
+  }
+  static_for<3>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    static_for<3>([&](auto B) {
+      constexpr int b = decltype(B)::value;
+      constexpr double cc = 9.0 * mrt_src_C<L>(K, a, b);
+      if constexpr (cc != 0.0) add(R(cc) * (u[a] * g[b]));
+    });
+  });
+  return any ? m * acc : R(0);
+}
+
 template <class L, int S, bool INC, class R>
 __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R jz, R rho0, R gx, R gy, R gz,
                                             const MrtRates &mr) {
@@ -395,35 +448,31 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R j
     uz = std::fma(jz, inv, R(0.5) * gz);
   }
   const R uu = std::fma(ux, ux, std::fma(uy, uy, uz * uz));
-  R d[Q], F[Q];
-  static_for<Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
-    constexpr R w = (R)L::Wt[i];
-    // c has components in {-1, 0, 1}: signed sums of the nonzero terms
-    const R cu = cdot<cx, cy, cz>(ux, uy, uz);
-    const R cg = cdot<cx, cy, cz>(gx, gy, gz);
-    const R ug = std::fma(ux, gx, std::fma(uy, gy, uz * gz));
-    const R poly = std::fma(R(3), cu, std::fma(R(4.5) * cu, cu, R(-1.5) * uu));
-    // f_eq (or its offset): w (rho + m poly), w (drho + m poly)
-    const R feq = w * std::fma(m, poly, off ? sum : rho);
-    d[i] = f[i] - feq;
-    // Guo source: w m [3 (c - u).g + 9 (c.u)(c.g)]
-    F[i] = (w * m) * std::fma(R(9) * cu, cg, R(3) * (cg - ug));
-  });
+  const R ug = std::fma(ux, gx, std::fma(uy, gy, uz * gz));
+  const R uv[3] = {ux, uy, uz}, gv[3] = {gx, gy, gz};
   // The transforms work on pair sums and differences: an even row reads
   // d_i + d_opp(i) (and the rest direction), an odd row d_i - d_opp(i), so
   // each row takes half the terms; the inverse collects the even and odd rows'
   // contributions per pair and splits them back over the two directions.
   constexpr int P = (Q - 1) / 2;
-  R ds[P], dd[P], fs[P], fd[P], ev[P], od[P];
+  R ds[P], dd[P], ev[P], od[P];
+  auto dev = [&](auto I) -> R {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::C[i][0], cy = L::C[i][1], cz = L::C[i][2];
+    constexpr R w = (R)L::Wt[i];
+    // c has components in {-1, 0, 1}: signed sums of the nonzero terms
+    const R cu = cdot<cx, cy, cz>(ux, uy, uz);
+    const R poly = std::fma(R(3), cu, std::fma(R(4.5) * cu, cu, R(-1.5) * uu));
+    // f - f_eq, with f_eq (or its offset) w (rho + m poly), w (drho + m poly)
+    return f[i] - w * std::fma(m, poly, off ? sum : rho);
+  };
+  const R d0 = dev(std::integral_constant<int, 0>{});
   static_for<P>([&](auto Pc) {
     constexpr int p = decltype(Pc)::value;
     constexpr int i = pair_dir<L>(p), j = L::Opp[i];
-    ds[p] = d[i] + d[j];
-    dd[p] = d[i] - d[j];
-    fs[p] = F[i] + F[j];
-    fd[p] = F[i] - F[j];
+    const R di = dev(std::integral_constant<int, i>{}), dj = dev(std::integral_constant<int, j>{});
+    ds[p] = di + dj;
+    dd[p] = di - dj;
     ev[p] = R(0);
     od[p] = R(0);
   });
@@ -440,19 +489,14 @@ __device__ __forceinline__ void collide_mrt(R (&f)[L::Q], R sum, R jx, R jy, R j
     constexpr int par = mrt_parity<L>(k);
     static_assert(par != 0, "every moment of the basis is even or odd in c");
     constexpr int c0 = mrt_row<L>(k, 0).value;  // zero in every odd row
-    R dm = 0, fm = 0;
-    if constexpr (c0 != 0) {
-      dm = madd(std::integral_constant<int, c0>{}, d[0], dm);
-      fm = madd(std::integral_constant<int, c0>{}, F[0], fm);
-    }
+    R dm = 0;
+    if constexpr (c0 != 0) dm = madd(std::integral_constant<int, c0>{}, d0, dm);
     static_for<P>([&](auto Pc) {
       constexpr int p = decltype(Pc)::value;
       constexpr int c = mrt_row<L>(k, pair_dir<L>(p)).value;
-      if constexpr (c != 0) {
-        dm = madd(std::integral_constant<int, c>{}, par > 0 ? ds[p] : dd[p], dm);
-        fm = madd(std::integral_constant<int, c>{}, par > 0 ? fs[p] : fd[p], fm);
-      }
+      if constexpr (c != 0) dm = madd(std::integral_constant<int, c>{}, par > 0 ? ds[p] : dd[p], dm);
     });
+    const R fm = mrt_source_moment<L, k>(m, uv, gv, ug);
     constexpr int cl = mrt_row<L>(k, 0).cls;
     constexpr R inv = R(1.0 / mrt_norm<L>(k));
     R ms, mh;
