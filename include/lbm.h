@@ -329,6 +329,24 @@ int lbm_components_device(int32_t q, const uint8_t *solid, const int32_t shape[3
  * bad shape. */
 int64_t lbm_components_device_scratch(const int32_t shape[3]);
 
+/* lbm_components_device for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same labels and count, with the scratch taken from a fixed
+ * device array inside the library instead of a caller buffer.  The array
+ * holds lbm_components_noalloc_max_scratch() int32 entries (2^22, 16 MiB;
+ * each GPU the library runs on keeps its own copy until the process ends),
+ * so a shape whose lbm_components_device_scratch(shape) exceeds it (more
+ * than 4,193,280 nodes) fails with LBM_ERR_ARG.  Nothing is allocated:
+ * the array's device address is looked up once per device on the first
+ * call.  Every call on one GPU shares the array and leaves its contents
+ * behind (nothing in it needs clearing: every entry used is written before
+ * it is read), so calls that overlap on one GPU race; the stream is
+ * synchronised before return.  Errors as for lbm_components_device. */
+int lbm_components_device_noalloc(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
+                                  int32_t axis, int32_t *labels, int32_t *count, void *stream);
+/* Size of that fixed array, in int32 entries. */
+int64_t lbm_components_noalloc_max_scratch(void);
+
 /* Give a starting state (rho, u) for lbm_init the invariants of a start
  * from rest.
  *   q, shape, periodic  the lattice, as for lbm_components;

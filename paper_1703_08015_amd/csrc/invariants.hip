@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.h"
 #include "internal.h"
@@ -375,21 +376,14 @@ extern "C" int64_t lbm_components_device_scratch(const int32_t shape[3]) {
   return n + (n + per - 1) / per + 1;
 }
 
-extern "C" int lbm_components_device(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
-                                     int32_t axis, int32_t *labels, int32_t *count, int32_t *scratch,
-                                     void *stream) {
-  if (!solid || !shape || !labels || !count || !scratch)
-    return set_error(LBM_ERR_ARG, "lbm_components_device: NULL argument");
-  if (q != 9 && q != 19) return set_error(LBM_ERR_UNSUPPORTED, "lbm_components_device: q = %d", q);
-  if (shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0)
-    return set_error(LBM_ERR_ARG, "lbm_components_device: shape %d x %d x %d", shape[0], shape[1], shape[2]);
-  if (q == 9 && shape[2] != 1) return set_error(LBM_ERR_ARG, "lbm_components_device: D2Q9 needs shape[2] = 1");
-  if (periodic > 7u) return set_error(LBM_ERR_ARG, "lbm_components_device: periodic bits %u", periodic);
-  if (axis < -1 || axis >= (q == 9 ? 2 : 3))
-    return set_error(LBM_ERR_ARG, "lbm_components_device: axis %d for q = %d", axis, q);
+namespace {
+
+// The labelling behind both device entry points; scratch holds
+// lbm_components_device_scratch(shape) int32 entries, every one written
+// before it is read.
+int components_device(const char *who, int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
+                      int32_t axis, int32_t *labels, int32_t *count, int32_t *scratch, hipStream_t s) {
   const int64_t n = (int64_t)shape[0] * shape[1] * shape[2];
-  if (n > INT32_MAX) return set_error(LBM_ERR_ARG, "lbm_components_device: %lld nodes exceed int32 labels", (long long)n);
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const CcGrid g{shape[0], shape[1], shape[2]};
   const int64_t per = (int64_t)kScanBlock * kScanItems, nb = (n + per - 1) / per;
   int32_t *flag = scratch, *sums = scratch + n;
@@ -406,6 +400,83 @@ extern "C" int lbm_components_device(int32_t q, const uint8_t *solid, const int3
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(count, sums + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return set_error(LBM_ERR_HIP, "lbm_components_device: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return set_error(LBM_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
   return LBM_OK;
+}
+
+// Argument checks shared by both device entry points.
+int components_device_args(const char *who, int32_t q, const uint8_t *solid, const int32_t shape[3],
+                           uint32_t periodic, int32_t axis, const int32_t *labels, const int32_t *count) {
+  if (!solid || !shape || !labels || !count) return set_error(LBM_ERR_ARG, "%s: NULL argument", who);
+  if (q != 9 && q != 19) return set_error(LBM_ERR_UNSUPPORTED, "%s: q = %d", who, q);
+  if (shape[0] <= 0 || shape[1] <= 0 || shape[2] <= 0)
+    return set_error(LBM_ERR_ARG, "%s: shape %d x %d x %d", who, shape[0], shape[1], shape[2]);
+  if (q == 9 && shape[2] != 1) return set_error(LBM_ERR_ARG, "%s: D2Q9 needs shape[2] = 1", who);
+  if (periodic > 7u) return set_error(LBM_ERR_ARG, "%s: periodic bits %u", who, periodic);
+  if (axis < -1 || axis >= (q == 9 ? 2 : 3)) return set_error(LBM_ERR_ARG, "%s: axis %d for q = %d", who, axis, q);
+  const int64_t n = (int64_t)shape[0] * shape[1] * shape[2];
+  if (n > INT32_MAX) return set_error(LBM_ERR_ARG, "%s: %lld nodes exceed int32 labels", who, (long long)n);
+  return LBM_OK;
+}
+
+// Fixed scratch of lbm_components_device_noalloc: one copy per GPU, held
+// until the process ends.  Host code never passes this name to a kernel (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoAllocEntries = int64_t(1) << 22;  // int32 entries, 16 MiB
+static __device__ __align__(256) int32_t cc_noalloc_scratch[kNoAllocEntries];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of cc_noalloc_scratch on the current device, looked up
+// once per device (with that device current) and kept.
+int noalloc_scratch(const char *who, int32_t **out) {
+  static std::mutex mu;
+  static int32_t *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(LBM_ERR_HIP, "%s: %s", who, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LBM_ERR_UNSUPPORTED, "%s: device %d", who, dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(cc_noalloc_scratch));
+    if (e != hipSuccess || !p)
+      return set_error(LBM_ERR_HIP, "%s: scratch address: %s", who, hipGetErrorString(e));
+    addr[dev] = static_cast<int32_t *>(p);
+  }
+  *out = addr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_components_device(int32_t q, const uint8_t *solid, const int32_t shape[3], uint32_t periodic,
+                                     int32_t axis, int32_t *labels, int32_t *count, int32_t *scratch,
+                                     void *stream) {
+  const char *who = "lbm_components_device";
+  if (!scratch) return set_error(LBM_ERR_ARG, "%s: NULL argument", who);
+  const int r = components_device_args(who, q, solid, shape, periodic, axis, labels, count);
+  if (r != LBM_OK) return r;
+  return components_device(who, q, solid, shape, periodic, axis, labels, count, scratch,
+                           static_cast<hipStream_t>(stream));
+}
+
+extern "C" int64_t lbm_components_noalloc_max_scratch(void) { return kNoAllocEntries; }
+
+extern "C" int lbm_components_device_noalloc(int32_t q, const uint8_t *solid, const int32_t shape[3],
+                                             uint32_t periodic, int32_t axis, int32_t *labels, int32_t *count,
+                                             void *stream) {
+  const char *who = "lbm_components_device_noalloc";
+  const int r = components_device_args(who, q, solid, shape, periodic, axis, labels, count);
+  if (r != LBM_OK) return r;
+  const int64_t need = lbm_components_device_scratch(shape);
+  if (need > kNoAllocEntries)
+    return set_error(LBM_ERR_ARG, "%s: %d x %d x %d needs %lld scratch entries, above the fixed %lld", who, shape[0],
+                     shape[1], shape[2], (long long)need, (long long)kNoAllocEntries);
+  int32_t *scratch = nullptr;
+  const int e = noalloc_scratch(who, &scratch);
+  if (e != LBM_OK) return e;
+  return components_device(who, q, solid, shape, periodic, axis, labels, count, scratch,
+                           static_cast<hipStream_t>(stream));
 }

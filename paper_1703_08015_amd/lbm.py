@@ -106,6 +106,8 @@ def lib():
             "lbm_components": (ctypes.c_int, [I32, P, P, U32, I32, P, P]),
             "lbm_components_device": (ctypes.c_int, [I32, P, P, U32, I32, P, P, P, P]),
             "lbm_components_device_scratch": (I64, [P]),
+            "lbm_components_device_noalloc": (ctypes.c_int, [I32, P, P, U32, I32, P, P, P]),
+            "lbm_components_noalloc_max_scratch": (I64, []),
             "lbm_project_invariants": (ctypes.c_int, [I32, P, U32, P, I32, ctypes.c_double, I32, P, P, P, P]),
             "lbm_device_copy": (ctypes.c_int, [P, P, ctypes.c_size_t, P]),
             "lbm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -189,6 +191,32 @@ def components_device(solid, lattice=19, axis=-1, periodic=(1, 1, 1), stream=Non
                                        ctypes.byref(count), ctypes.c_void_p(scratch.data_ptr()),
                                        ctypes.c_void_p(s.cuda_stream)), "lbm_components_device")
     return labels, int(count.value)
+
+
+def components_device_noalloc(solid, labels, lattice=19, axis=-1, periodic=(1, 1, 1), stream=None):
+    """lbm_components_device_noalloc: the labels of components_device written
+    into the caller's device int32 tensor `labels` (shape of solid), with the
+    library's fixed scratch instead of an allocated one; returns the count."""
+    import torch
+    m = solid if solid.dim() == 3 else solid.reshape((1,) + tuple(solid.shape))
+    if m.dtype != torch.uint8 or not m.is_contiguous() or not m.is_cuda:
+        raise ValueError("solid must be a contiguous uint8 CUDA tensor")
+    if labels.dtype != torch.int32 or not labels.is_contiguous() or labels.numel() != m.numel() or \
+            labels.device != m.device:
+        raise ValueError("labels must be a contiguous int32 tensor on the mask's device, one entry per node")
+    shape = np.array([m.shape[2], m.shape[1], m.shape[0]], np.int32)
+    count = ctypes.c_int32()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().lbm_components_device_noalloc(int(lattice), ctypes.c_void_p(m.data_ptr()), _np_ptr(shape),
+                                               _periodic_bits(periodic), int(axis),
+                                               ctypes.c_void_p(labels.data_ptr()), ctypes.byref(count),
+                                               ctypes.c_void_p(s.cuda_stream)), "lbm_components_device_noalloc")
+    return int(count.value)
+
+
+def components_noalloc_max_scratch():
+    """Entries (int32) of the fixed scratch of components_device_noalloc."""
+    return int(lib().lbm_components_noalloc_max_scratch())
 
 
 class Invariants:
