@@ -223,8 +223,11 @@ def test_reduce_and_residual_vs_oracle(torch, storage):
 
 def _sphere256_crop():
     """A 64^3 crop of the 256^3 porosity-0.3 sphere packing (seed 0, radii
-    4-12) that the step benchmark runs, with every axis closed: positions
-    outside the crop count as solid."""
+    4-12) that the step benchmark runs.  The tests run it periodic along x,
+    the force direction, and closed on y and z (positions outside the crop
+    count as solid): a crop closed on every axis settles towards a
+    hydrostatic state with no flow (mean |u| 1e-8 after 1000 steps, against
+    9e-6 with x periodic), where velocity errors measure only cancellation."""
     mask, _ = inputs.spheres_3d(256, 0.3, 4.0, 12.0, seed=0)
     return np.ascontiguousarray(mask[:64, :64, :64])
 
@@ -236,8 +239,8 @@ def test_fp64_1000_steps_sphere256_crop(torch, kernel):
     mask = _sphere256_crop()
     g = (1e-6, 0.0, 0.0)
     _log("sphere256 crop fp64", kernel, "porosity", float((~mask).mean()))
-    f, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (0, 0, 0), kernel=kernel)
-    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=0, nthreads=8)
+    f, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 0, 0), kernel=kernel)
+    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=(1, 0, 0), nthreads=8)
     fl = ~mask
     err = np.max(np.abs(f - want)[:, fl] / np.abs(want)[:, fl])
     _log("sphere256 crop fp64", kernel, "max rel PDF error", err)
@@ -251,8 +254,8 @@ def test_f32_1000_steps_sphere256_crop(torch):
     within the 2e-5 bar of the offset forms."""
     mask = _sphere256_crop()
     g = (1e-6, 0.0, 0.0)
-    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (0, 0, 0), storage="f32")
-    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=0, nthreads=8)
+    _, _, v, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 0, 0), storage="f32")
+    want = dense.step(19, mask, dense.init(19, mask), 0.7, g, 1000, periodic=(1, 0, 0), nthreads=8)
     _, uw = dense.moments(19, mask, want, g)
     fl = ~mask
     err = np.linalg.norm((v - uw)[:, fl]) / np.linalg.norm(uw[:, fl])
