@@ -26,6 +26,8 @@ def candidates(lattice=19, batched=False):
     for tpb in (1, 2, 4, 8):
         for persistent in (0, 1):
             out.append(dict(tile=(4, 4, 4), tiles_per_block=tpb, persistent=persistent, step_kernel="scalar"))
+    for tpb in (1, 4):  # coalesced own loads, in-tile sources from other lanes
+        out.append(dict(tile=(4, 4, 4), tiles_per_block=tpb, persistent=0, step_kernel="shuffle"))
     if not batched:
         for tpb in (1, 4):
             out.append(dict(tile=(4, 4, 8), tiles_per_block=tpb, persistent=0, step_kernel="generic"))
