@@ -229,31 +229,54 @@ def cpu_baseline(mask, args):
 COPY_KERNEL = "k_copy16"  # lbm_device_copy's kernel, as rocprofv3 -T names it
 
 
-def copy_reference(torch, lbm, gib, reps=10):
+class CopyReference:
     """Achievable HBM bandwidth of the library's own device copy
-    (lbm_device_copy: 16-byte non-temporal loads and stores, a fixed grid per
-    compute unit) over buffers of ``gib`` GiB each, timed with HIP events on
-    the current stream; the same kernel calibrates the rocprofv3 byte
-    counters."""
-    n = int(gib * (1 << 30)) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        lbm.device_copy(dst, src)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        lbm.device_copy(dst, src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    assert bool((dst[:: max(n // 4096, 1)] == 1.0).all()), "device copy lost data"
-    del src, dst
-    torch.cuda.empty_cache()
-    return {"kernel": "lbm_device_copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "ms": round(ms, 4),
-            "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}
+    (lbm_device_copy: one 16-byte non-temporal load and store per thread, a
+    grid covering the buffer) over buffers of ``gib`` GiB each, timed with HIP
+    events on the current stream; the same kernel calibrates the rocprofv3
+    byte counters.
+
+    ``launch`` queues copies for at least ``min_seconds`` without waiting for
+    them, so that the step's warm-up launches queue right behind them and the
+    GPU is never idle in between; ``result`` reads the events afterwards.  The
+    GPU's clock and power control needs about 100 ms of sustained memory
+    traffic to settle: a step launched after a quiet spell runs up to 9%
+    slower for its first few dozen launches (per-launch HIP-event profile:
+    309 us, then 325-337 us around launches 10-20, back to 307 us by launch
+    60; flat at 306-310 us right after 100 ms of copies)."""
+
+    def __init__(self, torch, lbm, gib):
+        self.torch, self.lbm = torch, lbm
+        self.n = int(gib * (1 << 30)) // 8
+        self.src = torch.ones(self.n, dtype=torch.float64, device="cuda")
+        self.dst = torch.empty_like(self.src)
+
+    def launch(self, min_seconds=0.2):
+        t = self.torch
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        t.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            self.lbm.device_copy(self.dst, self.src)
+        e1.record()
+        t.cuda.synchronize()
+        self.reps = max(10, int(min_seconds / (e0.elapsed_time(e1) / 3 * 1e-3)) + 1)
+        self.e0, self.e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        self.e0.record()
+        for _ in range(self.reps):
+            self.lbm.device_copy(self.dst, self.src)
+        self.e1.record()
+
+    def result(self):
+        t = self.torch
+        t.cuda.synchronize()
+        ms = self.e0.elapsed_time(self.e1) / self.reps
+        assert bool((self.dst[:: max(self.n // 4096, 1)] == 1.0).all()), "device copy lost data"
+        n = self.n
+        del self.src, self.dst
+        t.cuda.empty_cache()
+        return {"kernel": "lbm_device_copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "ms": round(ms, 4),
+                "reps": self.reps, "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}
 
 
 def _progress(tag):
@@ -511,6 +534,9 @@ def mode_warmstart(args, torch, lbm):
             "cold_steps_mean": float(np.mean([r["cold_steps"] for r in rows])),
             "warm_steps_mean": float(np.mean([r["warm_steps"] for r in rows])),
             "prediction_u_rel_l2_mean": float(np.mean([r["prediction_u_rel_l2"] for r in rows])),
+            "prediction_u_rel_l2_best_scale_mean": float(np.mean([r["prediction_u_rel_l2_best_scale"]
+                                                                  for r in rows])),
+            "prediction_best_scale_mean": float(np.mean([r["prediction_best_scale"] for r in rows])),
             "warm_vs_cold_u_rel_l2_max": float(np.max([r["warm_vs_cold_u_rel_l2"] for r in rows])),
             "fallbacks": int(sum(r["fell_back"] for r in rows)),
             "train_loss_first_last": [hist[0], hist[-1]], "data_seconds": round(t_data, 1),
@@ -606,9 +632,12 @@ def main():
                         pattern=args.pattern, collision=args.collision)
     if lid is not None:
         solver.set_lid(*lid)
-    # the copy reference runs right before the step's warm-up, on the same device state
-    copy_ref = copy_reference(torch, lbm, args.copy_gib) if args.copy_gib > 0 else None
     solver.init()
+    # the copy reference runs right before the step's warm-up, which queues
+    # behind it on the same stream with no idle gap
+    copy = CopyReference(torch, lbm, args.copy_gib) if args.copy_gib > 0 else None
+    if copy:
+        copy.launch()
     solver.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -624,6 +653,7 @@ def main():
     wall = time.perf_counter() - t0
     launch_ms = ev0.elapsed_time(ev1) / args.steps
 
+    copy_ref = copy.result() if copy else None
     # the state must still be physical after the timed steps
     tot = solver.reduce()[0]
     if not np.all(np.isfinite(tot)):

@@ -372,11 +372,12 @@ int lbm_project_invariants(int32_t q, const int32_t shape[3], uint32_t periodic,
 
 /* Measurement reference, not part of the method: copy `bytes` bytes from
  * src to dst on the device (both device pointers, 16-byte aligned, not
- * overlapping, bytes a multiple of 16) with 16-byte non-temporal loads and
- * stores and a fixed grid per compute unit striding over the buffers: the
- * rate one read and one write stream reach on this device, against which
- * the step's bandwidth is compared.  Asynchronous on the given stream;
- * LBM_ERR_ARG for bad arguments, LBM_ERR_HIP if the launch fails. */
+ * overlapping, bytes a multiple of 16) with one 16-byte non-temporal load
+ * and store per thread over a grid that covers the buffer: the rate one
+ * read and one write stream reach on this device, against which the step's
+ * bandwidth is compared.  Asynchronous on the given stream; LBM_ERR_ARG for
+ * bad arguments (or more than 2^31 - 1 workgroups of 256 threads),
+ * LBM_ERR_HIP if the launch fails. */
 int lbm_device_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 const char *lbm_strerror(int code);
