@@ -231,6 +231,8 @@ struct BrickShape {
 
 constexpr int tap_offset(int t) { return (t % 3) + kHaloX * (((t / 3) % 3) + kHaloY * (t / 9)); }
 
+constexpr int kBrickRing8 = 3;  // K steps of weights loaded ahead in the 8-channel form
+
 template <int NW, int CC, bool RELU>
 __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   using BS = BrickShape<CC>;
@@ -294,16 +296,26 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
     __syncthreads();
     if constexpr (CC == 8) {
       // four taps per K step: lane group kb takes tap 4s + kb (tap 27 is padding)
+      bf16x8 ring[kBrickRing8][NW];
+      auto load_w = [&](int s0, bf16x8(&dst)[NW]) {
+        const int t = s0 + kb;
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+          dst[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (t < 27 ? t : 26) * a.cin + c0);
+      };
+      static_for<kBrickRing8>([&](auto P) { load_w(4 * decltype(P)::value, ring[decltype(P)::value]); });
       static_for<7>([&](auto S) {
-        constexpr int s0 = 4 * decltype(S)::value;
+        constexpr int sidx = decltype(S)::value, s0 = 4 * sidx, slot = sidx % kBrickRing8;
         const int t = s0 + kb;
         const int off = kb == 0 ? tap_offset(s0) : kb == 1 ? tap_offset(s0 + 1)
                       : kb == 2 ? tap_offset(s0 + 2) : tap_offset(s0 + 3 < 27 ? s0 + 3 : 26);
         const bool tv = t < 27;
         bf16x8 bv[NW];
 #pragma unroll
-        for (int j = 0; j < NW; ++j)
-          bv[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (tv ? t : 26) * a.cin + c0);
+        for (int j = 0; j < NW; ++j) bv[j] = ring[slot][j];
+        // the weights kBrickRing8 K steps ahead are in flight during these MFMAs
+        if constexpr (sidx + kBrickRing8 < 7) load_w(4 * (sidx + kBrickRing8), ring[slot]);
+        __builtin_amdgcn_sched_barrier(0);  // keep the load here: the scheduler would sink it next to its use
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off * CP]);
@@ -317,22 +329,31 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       int cb[BS::KS];  // weight channel of this lane's k group, clamped into the tap
 #pragma unroll
       for (int st = 0; st < BS::KS; ++st) cb[st] = min(32 * st + 8 * kb, CC - 8);
-      static_for<27>([&](auto T) {
-        constexpr int t = decltype(T)::value;
+      // weight fragments of the next R (tap, K step) pairs are loaded ahead
+      // into a ring of registers, so their L2 latency overlaps R steps of MFMAs
+      constexpr int R = NW <= 2 ? 6 : 3, NSTEP = 27 * BS::KS;
+      bf16x8 ring[R][NW];
+      auto load_w = [&](int u, bf16x8(&dst)[NW]) {
+        const int t = u / BS::KS, st = u % BS::KS;
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+          dst[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (int64_t)t * a.cin + c0 + cb[st]);
+      };
+      static_for<R>([&](auto P) { load_w(decltype(P)::value, ring[decltype(P)::value]); });
+      static_for<NSTEP>([&](auto U) {
+        constexpr int u = decltype(U)::value, t = u / BS::KS, st = u % BS::KS, slot = u % R;
         constexpr int off = tap_offset(t) * CP;
-        const int64_t wt = (int64_t)t * a.cin + c0;
+        bf16x8 bv[NW];
 #pragma unroll
-        for (int st = 0; st < BS::KS; ++st) {
-          bf16x8 bv[NW];
+        for (int j = 0; j < NW; ++j) bv[j] = ring[slot][j];
+        if constexpr (u + R < NSTEP) load_w(u + R, ring[slot]);
+        __builtin_amdgcn_sched_barrier(0);  // keep the load here: the scheduler would sink it next to its use
 #pragma unroll
-          for (int j = 0; j < NW; ++j) bv[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + wt + cb[st]);
+        for (int f = 0; f < 4; ++f) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off + 32 * st + 8 * kb]);
 #pragma unroll
-          for (int f = 0; f < 4; ++f) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off + 32 * st + 8 * kb]);
-#pragma unroll
-            for (int j = 0; j < NW; ++j)
-              acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
-          }
+          for (int j = 0; j < NW; ++j)
+            acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
         }
       });
     }
@@ -475,6 +496,173 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
     if (c >= a.cin || n >= a.cout) continue;
     const float s = red[0][cl][nl] + red[1][cl][nl] + red[2][cl][nl] + red[3][cl][nl];
     atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, s);
+  }
+}
+
+// ---- weight gradient of a 3x3x3 convolution on spatial bricks ---------------
+// dW[n][t][c] += sum over output voxels v of x(v + o_t)[c] * dy(v)[n].  The
+// voxel-chunk kernel above gathers x and dy once per tap, so a large grid is
+// read 27 times; here a block owns a channel tile (16*CF input and 16*NF
+// output channels) and a run of 8x4x4-voxel bricks, and for each brick stages
+// the 10x6x6 input halo and the brick's dy in LDS once for all 27 taps.
+// The reduction (K) runs over voxels, so both are stored channel-major: a
+// lane's 8 K values are the 8 voxels of one x-row.  The halo is kept as three
+// copies shifted by tx = 0, 1, 2 along x, xs[tx][c][hz][hy][8], so every
+// tap's A fragment is one aligned 16-byte LDS read; dy is ys[n][z][y][8].
+// K step k is the brick's z-plane k and lane group g its y-row g.
+// Wavefront w accumulates the taps w, w + 4, ... (7 or 6 of them) for the
+// whole channel tile in registers; the next brick's global rows are loaded
+// while the current brick's MFMAs run, and each weight gets one FP32 atomic
+// add per block at the end.
+constexpr int kWbX = 8, kWbY = 4, kWbZ = 4;             // brick (output voxels)
+constexpr int kWhY = kWbY + 2, kWhZ = kWbZ + 2;         // halo rows along y and z
+constexpr int kWHalo = (kWbX + 2) * kWhY * kWhZ;        // 360 halo voxels
+constexpr int kWxStr = kWhY * kWhZ * 8 + 8;             // per-channel stride of a shifted copy (bf16)
+constexpr int kWyStr = kWbX * kWbY * kWbZ + 8;          // per-channel stride of ys (bf16)
+constexpr int kWTaps = 7;                               // taps per wavefront (27 = 7 + 7 + 7 + 6)
+
+template <int CF, int NF>
+struct WBrick {
+  static constexpr int GX = 2 * CF, GY = 2 * NF;                    // 8-channel groups per voxel
+  static constexpr int NSX = (kWHalo * GX + 255) / 256;             // staging loads per thread
+  static constexpr int NSY = (kWbX * kWbY * kWbZ * GY + 255) / 256;
+  static constexpr int LDS = (3 * 16 * CF * kWxStr + 16 * NF * kWyStr) * 2;  // bytes
+};
+
+template <int CF, int NF>
+__global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block, int cblocks) {
+  using WB = WBrick<CF, NF>;
+  extern __shared__ __attribute__((aligned(16))) bf16 wlds[];
+  bf16 *xs = wlds;                                 // [3][16*CF][kWxStr]
+  bf16 *ys = wlds + 3 * 16 * CF * kWxStr;          // [16*NF][kWyStr]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the tap branches below stay scalar
+  const int r = lane & 15, g = lane >> 4;
+  const Grid gr = a.rows;  // CONV3: input grid == output grid
+  const int cbase = (blockIdx.y % cblocks) * 16 * CF, nbase = (blockIdx.y / cblocks) * 16 * NF;
+  const int bxn = (gr.nx + kWbX - 1) / kWbX, byn = (gr.ny + kWbY - 1) / kWbY, bzn = (gr.nz + kWbZ - 1) / kWbZ;
+  const int nbricks = bxn * byn * bzn;
+  const int b0 = blockIdx.x * bricks_per_block;
+  const int b1 = min(b0 + bricks_per_block, nbricks);
+  const bf16 *__restrict__ dy = static_cast<const bf16 *>(a.y);
+
+  f32x4 acc[kWTaps][CF][NF];
+#pragma unroll
+  for (int m = 0; m < kWTaps; ++m)
+#pragma unroll
+    for (int i = 0; i < CF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) acc[m][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  bf16x8 vx[WB::NSX], vy[WB::NSY];
+  // global rows of brick b into registers (zeros past the channel counts and
+  // for output voxels outside the grid)
+  auto load = [&](int b) {
+    const int ox = (b % bxn) * kWbX, oy = ((b / bxn) % byn) * kWbY, oz = (b / (bxn * byn)) * kWbZ;
+#pragma unroll
+    for (int it = 0; it < WB::NSX; ++it) {
+      const int e = tid + 256 * it;
+      vx[it] = bf16x8{};
+      if (e < kWHalo * WB::GX) {
+        const int hv = e / WB::GX, q = e % WB::GX;
+        const int hx = hv % (kWbX + 2), hy = (hv / (kWbX + 2)) % kWhY, hz = hv / ((kWbX + 2) * kWhY);
+        int gx = (ox + hx - 1) % gr.nx, gy = (oy + hy - 1) % gr.ny, gz = (oz + hz - 1) % gr.nz;
+        gx += gx < 0 ? gr.nx : 0;
+        gy += gy < 0 ? gr.ny : 0;
+        gz += gz < 0 ? gr.nz : 0;
+        const int c = cbase + 8 * q;
+        if (c < a.cin) vx[it] = *reinterpret_cast<const bf16x8 *>(a.x + vidx(gx, gy, gz, gr) * a.ldx + c);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < WB::NSY; ++it) {
+      const int e = tid + 256 * it;
+      vy[it] = bf16x8{};
+      if (e < kWbX * kWbY * kWbZ * WB::GY) {
+        const int v = e / WB::GY, q = e % WB::GY;
+        const int x = ox + v % kWbX, y = oy + (v / kWbX) % kWbY, z = oz + v / (kWbX * kWbY);
+        const int n = nbase + 8 * q;
+        if (x < gr.nx && y < gr.ny && z < gr.nz && n < a.cout)
+          vy[it] = *reinterpret_cast<const bf16x8 *>(dy + vidx(x, y, z, gr) * a.ldy + n);
+      }
+    }
+  };
+  // registers -> LDS, channel-major (every entry of xs and ys is written)
+  auto stage = [&]() {
+#pragma unroll
+    for (int it = 0; it < WB::NSX; ++it) {
+      const int e = tid + 256 * it;
+      if (e < kWHalo * WB::GX) {
+        const int hv = e / WB::GX, q = e % WB::GX;
+        const int hx = hv % (kWbX + 2), row = hv / (kWbX + 2);  // row = hz * kWhY + hy
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx) {
+          const int j = hx - tx;
+          if (j < 0 || j >= 8) continue;
+          bf16 *dst = xs + (tx * 16 * CF + 8 * q) * kWxStr + row * 8 + j;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dst[k * kWxStr] = vx[it][k];
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < WB::NSY; ++it) {
+      const int e = tid + 256 * it;
+      if (e < kWbX * kWbY * kWbZ * WB::GY) {
+        const int v = e / WB::GY, q = e % WB::GY;
+        bf16 *dst = ys + (8 * q) * kWyStr + v;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[k * kWyStr] = vy[it][k];
+      }
+    }
+  };
+
+  if (b0 < b1) load(b0);
+  for (int b = b0; b < b1; ++b) {
+    __syncthreads();  // the previous brick's LDS reads are done
+    stage();
+    __syncthreads();
+    if (b + 1 < b1) load(b + 1);  // in flight during the MFMAs
+#pragma unroll
+    for (int k = 0; k < kWbZ; ++k) {
+      bf16x8 bv[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        bv[j] = *reinterpret_cast<const bf16x8 *>(ys + (16 * j + r) * kWyStr + (k * kWbY + g) * 8);
+      auto tap = [&](int m) {
+        const int t = wv + 4 * m;
+        const int tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
+#pragma unroll
+        for (int i = 0; i < CF; ++i) {
+          const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+              xs + (tx * 16 * CF + 16 * i + r) * kWxStr + ((k + tz) * kWhY + (g + ty)) * 8);
+#pragma unroll
+          for (int j = 0; j < NF; ++j)
+            acc[m][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[m][i][j], 0, 0, 0);
+        }
+      };
+      // taps wv + 4m < 27 for m < 6 on every wavefront; the seventh only on
+      // wavefronts 0-2 (one uniform branch)
+#pragma unroll
+      for (int m = 0; m < kWTaps - 1; ++m) tap(m);
+      if (wv < 3) tap(kWTaps - 1);
+    }
+  }
+  // lane holds C[c = 16i + 4g + q][n = 16j + r] of tap t
+  const int ktot = 27 * a.cin;
+#pragma unroll
+  for (int m = 0; m < kWTaps; ++m) {
+    const int t = wv + 4 * m;
+    if (t >= 27) continue;
+#pragma unroll
+    for (int i = 0; i < CF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = cbase + 16 * i + 4 * g + q, n = nbase + 16 * j + r;
+          if (c < a.cin && n < a.cout) atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, acc[m][i][j][q]);
+        }
   }
 }
 
@@ -881,6 +1069,57 @@ hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int CF, int NF>
+hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, hipStream_t s) {
+  using WB = WBrick<CF, NF>;
+  const int cblocks = (a.cin + 16 * CF - 1) / (16 * CF), nblocks = (a.cout + 16 * NF - 1) / (16 * NF);
+  const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
+                          ((a.rows.nz + kWbZ - 1) / kWbZ);
+  // about two blocks per compute unit in all: each block sums its bricks in
+  // registers, so fewer, longer blocks mean fewer atomic adds at the end
+  const int64_t tiles = (int64_t)cblocks * nblocks;
+  int64_t per = (nbricks * tiles + 511) / 512;
+  if (per < 1) per = 1;
+  const int64_t gx = (nbricks + per - 1) / per;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad_brick<CF, NF>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, WB::LDS);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)gx, (unsigned)tiles), dim3(256), WB::LDS, s, a, dw,
+                     (int)per, cblocks);
+  return hipGetLastError();
+}
+
+// channel tile width (in 16-channel fragments, 1..3) that pads c channels least
+int wgrad_frags(int c, int max_frags) {
+  int best = 1, waste = 1 << 30;
+  for (int f = 1; f <= max_frags; ++f) {
+    const int w = (c + 16 * f - 1) / (16 * f) * 16 * f - c;
+    if (w <= waste) best = f, waste = w;
+  }
+  return best;
+}
+
+// The brick weight gradient for 3x3x3 convolutions on grids of at least
+// 2048 bricks (64^3 and up); returns false to use k_wgrad instead.
+bool try_wgrad_brick(const GemmArgs &a, float *dw, hipStream_t s, hipError_t *err) {
+  const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
+                          ((a.rows.nz + kWbZ - 1) / kWbZ);
+  if (nbricks < 2048) return false;
+  const int cf = wgrad_frags(a.cin, 3);
+  const int nf = wgrad_frags(a.cout, cf == 3 ? 2 : 3);
+  switch (cf * 4 + nf) {
+    case 5: *err = launch_wgrad_brick_cf<1, 1>(a, dw, s); break;
+    case 6: *err = launch_wgrad_brick_cf<1, 2>(a, dw, s); break;
+    case 7: *err = launch_wgrad_brick_cf<1, 3>(a, dw, s); break;
+    case 9: *err = launch_wgrad_brick_cf<2, 1>(a, dw, s); break;
+    case 10: *err = launch_wgrad_brick_cf<2, 2>(a, dw, s); break;
+    case 11: *err = launch_wgrad_brick_cf<2, 3>(a, dw, s); break;
+    case 13: *err = launch_wgrad_brick_cf<3, 1>(a, dw, s); break;
+    default: *err = launch_wgrad_brick_cf<3, 2>(a, dw, s); break;
+  }
+  return true;
+}
+
 template <int SRC, int DST>
 hipError_t launch_wgrad(const GemmArgs &a, float *dw, hipStream_t s) {
   const int cf = a.cin <= 16 ? 1 : 2, nf = a.cout <= 16 ? 1 : 2;
@@ -925,7 +1164,9 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
   if (g->dst_mode == LBM_NN_SCATTER2) {
     NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
-    NN_TRY((launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s)));
+    hipError_t e = hipSuccess;
+    if (!try_wgrad_brick(a, dw, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s);
+    NN_TRY(e);
   } else if (g->src_mode == LBM_NN_GATHER2) {
     NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, s)));
   } else {

@@ -114,6 +114,27 @@ def test_conv3_wgrad_large_grid_split(torch):
     close(host(dw), gw, 2e-5)
 
 
+@pytest.mark.parametrize("grid,cin,cout", [
+    ((66, 62, 70), 24, 24),   # partial 8x4x4 bricks on every axis, 24-channel level
+    ((64, 64, 64), 8, 24),    # the first layer: 8 input channels
+    ((64, 64, 64), 48, 24),   # decoder: concatenated skip and upsampled halves
+    ((64, 64, 64), 24, 48),   # second level, three 16-column fragments
+    ((64, 64, 64), 48, 48),   # three output-channel tiles
+])
+def test_conv3_wgrad_brick_kernel(torch, grid, cin, cout):
+    """Grids of at least 2048 8x4x4 bricks take the weight gradient that
+    stages each brick's input halo and output gradient in LDS once for all 27
+    taps; against the oracle's dW (FP32 sums over 2.6-2.9e5 voxels)."""
+    x = bf(rng.normal(size=grid + (cin,)))
+    dy = bf(rng.normal(size=grid + (cout,)))
+    dw = torch.zeros((cout, 27, cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw, db)
+    _, gw, gb = onn.conv3_backward(x, np.zeros((cout, 27, cin)), dy)
+    close(host(dw), gw, 2e-5)
+    close(host(db), gb, 2e-5)
+
+
 @pytest.mark.parametrize("cin,cout", [(48, 24), (16, 8)])
 def test_up2_forward_backward(torch, cin, cout):
     coarse = (2, 3, 2)
