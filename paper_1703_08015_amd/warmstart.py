@@ -254,11 +254,18 @@ def evaluate(torch, net, samples, tau, storage="f32", tol=1e-6, check_every=100,
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         fl = sm.solid == 0
-        pred_err = float(((init[1][:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
+        up, uc = init[1][:, fl], u_cold[:, fl]
+        norm = float((uc ** 2).sum().sqrt())
+        pred_err = float(((up - uc) ** 2).sum().sqrt()) / norm
+        # the same error after the best single scale factor on the prediction:
+        # how much of it is the overall magnitude rather than the shape
+        alpha = float((up * uc).sum() / (up * up).sum().clamp_min(1e-300))
+        pred_err_scaled = float(((alpha * up - uc) ** 2).sum().sqrt()) / norm
         warm_steps, warm_s, u_warm, fb = solve(torch, sm, tau, init, storage, tol, check_every)
         agree = float(((u_warm[:, fl] - u_cold[:, fl]) ** 2).sum().sqrt() / (u_cold[:, fl] ** 2).sum().sqrt())
         row = dict(cold_steps=cold_steps, cold_s=cold_s, warm_steps=warm_steps, warm_s=warm_s + t_inf,
                    inference_s=t_inf, labels_s=t_lab, solve_s=warm_s, prediction_u_rel_l2=pred_err,
+                   prediction_best_scale=alpha, prediction_u_rel_l2_best_scale=pred_err_scaled,
                    warm_vs_cold_u_rel_l2=agree, fell_back=fb)
         if extra:
             u64 = extra.pop("u64")

@@ -87,3 +87,37 @@ def test_warm_start_matches_the_fp64_oracle_steady_state(torch, trained):
         err = np.linalg.norm(u[:, fl] - u_ref[:, fl]) / np.linalg.norm(u_ref[:, fl])
         print("warm FP32 vs FP64 oracle", err, flush=True)
         assert err <= 1e-3
+
+
+def test_gain_on_held_out_samples(torch, trained):
+    """What the trained network gains on geometries it never saw, and the
+    ceiling of any (rho, u) start.  On held-out 16^3 samples the network's
+    projected prediction reaches the cold start's steady state in no more
+    steps than a start from rest, to within one residual check (20 steps) on
+    average.  On a held-out 128^3 sample of the evaluation workload (spheres
+    r 4-12) the exact steady fields, put through f_eq and projected, reach it
+    in fewer steps than a start from rest (on the 16^3 packings they do not)."""
+    net, _, _ = trained
+    rng = np.random.default_rng(7)
+    cold, warm, errs = [], [], []
+    for k in range(4):
+        m, _ = inputs.spheres_3d(16, float(rng.uniform(0.4, 0.7)), 2.0, 4.0, seed=900 + k)
+        d = rng.normal(size=3)
+        sm = warmstart.Sample(torch, m, (1e-6 * d / np.linalg.norm(d)).tolist())
+        r = warmstart.evaluate(torch, net, [sm], 0.8, check_every=20)[0]
+        print("held-out 16^3 sample %d: cold %d, warm %d steps; prediction error %.3f, agreement %.1e"
+              % (k, r["cold_steps"], r["warm_steps"], r["prediction_u_rel_l2"], r["warm_vs_cold_u_rel_l2"]),
+              flush=True)
+        assert r["warm_steps"] > 0 and not r["fell_back"] and r["warm_vs_cold_u_rel_l2"] <= 1e-4
+        cold.append(r["cold_steps"])
+        warm.append(r["warm_steps"])
+        errs.append(r["prediction_u_rel_l2"])
+    print("16^3 mean steps: cold %.0f, warm %.0f; mean prediction error %.3f"
+          % (np.mean(cold), np.mean(warm), np.mean(errs)), flush=True)
+    assert np.mean(warm) <= np.mean(cold) + 20
+    m, _ = inputs.spheres_3d(128, 0.5, 4.0, 12.0, seed=950)
+    sm = warmstart.Sample(torch, m, (1e-6, 0.0, 0.0))
+    base, pts = warmstart.error_curve(torch, net, sm, 0.8, scales=(0.0, 1.0), check_every=20)
+    print("held-out 128^3: cold %d, exact fields %d, network %d steps (prediction error %.3f)"
+          % (base["cold_steps"], pts[0]["steps"], pts[1]["steps"], pts[1]["start_u_rel_l2"]), flush=True)
+    assert 0 < pts[0]["steps"] < base["cold_steps"]
