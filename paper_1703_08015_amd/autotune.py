@@ -9,6 +9,7 @@ geometry is tuned once.
 import hashlib
 import json
 import os
+import time
 
 import numpy as np
 
@@ -19,7 +20,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_autotune.js
 
 def candidates(lattice=19, batched=False):
     """Configurations tried for a lattice.  A batch that drops converged
-    samples needs the scalar-mask kernel (4x4x4 tiles)."""
+    samples needs the scalar-mask kernel (4x4x4 or 4x4x8 tiles)."""
     if lattice == 9:
         return [dict(tile=(16, 16, 1), tiles_per_block=4, persistent=0, step_kernel="generic")]
     out = []
@@ -28,6 +29,10 @@ def candidates(lattice=19, batched=False):
             out.append(dict(tile=(4, 4, 4), tiles_per_block=tpb, persistent=persistent, step_kernel="scalar"))
     for tpb in (1, 4):  # coalesced own loads, in-tile sources from other lanes
         out.append(dict(tile=(4, 4, 4), tiles_per_block=tpb, persistent=0, step_kernel="shuffle"))
+    # 4x4x8 tiles on the scalar-mask kernel (each tile two 4x4x4 wavefronts)
+    for tpb in (2, 4, 8):
+        for persistent in (0, 1):
+            out.append(dict(tile=(4, 4, 8), tiles_per_block=tpb, persistent=persistent, step_kernel="scalar"))
     if not batched:
         for tpb in (1, 4):
             out.append(dict(tile=(4, 4, 8), tiles_per_block=tpb, persistent=0, step_kernel="generic"))
@@ -50,7 +55,15 @@ def _time_candidate(torch, masks, periodic, cand, lattice, storage, tau, g, step
     s = lbm.Solver(tiles, lattice=lattice, storage=storage, tau=tau, g=g, tiles_per_block=cand["tiles_per_block"],
                    persistent=cand["persistent"], step_kernel=cand["step_kernel"])
     s.init()
+    # at least `warmup` steps and 0.1 s of them: the host tiling before each
+    # candidate leaves the GPU idle, and the clock and power control needs
+    # about that long of sustained load to settle
+    t0 = time.perf_counter()
     s.step(warmup)
+    torch.cuda.synchronize()
+    while time.perf_counter() - t0 < 0.1:
+        s.step(max(warmup, 10))
+        torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

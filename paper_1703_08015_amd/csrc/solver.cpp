@@ -188,33 +188,54 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
       nb += n;
     }
     P.entries = off;
-    if (q == 19 && W == 1) {
-      P.nrec_h.resize((size_t)nft + 1);
+    // Records of the scalar-mask D3Q19 kernel, one per wavefront: a 4x4x4
+    // tile, or one 4x4x4 half (z < 4, z >= 4) of a 4x4x8 tile.  A half's
+    // record holds its own fluid mask and its first entry (the tile's offset,
+    // plus the lower half's fluid nodes for the upper half), and the tile's
+    // node count as the stride between direction blocks, so the kernel's
+    // arithmetic is the same for both shapes.
+    const bool halves = W == 2 && v.ax == 4 && v.ay == 4 && v.az == 8;
+    const int64_t nw = nft * W;  // wavefronts
+    if (q == 19 && (W == 1 || halves)) {
+      P.nrec_h.resize((size_t)nw + 1);
       // neighbour rows hold byte offsets into the record array (the sentinel
       // record for a missing neighbour), so the kernel adds them to the base
       // pointer without a 64-bit multiply
-      if ((uint64_t)(nft + 1) * sizeof(lbm::NbRec) > UINT32_MAX)
+      if ((uint64_t)(nw + 1) * sizeof(lbm::NbRec) > UINT32_MAX)
         return set_error(LBM_ERR_UNSUPPORTED, "too many tiles (%lld) for 32-bit record offsets", (long long)nft);
-      const uint32_t sentinel = (uint32_t)((uint64_t)nft * sizeof(lbm::NbRec));
-      P.nrow_h.assign((size_t)(nft * 20), sentinel);
+      const uint32_t sentinel = (uint32_t)((uint64_t)nw * sizeof(lbm::NbRec));
+      P.nrow_h.assign((size_t)(nw * 20), sentinel);
       for (int64_t k = 0; k < nft; ++k) {
         const lbm::TileRec &r = P.rec_h[(size_t)k];
-        P.nrec_h[(size_t)k] = lbm::NbRec{(uint32_t)r.off, (uint32_t)r.n, P.fluid_h[(size_t)k], r.sample, 0};
-        for (int j = 0; j < 18; ++j) {
-          const int32_t o = P.nbr_h[(size_t)(k * 27 + kGatherSlots[j])];
-          P.nrow_h[(size_t)(k * 20 + j)] = o < 0 ? sentinel : (uint32_t)((uint64_t)o * sizeof(lbm::NbRec));
+        int lower = 0;  // fluid nodes of the halves below this one
+        for (int h = 0; h < W; ++h) {
+          const int64_t wv = k * W + h;
+          const uint64_t m = P.fluid_h[(size_t)(k * W + h)];
+          P.nrec_h[(size_t)wv] = lbm::NbRec{(uint32_t)(r.off + lower), (uint32_t)r.n, m, r.sample, 0};
+          lower += __builtin_popcountll(m);
+          for (int j = 0; j < 18; ++j) {
+            // slot (dx, dy, dz) of the 3x3x3 neighbourhood in units of 4x4x4 wavefront tiles
+            const int sl = kGatherSlots[j], dx = sl % 3 - 1, dy = (sl / 3) % 3 - 1, dz = sl / 9 - 1;
+            const int hz = h + dz;                            // neighbour half along z
+            const int tdz = hz < 0 ? -1 : (hz >= W ? 1 : 0);  // tile step along z
+            const int nh = hz - tdz * W;
+            const int32_t o = P.nbr_h[(size_t)(k * 27 + (dx + 1) + 3 * (dy + 1) + 9 * (tdz + 1))];
+            P.nrow_h[(size_t)(wv * 20 + j)] =
+                o < 0 ? sentinel : (uint32_t)((uint64_t)((int64_t)o * W + nh) * sizeof(lbm::NbRec));
+          }
         }
       }
-      P.nrec_h[(size_t)nft] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
+      P.nrec_h[(size_t)nw] = lbm::NbRec{0u, 0u, 0ull, 0, 0};
       // region bases: off + b*n of the region's source tile (b the slot the
       // gather reads: i, or opp(i) for the single copy), plus the fluid nodes
       // that the shift to the destination lanes moves out below lane 0 (the
       // kernel adds v_mbcnt of the shifted mask); 0 for a missing source.
-      // Only the FP16 form reads them: it is bound by scalar issue, while for
-      // FP32 and FP64 the 256 extra bytes per tile cost more than the scalar
-      // work they save.
-      if (p->storage == LBM_F16_OFFSET) P.rbase_h.assign((size_t)(nft * lbm::kRegionBases), 0u);
-      for (int64_t k = 0; k < nft && !P.rbase_h.empty(); ++k) {
+      // Only the FP16 form reads them.  For FP32 the table (read with the
+      // loads kept where their addresses are ready, or without) measured
+      // 17-30% slower than computing the bases, and as 16-bit entries
+      // relative to the source tile 37% slower; FP64 is bound by bytes.
+      if (p->storage == LBM_F16_OFFSET) P.rbase_h.assign((size_t)(nw * lbm::kRegionBases), 0u);
+      for (int64_t k = 0; k < nw && !P.rbase_h.empty(); ++k) {
         uint32_t *rb = &P.rbase_h[(size_t)(k * lbm::kRegionBases)];
         for (int i = 1; i < 19; ++i) {
           const int cx = lbm::D3Q19::C[i][0], cy = lbm::D3Q19::C[i][1], cz = lbm::D3Q19::C[i][2];
@@ -279,7 +300,7 @@ int make_plan(const lbm_tiles *t, const lbm_params *p, const lbm::Variant &v, Pl
   P.nrec = take(P.nrec_h.size() * sizeof(lbm::NbRec));
   P.nrow = take(P.nrow_h.size() * sizeof(uint32_t));
   P.rbase = take(P.rbase_h.size() * sizeof(uint32_t));
-  P.list = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
+  P.list = take((size_t)(nft > 0 ? nft * W : 1) * sizeof(int32_t));
   P.lid = take((size_t)(nft > 0 ? nft : 1) * sizeof(int32_t));
   P.count = take(sizeof(int32_t));
   P.part = take((size_t)(waves > 0 ? waves : 1) * 4 * sizeof(double));
@@ -413,9 +434,10 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   s->count_d = reinterpret_cast<int32_t *>(base + P.count);
   s->storage_bytes = lbm::storage_bytes(v.storage);
   try {
-    s->list_h.resize((size_t)t->n_ftiles);
-    for (int64_t k = 0; k < t->n_ftiles; ++k) s->list_h[(size_t)k] = (int32_t)k;
-    s->count_h = (int32_t)t->n_ftiles;
+    // the active list counts wavefronts: tiles, or the 4x4x4 halves of 4x4x8 tiles
+    s->list_h.resize((size_t)(t->n_ftiles * t->words));
+    for (int64_t k = 0; k < t->n_ftiles * t->words; ++k) s->list_h[(size_t)k] = (int32_t)k;
+    s->count_h = (int32_t)(t->n_ftiles * t->words);
     s->active_h.assign(t->samples.size(), 1);
     for (const lbm::Sample &S : t->samples) s->periodic.push_back(S.periodic);
     for (const lbm::Sample &S : t->samples) {
@@ -437,14 +459,17 @@ extern "C" int lbm_create(const lbm_tiles *t, const lbm_params *p, void *ws, siz
   if ((p->step_kernel == LBM_KERNEL_SCALAR_MASK || p->step_kernel == LBM_KERNEL_SHUFFLE) &&
       !(lbm::step19_supported(v) && fits32)) {
     delete s;
-    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the scalar-mask and shuffle kernels need D3Q19, 4x4x4 "
-                                          "tiles and fewer than 2^32 PDF entries per copy");
+    return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the scalar-mask and shuffle kernels need D3Q19, 4x4x4 or "
+                                          "4x4x8 tiles and fewer than 2^32 PDF entries per copy");
   }
   if (p->step_kernel == LBM_KERNEL_SHUFFLE && p->pattern != LBM_PATTERN_TWO_COPY) {
     delete s;
     return set_error(LBM_ERR_UNSUPPORTED, "lbm_create: the shuffle kernel is a two-copy step");
   }
-  s->scalar_mask = p->step_kernel != LBM_KERNEL_GENERIC && lbm::step19_supported(v) && fits32;
+  // automatic choice: the scalar-mask kernel for 4x4x4 tiles; for 4x4x8 tiles
+  // only when asked for
+  s->scalar_mask = (p->step_kernel == LBM_KERNEL_AUTO ? v.az == 4 : p->step_kernel != LBM_KERNEL_GENERIC) &&
+                   lbm::step19_supported(v) && fits32;
   s->shuffle = p->step_kernel == LBM_KERNEL_SHUFFLE;
   if (p->persistent && !s->scalar_mask) {
     delete s;
@@ -554,7 +579,8 @@ extern "C" int lbm_set_active(lbm_solver *s, const uint8_t *active) {
     all &= active[k] != 0;
     if (!active[k]) continue;
     const lbm::SampleRec &S = s->samples_h[(size_t)k];
-    for (int64_t t = S.tile0; t < S.tile0 + S.n_ftiles; ++t) s->list_h[(size_t)n++] = (int32_t)t;
+    for (int64_t w = S.tile0 * s->words; w < (S.tile0 + S.n_ftiles) * s->words; ++w)
+      s->list_h[(size_t)n++] = (int32_t)w;
   }
   s->count_h = n;
   HIP_TRY(hipMemcpyAsync(s->list_d, s->list_h.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));

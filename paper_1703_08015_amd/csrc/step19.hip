@@ -445,7 +445,9 @@ hipError_t with_variant(const Variant &v, int phase, bool shuffle, F &&f) {
 
 }  // namespace
 
-bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && v.az == 4; }
+// 4x4x4 tiles, or 4x4x8 tiles run as two 4x4x4 halves (one wavefront each)
+// whose records the planner builds
+bool step19_supported(const Variant &v) { return v.q == 19 && v.ax == 4 && v.ay == 4 && (v.az == 4 || v.az == 8); }
 
 hipError_t launch_step19(const Variant &v, int phase, bool shuffle, const void *src, void *dst, const TileArgs &a,
                          const NbRec *nrec, const uint32_t *nrow, const uint32_t *rbase, const CollideCoef *coef,

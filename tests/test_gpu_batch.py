@@ -129,3 +129,26 @@ def test_autotuner_picks_a_timed_candidate_and_caches(torch, tmp_path):
     specs, masks = _samples()
     bb = autotune.autotune(masks, tau=0.8, steps=3, warmup=1, cache_path=cache)
     assert bb["tile"] == (4, 4, 4) and bb["step_kernel"] == "scalar"
+
+
+@pytest.mark.parametrize("persistent,graph_steps", [(0, 0), (1, 5)])
+def test_tall_tile_batch_on_scalar_kernel(torch, persistent, graph_steps):
+    """4x4x8 tiles on the scalar-mask kernel (two wavefronts per tile): a batch
+    with per-sample forces, direct or persistent launches with graph replay,
+    and a sample frozen half way, gives the bits of each sample run alone on
+    4x4x4 tiles."""
+    specs = [dict(edge=16, porosity=0.5, g=(1e-5, 2e-6, 0.0), seed=1),
+             dict(edge=24, porosity=0.35, g=(0.0, -3e-6, 4e-6), seed=2),
+             dict(edge=8, porosity=0.7, g=(-2e-6, 0.0, 1e-6), seed=3)]
+    masks = [inputs.spheres_3d(sp["edge"], sp["porosity"], rmin=2, rmax=5, seed=sp["seed"])[0] for sp in specs]
+    tb = lbm.Tiles.concat([lbm.Tiles(m, (4, 4, 8)) for m in masks])
+    s = lbm.Solver(tb, lattice=19, tau=0.8, step_kernel="scalar", persistent=persistent, graph_steps=graph_steps)
+    s.set_sample_force(np.array([sp["g"] for sp in specs]))
+    s.init()
+    s.step(12)
+    s.set_active([1, 0, 1])
+    s.step(8)
+    parts = _split(s.pdfs_export().cpu().numpy(), masks)
+    for k, (sp, m, got) in enumerate(zip(specs, masks, parts)):
+        want = _single(torch, m, sp["g"], 12 if k == 1 else 20)
+        assert np.array_equal(got, want), k

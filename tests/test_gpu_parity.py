@@ -86,11 +86,50 @@ def test_permutation_mode_bitexact_launch_shapes(torch, tpb, kernel):
     assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 3, periodic=7))
 
 
-def test_permutation_mode_bitexact_tall_tiles(torch):
-    mask = inputs.spheres_3d((16, 12, 24), 0.45, rmin=2, rmax=5, seed=6)[0]
-    f0 = inputs.random_pdfs(19, mask, seed=23)
-    f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 5, (1, 1, 1), f0=f0, tile=(4, 4, 8))
-    assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 5, periodic=7))
+def _tall_geoms():
+    yield "periodic", inputs.spheres_3d((16, 12, 24), 0.45, rmin=2, rmax=5, seed=6)[0], (1, 1, 1)
+    # z = 13 pads the last tile row to z = 16 with solid; walls on y and z
+    yield "ragged", inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=2, periodic=(1, 0, 0))[0], (1, 0, 0)
+
+
+@pytest.mark.parametrize("kernel", ["generic", "scalar"])
+@pytest.mark.parametrize("tpb", [1, 4])
+def test_permutation_mode_bitexact_tall_tiles(torch, kernel, tpb):
+    """4x4x8 tiles: the generic kernel, and the scalar-mask kernel running each
+    tile as two 4x4x4 halves (one wavefront each)."""
+    for name, mask, per in _tall_geoms():
+        _log("tall tiles permutation", kernel, tpb, name, mask.shape)
+        f0 = inputs.random_pdfs(19, mask, seed=23)
+        f, _, _, _ = _gpu_run(torch, mask, 19, math.inf, (0, 0, 0), 5, per, f0=f0, tile=(4, 4, 8), kernel=kernel,
+                              tpb=tpb)
+        assert np.array_equal(f, dense.step(19, mask, f0, math.inf, [0, 0, 0], 5, periodic=per)), name
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_tall_tiles_scalar_equals_4x4x4(torch, storage):
+    """The scalar-mask kernel does the same arithmetic per node whatever the
+    tile shape, so 4x4x8 tiles give the 4x4x4 tiles' bits after 30 steps
+    from a random state with a force (all storage forms).  (The generic
+    kernel groups the collision's operations differently: it agrees with both
+    to rounding, as the oracle tests show.)"""
+    for name, mask, per in _tall_geoms():
+        rho, u = inputs.random_macro(mask, seed=24)
+        kw = dict(rho=rho, u=u, storage=storage, f16_scale_log2=16, kernel="scalar")
+        a, _, _, _ = _gpu_run(torch, mask, 19, 0.7, (2e-5, -1e-5, 3e-6), 30, per, tile=(4, 4, 4), **kw)
+        b, _, _, _ = _gpu_run(torch, mask, 19, 0.7, (2e-5, -1e-5, 3e-6), 30, per, tile=(4, 4, 8), **kw)
+        assert np.array_equal(a, b), (name, storage)
+
+
+def test_fp64_1000_steps_tall_tiles_scalar(torch):
+    """FP64 PDFs within 1e-12 of the oracle after 1000 steps, 4x4x8 tiles on
+    the scalar-mask kernel, random state and force."""
+    mask = inputs.spheres_3d((20, 22, 13), 0.5, rmin=2, rmax=5, seed=9, periodic=(1, 0, 0))[0]
+    g = (2e-5, -1e-5, 3e-6)
+    rho, u = inputs.random_macro(mask, seed=10)
+    f, _, _, _ = _gpu_run(torch, mask, 19, 0.7, g, 1000, (1, 0, 0), rho=rho, u=u, kernel="scalar", tile=(4, 4, 8))
+    want = dense.step(19, mask, dense.init(19, mask, rho=rho, u=u), 0.7, g, 1000, periodic=(1, 0, 0), nthreads=8)
+    fl = ~mask
+    assert np.max(np.abs(f - want)[:, fl] / np.abs(want)[:, fl]) <= 1e-12
 
 
 def _rel(a, b):

@@ -167,7 +167,9 @@ def test_autotune_candidates_and_key():
     from paper_1703_08015_amd import autotune
     c19 = autotune.candidates(19)
     assert any(c["tile"] == (4, 4, 8) for c in c19) and any(c["persistent"] for c in c19)
-    assert all(c["tile"] == (4, 4, 4) for c in autotune.candidates(19, batched=True))
+    # a batch that drops converged samples needs the scalar-mask step (either form, either tile shape)
+    cb = autotune.candidates(19, batched=True)
+    assert all(c["step_kernel"] in ("scalar", "shuffle") for c in cb) and any(c["tile"] == (4, 4, 8) for c in cb)
     m = np.zeros((8, 8, 8), bool)
     k1 = autotune.geometry_key([m], (1, 1, 1), 19, "f64", 0.7)
     m2 = m.copy()
