@@ -66,7 +66,8 @@ def workload(args):
 
 def traffic_for(kernel_name, workload_key):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernel source; else None.  Returns (bytes, note):
+    the figure is recorded, not measured in this run."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -81,7 +82,9 @@ def traffic_for(kernel_name, workload_key):
             src += fh.read()
     if not src or rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return rec.get("bytes_per_launch")
+    note = "recorded %s in profiles/traffic.json from rocprofv3 FETCH_SIZE and WRITE_SIZE runs of the same kernel " \
+           "source (L2 misses, including those the MALL serves: an upper bound on HBM bytes)" % rec.get("date", "")
+    return rec.get("bytes_per_launch"), note
 
 
 def step_kernel_key(args):
@@ -158,6 +161,8 @@ def record_traffic(args, argv):
         "write_kib_per_dispatch_raw": round(sum(wk) / len(wk), 1),
         "dispatches": [len(fk), len(wk)],
         "source_sha256": hashlib.sha256(src).hexdigest(), "source_files": files,
+        "date": time.strftime("%Y-%m-%d", time.gmtime(os.path.getmtime(os.path.join(fetch_dir,
+                                                                                 "run_counter_collection.csv")))),
         "commands": ["rocprofv3 --pmc %s -T -d %s -o run --output-format csv -- %s" % (c, d, cmd)
                      for c, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir))]}
     with open(path, "w") as fh:
@@ -288,6 +293,26 @@ def _progress(tag):
 
 def _rel_l2(a, b):
     return float(((a - b) ** 2).sum().sqrt() / (b ** 2).sum().sqrt())
+
+
+def mode_autotune(args, torch, lbm):
+    """The autotuner on the step workload (--geometry, --storage): every
+    candidate tile shape, step kernel, workgroup size and launch mode timed
+    with HIP events (--steps after --warmup), fresh (no cache)."""
+    from paper_1703_08015_amd import autotune
+    mask, phi, desc = workload(args)
+    g, per, lid, q, tile = step_setup(args)
+    if lid is not None or q != 19:
+        raise SystemExit("--mode autotune runs the D3Q19 step workloads without a lid")
+    best = autotune.autotune(mask, periodic=per, lattice=19, storage=args.storage, tau=args.tau, g=tuple(g),
+                             steps=args.steps, warmup=args.warmup, cache_path=None, refresh=True)
+    trials = sorted(best.pop("trials"), key=lambda t: t.get("ms_per_step", 1e9))
+    for t in trials:
+        t["tile"] = "x".join(str(a) for a in t["tile"])
+    return {"metric": "autotuner trials, ms per step", "unit": "MLUPS", "higher_is_better": True,
+            "value": round(best["mlups"], 1), "dtype": args.storage, "data": "synthetic",
+            "config": {"workload": desc}, "best": {k: v for k, v in best.items() if k != "cached"},
+            "trials": trials}
 
 
 def mode_steady(args, torch, lbm):
@@ -570,7 +595,8 @@ def main():
                          "(modes step, steady and vessel)")
     ap.add_argument("--pattern", default="two-copy", choices=["two-copy", "single-copy"],
                     help="PDF buffers: the paper's two copies, or one copy updated in place (step mode)")
-    ap.add_argument("--mode", default="step", choices=["step", "steady", "vessel", "batch", "warmstart", "unet"])
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "steady", "vessel", "batch", "warmstart", "unet", "autotune"])
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--test-samples", type=int, default=16)
@@ -617,7 +643,7 @@ def main():
         if args.mode in ("batch", "warmstart"):
             args.tau = 0.8 if args.tau == 0.7 else args.tau
             args.storage = "f32" if args.storage == "f64" else args.storage
-        res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch,
+        res = {"steady": mode_steady, "vessel": mode_vessel, "batch": mode_batch, "autotune": mode_autotune,
                "warmstart": mode_warmstart, "unet": mode_unet}[args.mode](args, torch, lbm)
         res["n_gpus"] = 1
         print(json.dumps(res), flush=True)
@@ -666,7 +692,7 @@ def main():
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     # D3Q19 on 4x4x4 tiles runs the scalar-mask kernel unless the generic one is asked for
     kernel, wkey = step_kernel_key(args)
-    traffic = traffic_for(kernel, wkey)
+    traffic, traffic_note = traffic_for(kernel, wkey) or (None, None)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -693,7 +719,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
+            "traffic": traffic, "traffic_source": traffic_note,
             # measured overhead over the algorithmic bytes (the paper's Delta^B, Table 5)
             "delta_b": round(traffic / alg_bytes - 1.0, 4) if traffic else None,
             "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes, "launch_ms": round(launch_ms, 5),
