@@ -40,6 +40,9 @@ __device__ __forceinline__ int64_t vidx(int x, int y, int z, const Grid &g) {
   return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
 }
 
+// periodic wrap of a coordinate within one period of the grid: v in [-n, 2n)
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
 // input voxel of GEMM row m for tap t
 template <int SRC>
 __device__ __forceinline__ int64_t src_voxel(int64_t m, int t, const Grid &rows, const Grid &in) {
@@ -237,7 +240,10 @@ template <int NW, int CC, bool RELU>
 __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   using BS = BrickShape<CC>;
   constexpr int CP = BS::CP;
-  __shared__ __attribute__((aligned(16))) bf16 halo[kHalo * CP];
+  // the output tile reuses the halo's LDS: 256 voxels x (16*NW + 8) bf16
+  constexpr int OS = 16 * NW + 8;
+  constexpr int kLds = kHalo * CP > kBrickX * kBrickY * kBrickZ * OS ? kHalo * CP : kBrickX * kBrickY * kBrickZ * OS;
+  __shared__ __attribute__((aligned(16))) bf16 halo[kLds];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, kb = lane >> 4;
   const Grid g = a.rows;  // CONV3: output grid == input grid
@@ -251,10 +257,15 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   int rowbase[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) rowbase[f] = ((r & 7) + kHaloX * ((2 * f + (r >> 3)) + kHaloY * wv)) * CP;
-  // per-lane weight rows (clamped to a valid output channel)
-  const bf16 *wrow[NW];
+  // per-lane byte offsets of the weight rows (clamped to a valid output
+  // channel) from a uniform base, so each weight load is a scalar base plus
+  // a 32-bit lane offset with no per-load address arithmetic
+  uint32_t wrow[NW];
 #pragma unroll
-  for (int j = 0; j < NW; ++j) wrow[j] = a.w + (int64_t)min(n0 + 16 * j + r, a.cout - 1) * ktot;
+  for (int j = 0; j < NW; ++j) wrow[j] = (uint32_t)(min(n0 + 16 * j + r, a.cout - 1) * ktot) * 2u;
+  auto wload = [&](int k, uint32_t lane_off) {  // k: uniform element offset inside a weight row
+    return *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const char *>(a.w + k) + lane_off);
+  };
 
   f32x4 acc[4][NW];
 #pragma unroll
@@ -271,11 +282,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
     const int e = tid + 256 * it;
     const int hv = e / G;
     const int hx = hv % kHaloX, hy = (hv / kHaloX) % kHaloY, hz = hv / (kHaloX * kHaloY);
-    int gx = (ox + hx - 1) % g.nx, gy = (oy + hy - 1) % g.ny, gz = (oz + hz - 1) % g.nz;
-    gx += gx < 0 ? g.nx : 0;
-    gy += gy < 0 ? g.ny : 0;
-    gz += gz < 0 ? g.nz : 0;
-    srow[it] = vidx(gx, gy, gz, g) * a.ldx;
+    srow[it] = vidx(wrap(ox + hx - 1, g.nx), wrap(oy + hy - 1, g.ny), wrap(oz + hz - 1, g.nz), g) * a.ldx;
   }
   for (int c0 = 0; c0 < a.cin; c0 += CC) {
     // issue every staging load of the chunk before the first LDS store
@@ -298,10 +305,11 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       // four taps per K step: lane group kb takes tap 4s + kb (tap 27 is padding)
       bf16x8 ring[kBrickRing8][NW];
       auto load_w = [&](int s0, bf16x8(&dst)[NW]) {
-        const int t = s0 + kb;
+        // lane group kb reads tap s0 + kb (tap 27, the padding, reads tap 26:
+        // its A values are zero)
+        const uint32_t toff = (uint32_t)((min(s0 + kb, 26) - s0) * a.cin) * 2u;
 #pragma unroll
-        for (int j = 0; j < NW; ++j)
-          dst[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (t < 27 ? t : 26) * a.cin + c0);
+        for (int j = 0; j < NW; ++j) dst[j] = wload(s0 * a.cin + c0, wrow[j] + toff);
       };
       static_for<kBrickRing8>([&](auto P) { load_w(4 * decltype(P)::value, ring[decltype(P)::value]); });
       static_for<7>([&](auto S) {
@@ -336,8 +344,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       auto load_w = [&](int u, bf16x8(&dst)[NW]) {
         const int t = u / BS::KS, st = u % BS::KS;
 #pragma unroll
-        for (int j = 0; j < NW; ++j)
-          dst[j] = *reinterpret_cast<const bf16x8 *>(wrow[j] + (int64_t)t * a.cin + c0 + cb[st]);
+        for (int j = 0; j < NW; ++j) dst[j] = wload(t * a.cin + c0, wrow[j] + (uint32_t)cb[st] * 2u);
       };
       static_for<R>([&](auto P) { load_w(decltype(P)::value, ring[decltype(P)::value]); });
       static_for<NSTEP>([&](auto U) {
@@ -359,23 +366,31 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
     }
   }
 
+  // epilogue: bias and ReLU, then the tile goes through LDS as [voxel][channel]
+  // so that each thread writes whole 16-byte channel groups of one voxel
+  __syncthreads();  // every wavefront's last halo reads are done
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
+  for (int j = 0; j < NW; ++j) {
+    const int nl = 16 * j + r, n = n0 + nl;
+    const float bias = (a.bias && n < a.cout) ? a.bias[n] : 0.f;
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const int n = n0 + 16 * j + r;
-      if (n >= a.cout) continue;
-      const float bias = a.bias ? a.bias[n] : 0.f;
+    for (int f = 0; f < 4; ++f)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int q = 4 * kb + i;  // row of the fragment
-        const int x = ox + (q & 7), y = oy + 2 * f + (q >> 3), z = oz + wv;
-        if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+        const int q = 4 * kb + i;  // row of the fragment: x = q & 7, y = 2f + (q >> 3), z = wv
         float v = acc[f][j][i] + bias;
         if (RELU) v = fmaxf(v, 0.f);
-        static_cast<bf16 *>(a.y)[vidx(x, y, z, g) * a.ldy + n] = (bf16)v;
+        halo[((q & 7) + kBrickX * (2 * f + (q >> 3) + kBrickY * wv)) * OS + nl] = (bf16)v;
       }
-    }
+  }
+  __syncthreads();
+  const int x = ox + (tid & 7), y = oy + ((tid >> 3) & 7), z = oz + (tid >> 6);
+  if (x < g.nx && y < g.ny && z < g.nz) {
+    bf16 *dst = static_cast<bf16 *>(a.y) + vidx(x, y, z, g) * a.ldy + n0;
+#pragma unroll
+    for (int c = 0; c < 2 * NW; ++c)
+      if (n0 + 8 * c < a.cout)
+        *reinterpret_cast<bf16x8 *>(dst + 8 * c) = *reinterpret_cast<const bf16x8 *>(&halo[tid * OS + 8 * c]);
   }
 }
 
@@ -509,6 +524,8 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
 // lane's 8 K values are the 8 voxels of one x-row.  The halo is kept as three
 // copies shifted by tx = 0, 1, 2 along x, xs[tx][c][hz][hy][8], so every
 // tap's A fragment is one aligned 16-byte LDS read; dy is ys[n][z][y][8].
+// Staging gives consecutive lanes consecutive voxels of one 8-channel group,
+// so a wavefront's 2-byte LDS writes of one channel fall into adjacent words.
 // K step k is the brick's z-plane k and lane group g its y-row g.
 // Wavefront w accumulates the taps w, w + 4, ... (7 or 6 of them) for the
 // whole channel tile in registers; the next brick's global rows are loaded
@@ -564,14 +581,12 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
       const int e = tid + 256 * it;
       vx[it] = bf16x8{};
       if (e < kWHalo * WB::GX) {
-        const int hv = e / WB::GX, q = e % WB::GX;
+        const int hv = e % kWHalo, q = e / kWHalo;
         const int hx = hv % (kWbX + 2), hy = (hv / (kWbX + 2)) % kWhY, hz = hv / ((kWbX + 2) * kWhY);
-        int gx = (ox + hx - 1) % gr.nx, gy = (oy + hy - 1) % gr.ny, gz = (oz + hz - 1) % gr.nz;
-        gx += gx < 0 ? gr.nx : 0;
-        gy += gy < 0 ? gr.ny : 0;
-        gz += gz < 0 ? gr.nz : 0;
         const int c = cbase + 8 * q;
-        if (c < a.cin) vx[it] = *reinterpret_cast<const bf16x8 *>(a.x + vidx(gx, gy, gz, gr) * a.ldx + c);
+        if (c < a.cin)
+          vx[it] = *reinterpret_cast<const bf16x8 *>(
+              a.x + vidx(wrap(ox + hx - 1, gr.nx), wrap(oy + hy - 1, gr.ny), wrap(oz + hz - 1, gr.nz), gr) * a.ldx + c);
       }
     }
 #pragma unroll
@@ -579,7 +594,7 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
       const int e = tid + 256 * it;
       vy[it] = bf16x8{};
       if (e < kWbX * kWbY * kWbZ * WB::GY) {
-        const int v = e / WB::GY, q = e % WB::GY;
+        const int v = e % (kWbX * kWbY * kWbZ), q = e / (kWbX * kWbY * kWbZ);
         const int x = ox + v % kWbX, y = oy + (v / kWbX) % kWbY, z = oz + v / (kWbX * kWbY);
         const int n = nbase + 8 * q;
         if (x < gr.nx && y < gr.ny && z < gr.nz && n < a.cout)
@@ -593,7 +608,7 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
     for (int it = 0; it < WB::NSX; ++it) {
       const int e = tid + 256 * it;
       if (e < kWHalo * WB::GX) {
-        const int hv = e / WB::GX, q = e % WB::GX;
+        const int hv = e % kWHalo, q = e / kWHalo;
         const int hx = hv % (kWbX + 2), row = hv / (kWbX + 2);  // row = hz * kWhY + hy
 #pragma unroll
         for (int tx = 0; tx < 3; ++tx) {
@@ -609,7 +624,7 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
     for (int it = 0; it < WB::NSY; ++it) {
       const int e = tid + 256 * it;
       if (e < kWbX * kWbY * kWbZ * WB::GY) {
-        const int v = e / WB::GY, q = e % WB::GY;
+        const int v = e % (kWbX * kWbY * kWbZ), q = e / (kWbX * kWbY * kWbZ);
         bf16 *dst = ys + (8 * q) * kWyStr + v;
 #pragma unroll
         for (int k = 0; k < 8; ++k) dst[k * kWyStr] = vy[it][k];
