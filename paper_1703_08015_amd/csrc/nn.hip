@@ -333,6 +333,53 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
             acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
         }
       });
+    } else if constexpr (CC == 24) {
+      // 24-channel chunks: K runs over (tap, channel) flattened, 27 * 24 = 648
+      // = 20.25 K steps of 32 instead of 27 steps padded from 24 to 32
+      // channels.  Lane group kb of step s takes k = 32 s + 8 kb: channels
+      // c .. c + 7 of tap t, with t = t0 + carry and c = c0 + 8 kb - 24 carry,
+      // where (t0, c0) is lane group 0's (a constant of the step, c0 in
+      // {0, 8, 16}) and carry = (c0 + 8 kb >= 24).  So a lane's LDS offset is a
+      // per-step constant plus 8 kb plus a carry term, and its weight offset
+      // likewise; the four fragments sit at fixed distances from fragment 0.
+      constexpr int NSTEP = (27 * 24 + 31) / 32;  // 21; lane groups 1-3 of the last step lie past k = 648
+      const bool carry8 = kb >= 2, carry16 = kb >= 1, carry0 = kb >= 3;  // carry for c0 = 8, 16, 0
+      const int abase = rowbase[0] + 8 * kb;
+      const uint32_t wlane = 16u * (uint32_t)kb, wcarry = (uint32_t)(a.cin - 24) * 2u;
+      constexpr int R = NW <= 2 ? 6 : 3;
+      bf16x8 ring[R][NW];
+      auto load_w = [&](auto U, bf16x8(&dst)[NW]) {
+        constexpr int k0 = 32 * decltype(U)::value, t0 = k0 / 24, cc0 = k0 % 24;
+        const bool cy = cc0 == 0 ? carry0 : (cc0 == 8 ? carry8 : carry16);
+        // lanes past the end (last step, kb >= 1) read a valid weight; their A is zero
+        const bool past = k0 + 8 * kb >= 27 * 24;
+        const uint32_t lo = past ? 0u : wlane + (cy ? wcarry : 0u);
+#pragma unroll
+        for (int j = 0; j < NW; ++j) dst[j] = wload(c0 + t0 * a.cin + cc0, wrow[j] + lo);
+      };
+      static_for<R>([&](auto P) { load_w(P, ring[decltype(P)::value]); });
+      static_for<NSTEP>([&](auto U) {
+        constexpr int u = decltype(U)::value, slot = u % R;
+        constexpr int k0 = 32 * u, t0 = k0 / 24, cc0 = k0 % 24;
+        constexpr int abase_u = tap_offset(t0) * CP + cc0;
+        constexpr int acarry = t0 < 26 ? (tap_offset(t0 + 1) - tap_offset(t0)) * CP - 24 : 0;
+        const bool cy = cc0 == 0 ? carry0 : (cc0 == 8 ? carry8 : carry16);
+        const int aoff = abase + (cy ? acarry : 0) + abase_u;
+        bf16x8 bv[NW];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) bv[j] = ring[slot][j];
+        if constexpr (u + R < NSTEP) load_w(std::integral_constant<int, u + R>{}, ring[slot]);
+        __builtin_amdgcn_sched_barrier(0);  // keep the load here: the scheduler would sink it next to its use
+        const bool zero = u == NSTEP - 1 && k0 + 8 * kb >= 27 * 24;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[(zero ? abase : aoff) + f * 2 * kHaloX * CP]);
+          if (zero) av = bf16x8{};
+#pragma unroll
+          for (int j = 0; j < NW; ++j)
+            acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
+        }
+      });
     } else {
       int cb[BS::KS];  // weight channel of this lane's k group, clamped into the tap
 #pragma unroll
@@ -547,7 +594,8 @@ struct WBrick {
 };
 
 template <int CF, int NF>
-__global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block, int cblocks) {
+__global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block, int cblocks,
+                                                     float *ws) {
   using WB = WBrick<CF, NF>;
   extern __shared__ __attribute__((aligned(16))) bf16 wlds[];
   bf16 *xs = wlds;                                 // [3][16*CF][kWxStr]
@@ -663,8 +711,12 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
       if (wv < 3) tap(kWTaps - 1);
     }
   }
-  // lane holds C[c = 16i + 4g + q][n = 16j + r] of tap t
+  // lane holds C[c = 16i + 4g + q][n = 16j + r] of tap t.  With a workspace,
+  // the block's partial sums go to its own slot [27][16*CF][16*NF] there and
+  // k_wgrad_sum adds the blocks in a fixed order; without one, each weight
+  // takes one FP32 atomic add per block.
   const int ktot = 27 * a.cin;
+  float *slot = ws ? ws + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (27 * 256 * CF * NF) : nullptr;
 #pragma unroll
   for (int m = 0; m < kWTaps; ++m) {
     const int t = wv + 4 * m;
@@ -675,10 +727,50 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
       for (int j = 0; j < NF; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int c = cbase + 16 * i + 4 * g + q, n = nbase + 16 * j + r;
-          if (c < a.cin && n < a.cout) atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, acc[m][i][j][q]);
+          const int cl = 16 * i + 4 * g + q, nl = 16 * j + r;
+          if (slot) {
+            slot[(t * 16 * CF + cl) * 16 * NF + nl] = acc[m][i][j][q];
+          } else {
+            const int c = cbase + cl, n = nbase + nl;
+            if (c < a.cin && n < a.cout) atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, acc[m][i][j][q]);
+          }
         }
   }
+}
+
+// dw += the sum over the blocks of one channel tile of their partial slots,
+// in two passes with a fixed order (run to run identical).  Pass 1: thread
+// (e, part) sums the slots of blocks part*per .. part*per + per - 1 with eight
+// independent partial sums (eight loads in flight) and writes the total into
+// the first of those slots, which only it reads.  Pass 2 (parts = 0): thread e
+// adds the parts' totals in order into dw.  e = (t * 16*CF + cl) * 16*NF + nl.
+__global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int blocks, int per, int cf, int nf,
+                                                   int cblocks, int cin, int cout, float *dw, int pass) {
+  const int E = 27 * 256 * cf * nf;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= E) return;
+  const int parts = (blocks + per - 1) / per;
+  if (pass == 1) {
+    const int tile = blockIdx.y / parts, part = blockIdx.y % parts;
+    float *p = ws + ((int64_t)tile * blocks + (int64_t)part * per) * E + e;
+    const int n = min(per, blocks - part * per);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int b = 0;
+    for (; b + 8 <= n; b += 8)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += p[(int64_t)(b + k) * E];
+    for (; b < n; ++b) acc[0] += p[(int64_t)b * E];
+    p[0] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    return;
+  }
+  const int tile = blockIdx.y;
+  const int nl = e % (16 * nf), cl = (e / (16 * nf)) % (16 * cf), t = e / (256 * cf * nf);
+  const int c = (tile % cblocks) * 16 * cf + cl, n = (tile / cblocks) * 16 * nf + nl;
+  if (c >= cin || n >= cout) return;
+  const float *p = ws + (int64_t)tile * blocks * E + e;
+  float sum = 0.f;
+  for (int q = 0; q < parts; ++q) sum += p[(int64_t)q * per * E];
+  dw[((int64_t)n * 27 + t) * cin + c] += sum;
 }
 
 // bias gradient: db[n] += sum over rows of dy[row][n], a column sum of a
@@ -1084,23 +1176,42 @@ hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int CF, int NF>
-hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, hipStream_t s) {
-  using WB = WBrick<CF, NF>;
-  const int cblocks = (a.cin + 16 * CF - 1) / (16 * CF), nblocks = (a.cout + 16 * NF - 1) / (16 * NF);
+// Grid of the brick weight gradient: about two blocks per compute unit in
+// all; each block sums its bricks in registers.
+struct WgradGrid {
+  int cblocks, nblocks;
+  int64_t per, gx;
+};
+WgradGrid wgrad_grid(const GemmArgs &a, int cf, int nf) {
+  WgradGrid w;
+  w.cblocks = (a.cin + 16 * cf - 1) / (16 * cf);
+  w.nblocks = (a.cout + 16 * nf - 1) / (16 * nf);
   const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
                           ((a.rows.nz + kWbZ - 1) / kWbZ);
-  // about two blocks per compute unit in all: each block sums its bricks in
-  // registers, so fewer, longer blocks mean fewer atomic adds at the end
-  const int64_t tiles = (int64_t)cblocks * nblocks;
-  int64_t per = (nbricks * tiles + 511) / 512;
-  if (per < 1) per = 1;
-  const int64_t gx = (nbricks + per - 1) / per;
+  const int64_t tiles = (int64_t)w.cblocks * w.nblocks;
+  w.per = (nbricks * tiles + 511) / 512;
+  if (w.per < 1) w.per = 1;
+  w.gx = (nbricks + w.per - 1) / w.per;
+  return w;
+}
+
+template <int CF, int NF>
+hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+  using WB = WBrick<CF, NF>;
+  const WgradGrid w = wgrad_grid(a, CF, NF);
+  const int tiles = w.cblocks * w.nblocks;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad_brick<CF, NF>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, WB::LDS);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)gx, (unsigned)tiles), dim3(256), WB::LDS, s, a, dw,
-                     (int)per, cblocks);
+  hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)w.gx, (unsigned)tiles), dim3(256), WB::LDS, s, a, dw,
+                     (int)w.per, w.cblocks, ws);
+  e = hipGetLastError();
+  if (e != hipSuccess || !ws) return e;
+  const int E = 27 * 256 * CF * NF, per = 32, parts = (int)((w.gx + per - 1) / per);
+  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)(tiles * parts)), dim3(256), 0, s, ws,
+                     (int)w.gx, per, CF, NF, w.cblocks, a.cin, a.cout, dw, 1);
+  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,
+                     (int)w.gx, per, CF, NF, w.cblocks, a.cin, a.cout, dw, 2);
   return hipGetLastError();
 }
 
@@ -1115,22 +1226,41 @@ int wgrad_frags(int c, int max_frags) {
 }
 
 // The brick weight gradient for 3x3x3 convolutions on grids of at least
-// 2048 bricks (64^3 and up); returns false to use k_wgrad instead.
-bool try_wgrad_brick(const GemmArgs &a, float *dw, hipStream_t s, hipError_t *err) {
+// 2048 bricks (64^3 and up).
+bool wgrad_brick_applies(const GemmArgs &a) {
   const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
                           ((a.rows.nz + kWbZ - 1) / kWbZ);
-  if (nbricks < 2048) return false;
-  const int cf = wgrad_frags(a.cin, 3);
-  const int nf = wgrad_frags(a.cout, cf == 3 ? 2 : 3);
+  return nbricks >= 2048;
+}
+void wgrad_brick_frags(const GemmArgs &a, int *cf, int *nf) {
+  *cf = wgrad_frags(a.cin, 3);
+  *nf = wgrad_frags(a.cout, *cf == 3 ? 2 : 3);
+}
+// Workspace floats the brick weight gradient's partial sums need (0 when the
+// brick kernel does not apply).
+int64_t wgrad_brick_ws_floats(const GemmArgs &a) {
+  if (!wgrad_brick_applies(a)) return 0;
+  int cf, nf;
+  wgrad_brick_frags(a, &cf, &nf);
+  const WgradGrid w = wgrad_grid(a, cf, nf);
+  return (int64_t)w.cblocks * w.nblocks * w.gx * 27 * 256 * cf * nf;
+}
+
+// Runs the brick weight gradient if it applies (returns false to use k_wgrad
+// instead); ws: partial sums (wgrad_brick_ws_floats) or NULL for atomics.
+bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, hipStream_t s, hipError_t *err) {
+  if (!wgrad_brick_applies(a)) return false;
+  int cf, nf;
+  wgrad_brick_frags(a, &cf, &nf);
   switch (cf * 4 + nf) {
-    case 5: *err = launch_wgrad_brick_cf<1, 1>(a, dw, s); break;
-    case 6: *err = launch_wgrad_brick_cf<1, 2>(a, dw, s); break;
-    case 7: *err = launch_wgrad_brick_cf<1, 3>(a, dw, s); break;
-    case 9: *err = launch_wgrad_brick_cf<2, 1>(a, dw, s); break;
-    case 10: *err = launch_wgrad_brick_cf<2, 2>(a, dw, s); break;
-    case 11: *err = launch_wgrad_brick_cf<2, 3>(a, dw, s); break;
-    case 13: *err = launch_wgrad_brick_cf<3, 1>(a, dw, s); break;
-    default: *err = launch_wgrad_brick_cf<3, 2>(a, dw, s); break;
+    case 5: *err = launch_wgrad_brick_cf<1, 1>(a, dw, ws, s); break;
+    case 6: *err = launch_wgrad_brick_cf<1, 2>(a, dw, ws, s); break;
+    case 7: *err = launch_wgrad_brick_cf<1, 3>(a, dw, ws, s); break;
+    case 9: *err = launch_wgrad_brick_cf<2, 1>(a, dw, ws, s); break;
+    case 10: *err = launch_wgrad_brick_cf<2, 2>(a, dw, ws, s); break;
+    case 11: *err = launch_wgrad_brick_cf<2, 3>(a, dw, ws, s); break;
+    case 13: *err = launch_wgrad_brick_cf<3, 1>(a, dw, ws, s); break;
+    default: *err = launch_wgrad_brick_cf<3, 2>(a, dw, ws, s); break;
   }
   return true;
 }
@@ -1169,10 +1299,18 @@ extern "C" int lbm_nn_forward(const lbm_nn_gemm *g, void *stream) {
   return LBM_OK;
 }
 
-extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream) {
+// Weight gradient with an optional workspace for the brick kernel's partial sums.
+static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int64_t ws_floats, void *stream) {
   int rc = check_gemm(g, true);
   if (rc) return rc;
   if (!dw) return set_error(LBM_ERR_ARG, "lbm_nn_wgrad: NULL dw");
+  if (ws) {
+    const int64_t need =
+        (g->src_mode == LBM_NN_CONV3 && g->dst_mode == LBM_NN_IDENT) ? wgrad_brick_ws_floats(to_args(g)) : 0;
+    if (ws_floats < need)
+      return set_error(LBM_ERR_ARG, "lbm_nn_wgrad_ws: workspace of %lld floats, %lld needed", (long long)ws_floats,
+                       (long long)need);
+  }
   if (db && g->cout > 2048) return set_error(LBM_ERR_SHAPE, "lbm_nn_wgrad: bias gradient of %d > 2048 channels", g->cout);
   const GemmArgs a = to_args(g);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1180,7 +1318,7 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
     NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
     hipError_t e = hipSuccess;
-    if (!try_wgrad_brick(a, dw, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s);
+    if (!try_wgrad_brick(a, dw, ws, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s);
     NN_TRY(e);
   } else if (g->src_mode == LBM_NN_GATHER2) {
     NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, s)));
@@ -1197,6 +1335,21 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
     NN_TRY(hipGetLastError());
   }
   return LBM_OK;
+}
+
+extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream) {
+  return wgrad_impl(g, dw, db, nullptr, 0, stream);
+}
+
+extern "C" int64_t lbm_nn_wgrad_workspace(const lbm_nn_gemm *g) {
+  if (check_gemm(g, true)) return -1;
+  if (g->src_mode != LBM_NN_CONV3 || g->dst_mode != LBM_NN_IDENT) return 0;
+  return wgrad_brick_ws_floats(to_args(g));
+}
+
+extern "C" int lbm_nn_wgrad_ws(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int64_t ws_floats,
+                               void *stream) {
+  return wgrad_impl(g, dw, db, ws, ws_floats, stream);
 }
 
 extern "C" int lbm_nn_backward_weights(int32_t mode, int32_t taps, int32_t cin, int32_t cout, const void *w, void *wt,

@@ -7,7 +7,7 @@ bfloat16 (cout, taps, cin).
 """
 import ctypes
 
-from .lbm import _check, lib
+from .lbm import LbmError, _check, lib
 
 IDENT, CONV3, GATHER2, SCATTER2 = 0, 1, 2, 3
 
@@ -34,6 +34,7 @@ def _lib():
         sig = {
             "lbm_nn_forward": [G, P],
             "lbm_nn_wgrad": [G, P, P, P],
+            "lbm_nn_wgrad_ws": [G, P, P, P, I64, P],
             "lbm_nn_backward_weights": [I32, I32, I32, I32, P, P, P],
             "lbm_nn_maxpool2": [P, I32, P, I32, P, I32, P, P],
             "lbm_nn_maxpool2_backward": [P, I32, P, I32, P, P, I32, I32, P],
@@ -51,6 +52,8 @@ def _lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = args
+        L.lbm_nn_wgrad_workspace.restype = I64
+        L.lbm_nn_wgrad_workspace.argtypes = [G]
         _sigs_done = True
     return L
 
@@ -95,10 +98,26 @@ def forward(src, dst, rows, taps, cin, cout, x, ldx, w, y, ldy, bias=None, y_fp3
     _check(_lib().lbm_nn_forward(ctypes.byref(g), _stream(stream)), "lbm_nn_forward")
 
 
-def wgrad(src, dst, rows, taps, cin, cout, x, ldx, dy, lddy, dw, db=None, stream=None, x_offset=0, dy_offset=0):
+def wgrad(src, dst, rows, taps, cin, cout, x, ldx, dy, lddy, dw, db=None, stream=None, x_offset=0, dy_offset=0,
+          ws=None):
+    """lbm_nn_wgrad, or lbm_nn_wgrad_ws when a workspace tensor (FP32, at
+    least wgrad_workspace(...) elements) is given."""
     g = _gemm(src, dst, rows, taps, cin, cout, x.data_ptr() + 2 * x_offset, ldx, None, None,
               dy.data_ptr() + 2 * dy_offset, lddy, False, False)
-    _check(_lib().lbm_nn_wgrad(ctypes.byref(g), _ptr(dw), _ptr(db), _stream(stream)), "lbm_nn_wgrad")
+    if ws is None:
+        _check(_lib().lbm_nn_wgrad(ctypes.byref(g), _ptr(dw), _ptr(db), _stream(stream)), "lbm_nn_wgrad")
+    else:
+        _check(_lib().lbm_nn_wgrad_ws(ctypes.byref(g), _ptr(dw), _ptr(db), _ptr(ws), int(ws.numel()),
+                                      _stream(stream)), "lbm_nn_wgrad_ws")
+
+
+def wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy):
+    """FP32 elements of the workspace lbm_nn_wgrad_ws uses for this layer."""
+    g = _gemm(src, dst, rows, taps, cin, cout, 16, ldx, None, None, 16, lddy, False, False)
+    n = int(_lib().lbm_nn_wgrad_workspace(ctypes.byref(g)))
+    if n < 0:
+        raise LbmError(-1, "lbm_nn_wgrad_workspace", "invalid layer")
+    return n
 
 
 def backward_weights(mode, taps, cin, cout, w, wt, stream=None):

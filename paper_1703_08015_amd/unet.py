@@ -169,10 +169,22 @@ class UNet:
         if relu:
             nn.relu_backward(n, cout, y, ldy, dy, lddy, y_offset=y_offset, dy_offset=dy_offset)
         nn.wgrad(nn.CONV3, nn.IDENT, rows, 27, cin, cout, x, ldx, dy, lddy, w.g, b.g, x_offset=x_offset,
-                 dy_offset=dy_offset)
+                 dy_offset=dy_offset, ws=self._wgrad_ws(rows, cin, cout, ldx, lddy))
         if need_dx:
             wt = self._wt(w, nn.CONV3, 27, cin, cout)
             nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, x_offset=dy_offset)
+
+    def _wgrad_ws(self, rows, cin, cout, ldx, lddy):
+        """The shared workspace of the 3x3x3 weight gradients (partial sums
+        per block, added in a fixed order), grown to the largest layer; None
+        where a layer needs none."""
+        n = nn.wgrad_workspace(nn.CONV3, nn.IDENT, rows, 27, cin, cout, ldx, lddy)
+        if n == 0:
+            return None
+        ws = getattr(self, "_ws", None)
+        if ws is None or ws.numel() < n:
+            ws = self._ws = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
+        return ws[:n]
 
     def _wt(self, w, mode, taps, cin, cout):
         t = self.torch

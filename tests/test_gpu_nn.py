@@ -133,6 +133,22 @@ def test_conv3_wgrad_brick_kernel(torch, grid, cin, cout):
     _, gw, gb = onn.conv3_backward(x, np.zeros((cout, 27, cin)), dy)
     close(host(dw), gw, 2e-5)
     close(host(db), gb, 2e-5)
+    # with a workspace: per-block partial sums added in a fixed order, the same
+    # result to rounding and identical from run to run
+    n = nn.wgrad_workspace(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, cin, cout)
+    assert n > 0
+    ws = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    runs = []
+    for _ in range(2):
+        dw2 = torch.zeros((cout, 27, cin), dtype=torch.float32, device="cuda")
+        nn.wgrad(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw2,
+                 ws=ws)
+        runs.append(host(dw2))
+    close(runs[0], gw, 2e-5)
+    assert np.array_equal(runs[0], runs[1])
+    with pytest.raises(Exception):
+        nn.wgrad(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw2,
+                 ws=ws[: n - 1])
 
 
 @pytest.mark.parametrize("cin,cout", [(48, 24), (16, 8)])
