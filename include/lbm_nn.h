@@ -56,11 +56,19 @@ typedef struct {
   int32_t ldy;
   int32_t y_fp32;
   int32_t relu;         /* apply max(0, .) */
+  int32_t gate_channels; /* 0, or the leading output channels that gate masks (a multiple of 8, <= cout) */
+  const void *gate;     /* NULL, or BF16 rows on the output grid, stride ldg (16-byte aligned, ldg a multiple of 8) */
+  int32_t ldg;
   int32_t reserved;
 } lbm_nn_gemm;
 
 /* y = act(gather-GEMM(x, w) + bias).  For LBM_NN_SCATTER2 every output voxel
- * of the fine grid is written once over the 8 taps. */
+ * of the fine grid is written once over the 8 taps.
+ * With a gate, y[v][n] = 0 for n < gate_channels wherever gate[v][n] is not
+ * greater than 0 (NaN included).  This is the derivative of a ReLU applied to
+ * a backward-data pass: with gate = the layer's forward input x, itself a
+ * ReLU output, the kernel writes dL/d(pre-activation) instead of dL/dx, and
+ * no separate lbm_nn_relu_backward pass over the gradient is needed. */
 int lbm_nn_forward(const lbm_nn_gemm *g, void *stream);
 
 /* Weight gradient of the same layer: dw[n][t*cin + c] += sum_m x[src(m,t)][c]

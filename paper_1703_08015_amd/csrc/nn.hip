@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <initializer_list>
 
 #include "device.h"
 #include "internal.h"
@@ -34,7 +35,12 @@ struct GemmArgs {
   const bf16 *w;
   const float *bias;
   void *y;
+  const bf16 *gate;  // ReLU gate of a backward-data pass (NULL: none)
+  int ldg, gate_ch;
 };
+
+// the derivative of a ReLU whose output is g: 1 where g > 0 (NaN: 0)
+__device__ __forceinline__ bool gate_open(bf16 g) { return (float)g > 0.f; }
 
 __device__ __forceinline__ int64_t vidx(int x, int y, int z, const Grid &g) {
   return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
@@ -199,7 +205,9 @@ __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
         if (mo >= a.M) continue;
         float v = acc[f][j][i] + bias;
         if (RELU) v = fmaxf(v, 0.f);
-        const int64_t d = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid) * a.ldy + n;
+        const int64_t dv = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid);
+        if (n < a.gate_ch && !gate_open(a.gate[dv * a.ldg + n])) v = 0.f;
+        const int64_t d = dv * a.ldy + n;
         if (F32)
           static_cast<float *>(a.y)[d] = v;
         else
@@ -433,11 +441,20 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   __syncthreads();
   const int x = ox + (tid & 7), y = oy + ((tid >> 3) & 7), z = oz + (tid >> 6);
   if (x < g.nx && y < g.ny && z < g.nz) {
-    bf16 *dst = static_cast<bf16 *>(a.y) + vidx(x, y, z, g) * a.ldy + n0;
+    const int64_t v = vidx(x, y, z, g);
+    bf16 *dst = static_cast<bf16 *>(a.y) + v * a.ldy + n0;
 #pragma unroll
     for (int c = 0; c < 2 * NW; ++c)
-      if (n0 + 8 * c < a.cout)
-        *reinterpret_cast<bf16x8 *>(dst + 8 * c) = *reinterpret_cast<const bf16x8 *>(&halo[tid * OS + 8 * c]);
+      if (n0 + 8 * c < a.cout) {
+        bf16x8 o = *reinterpret_cast<const bf16x8 *>(&halo[tid * OS + 8 * c]);
+        if (n0 + 8 * c < a.gate_ch) {  // whole 8-channel groups (gate_ch is a multiple of 8)
+          const bf16x8 gv = *reinterpret_cast<const bf16x8 *>(a.gate + v * a.ldg + n0 + 8 * c);
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (!gate_open(gv[e])) o[e] = (bf16)0.f;
+        }
+        *reinterpret_cast<bf16x8 *>(dst + 8 * c) = o;
+      }
   }
 }
 
@@ -791,7 +808,20 @@ __global__ void __launch_bounds__(256) k_colsum(const bf16 *y, int64_t rows, int
   const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
   if (lane_row < rp) {
     const int c = 8 * cg;
-    for (int64_t r = r0 + lane_row; r < r1; r += rp) {
+    int64_t r = r0 + lane_row;
+    if (c + 8 <= cols) {
+      // four rows' loads in flight per iteration
+      for (; r + 3 * rp < r1; r += 4 * rp) {
+        bf16x8 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8 *>(y + (r + u * rp) * ld + c);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[q] += (float)v[u][q];
+      }
+    }
+    for (; r < r1; r += rp) {
       const bf16 *row = y + r * ld + c;
       if (c + 8 <= cols) {
         const bf16x8 v = *reinterpret_cast<const bf16x8 *>(row);
@@ -862,6 +892,86 @@ __global__ void k_maxpool_backward(Grid g, int channels, const bf16 *dy, int ldy
   }
 }
 
+// The same three operations on whole 8-channel groups (channels, strides and
+// pointers multiples of 8 elements / 16 bytes, fewer than 2^31 groups): one
+// thread per (voxel, group) with 16-byte loads and stores and 32-bit index
+// arithmetic.  Thread e takes group q = e % groups of voxel e / groups.
+__global__ void __launch_bounds__(256) k_maxpool8(Grid g, int groups, const bf16 *x, int ldx, bf16 *y, int ldy,
+                                                  uint8_t *arg) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= g.nx * g.ny * g.nz * groups) return;
+  const int q = e % groups, v = e / groups;
+  const int cx = v % g.nx, cy = (v / g.nx) % g.ny, cz = v / (g.nx * g.ny);
+  const Grid f{2 * g.nx, 2 * g.ny, 2 * g.nz};
+  bf16x8 in[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    in[k] = *reinterpret_cast<const bf16x8 *>(
+        x + vidx(2 * cx + (k & 1), 2 * cy + ((k >> 1) & 1), 2 * cz + (k >> 2), f) * ldx + 8 * q);
+  bf16x8 best;
+  uint64_t who = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    float b = -INFINITY;
+    int w = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {  // first strict maximum wins (NaN never does)
+      const float val = (float)in[k][c];
+      if (val > b) b = val, w = k;
+    }
+    best[c] = (bf16)b;
+    who |= (uint64_t)w << (8 * c);
+  }
+  *reinterpret_cast<bf16x8 *>(y + (int64_t)v * ldy + 8 * q) = best;
+  *reinterpret_cast<uint64_t *>(arg + (int64_t)v * (8 * groups) + 8 * q) = who;
+}
+
+__global__ void __launch_bounds__(256) k_maxpool_backward8(Grid g, int groups, const bf16 *dy, int ldy,
+                                                           const uint8_t *arg, bf16 *dx, int ldx, int accumulate) {
+  const Grid f{2 * g.nx, 2 * g.ny, 2 * g.nz};
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= f.nx * f.ny * f.nz * groups) return;
+  const int q = e % groups, v = e / groups;
+  const int xx = v % f.nx, yy = (v / f.nx) % f.ny, zz = v / (f.nx * f.ny);
+  const int k = (xx & 1) | ((yy & 1) << 1) | ((zz & 1) << 2);
+  const int64_t cv = vidx(xx >> 1, yy >> 1, zz >> 1, g);
+  const uint64_t who = *reinterpret_cast<const uint64_t *>(arg + cv * (8 * groups) + 8 * q);
+  const bf16x8 d = *reinterpret_cast<const bf16x8 *>(dy + cv * ldy + 8 * q);
+  bf16 *out = dx + (int64_t)v * ldx + 8 * q;
+  bf16x8 o = accumulate ? *reinterpret_cast<const bf16x8 *>(out) : bf16x8{};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const float routed = (int)((who >> (8 * c)) & 0xff) == k ? (float)d[c] : 0.f;
+    o[c] = (bf16)(accumulate ? (float)o[c] + routed : routed);
+  }
+  *reinterpret_cast<bf16x8 *>(out) = o;
+}
+
+__global__ void __launch_bounds__(256) k_relu_backward8(int n, int groups, const bf16 *y, int ldy, bf16 *dy,
+                                                        int lddy) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * groups) return;
+  const int q = e % groups, row = e / groups;
+  const bf16x8 yv = *reinterpret_cast<const bf16x8 *>(y + (int64_t)row * ldy + 8 * q);
+  bf16 *p = dy + (int64_t)row * lddy + 8 * q;
+  bf16x8 d = *reinterpret_cast<const bf16x8 *>(p);
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (!((float)yv[c] > 0.f)) d[c] = (bf16)0.f;
+  *reinterpret_cast<bf16x8 *>(p) = d;
+}
+
+// whether an element-wise BF16 operation can run on whole 16-byte groups
+bool groups8(int64_t elements_per_row, std::initializer_list<int64_t> strides,
+             std::initializer_list<const void *> ptrs, int64_t rows) {
+  if (elements_per_row % 8) return false;
+  for (int64_t s : strides)
+    if (s % 8) return false;
+  for (const void *p : ptrs)
+    if ((uintptr_t)p % 16) return false;
+  return rows * (elements_per_row / 8) <= INT32_MAX - 255;
+}
+
 __global__ void k_relu_backward(int64_t n, int channels, const bf16 *y, int ldy, bf16 *dy, int lddy) {
   const int64_t total = n * channels;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -910,17 +1020,34 @@ __global__ void k_adam(int64_t n, float *p, float *m, float *v, const float *g, 
   }
 }
 
-__global__ void k_mix(int64_t n, const float *y, float d0, float d1, float d2, float *p) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    for (int k = 0; k < 4; ++k) p[4 * e + k] = d0 * y[12 * e + k] + d1 * y[12 * e + 4 + k] + d2 * y[12 * e + 8 + k];
+// one voxel per thread: three 16-byte loads of y (12 FP32 channels), one
+// 16-byte store of p
+__global__ void __launch_bounds__(256) k_mix(int64_t n, const float *y, float d0, float d1, float d2, float *p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float4 *row = reinterpret_cast<const float4 *>(y + 12 * e);
+  const float4 a = row[0], b = row[1], c = row[2];
+  reinterpret_cast<float4 *>(p)[e] = make_float4(d0 * a.x + d1 * b.x + d2 * c.x, d0 * a.y + d1 * b.y + d2 * c.y,
+                                                 d0 * a.z + d1 * b.z + d2 * c.z, d0 * a.w + d1 * b.w + d2 * c.w);
 }
 
-__global__ void k_mix_backward(int64_t n, const bf16 *dp, int ldp, float d0, float d1, float d2, bf16 *dy, int ldy) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    const float d[3] = {d0, d1, d2};
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 4; ++k) dy[e * ldy + 4 * j + k] = (bf16)(d[j] * (float)dp[e * ldp + k]);
-    for (int c = 12; c < ldy; ++c) dy[e * ldy + c] = (bf16)0.f;
+// one voxel per thread; dy rows (ldy a multiple of 8, 16-byte aligned) are
+// written in 16-byte groups: channels 0..11 = d_j dp[k], the rest 0
+__global__ void __launch_bounds__(256) k_mix_backward(int64_t n, const bf16 *dp, int ldp, float d0, float d1,
+                                                      float d2, bf16 *dy, int ldy) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float d[3] = {d0, d1, d2};
+  float g[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[k] = (float)dp[e * ldp + k];
+  bf16 *row = dy + e * ldy;
+  for (int c0 = 0; c0 < ldy; c0 += 8) {
+    bf16x8 o = {};
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c0 + c < 12) o[c] = (bf16)(d[(c0 + c) / 4] * g[(c0 + c) % 4]);
+    *reinterpret_cast<bf16x8 *>(row + c0) = o;
   }
 }
 
@@ -1049,6 +1176,9 @@ GemmArgs to_args(const lbm_nn_gemm *g) {
   a.w = static_cast<const bf16 *>(g->w);
   a.bias = g->bias;
   a.y = g->y;
+  a.gate = static_cast<const bf16 *>(g->gate);
+  a.ldg = g->ldg;
+  a.gate_ch = g->gate ? g->gate_channels : 0;
   return a;
 }
 
@@ -1071,6 +1201,14 @@ int check_gemm(const lbm_nn_gemm *g, bool wgrad) {
     return set_error(LBM_ERR_SHAPE, "lbm_nn: BF16 rows need cout and ldy multiples of 8");
   if ((uintptr_t)g->x % 16 || (g->w && (uintptr_t)g->w % 16) || (uintptr_t)g->y % 16)
     return set_error(LBM_ERR_ARG, "lbm_nn: tensors must be 16-byte aligned");
+  if (g->gate && !wgrad) {
+    if (g->gate_channels <= 0 || g->gate_channels > g->cout || g->gate_channels % 8)
+      return set_error(LBM_ERR_SHAPE, "lbm_nn: gate_channels %d (multiple of 8 in 8..cout = %d)", g->gate_channels,
+                       g->cout);
+    if (g->ldg < g->gate_channels || g->ldg % 8 || (uintptr_t)g->gate % 16)
+      return set_error(LBM_ERR_SHAPE, "lbm_nn: gate rows need ldg %d >= gate_channels, a multiple of 8, 16-byte aligned",
+                       g->ldg);
+  }
   return LBM_OK;
 }
 
@@ -1328,7 +1466,10 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
   if (db) {
     // all output voxels: M rows, or M * 8 fine voxels of a 2x2x2 transposed convolution
     const int64_t rows = g->dst_mode == LBM_NN_SCATTER2 ? (int64_t)a.out_grid.nx * a.out_grid.ny * a.out_grid.nz : a.M;
-    const int64_t chunk = 1024;
+    // about 2048 blocks (each block's rows: at least 256, so that its row
+    // lanes have several rows each on small grids)
+    int64_t chunk = (rows + 2047) / 2048;
+    if (chunk < 256) chunk = 256;
     const unsigned gx = (unsigned)((rows + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_colsum, dim3(gx), dim3(256), 0, s, static_cast<const bf16 *>(a.y), rows, a.ldy, a.cout, db,
                        chunk);
@@ -1369,6 +1510,14 @@ extern "C" int lbm_nn_maxpool2(const int32_t grid[3], int32_t channels, const vo
     return set_error(LBM_ERR_ARG, "lbm_nn_maxpool2: args");
   const Grid g{grid[0], grid[1], grid[2]};
   const int64_t n = (int64_t)g.nx * g.ny * g.nz * channels;
+  if (n == 0) return LBM_OK;
+  if (groups8(channels, {ldx, ldy}, {x, y}, 8 * (int64_t)g.nx * g.ny * g.nz) && (uintptr_t)arg % 8 == 0) {
+    hipLaunchKernelGGL(k_maxpool8, dim3((unsigned)((n / 8 + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), g, channels / 8, static_cast<const bf16 *>(x), ldx,
+                       static_cast<bf16 *>(y), ldy, arg);
+    NN_TRY(hipGetLastError());
+    return LBM_OK;
+  }
   hipLaunchKernelGGL(k_maxpool, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), g, channels,
                      static_cast<const bf16 *>(x), ldx, static_cast<bf16 *>(y), ldy, arg);
   NN_TRY(hipGetLastError());
@@ -1381,6 +1530,14 @@ extern "C" int lbm_nn_maxpool2_backward(const int32_t grid[3], int32_t channels,
     return set_error(LBM_ERR_ARG, "lbm_nn_maxpool2_backward: args");
   const Grid g{grid[0], grid[1], grid[2]};
   const int64_t n = (int64_t)8 * g.nx * g.ny * g.nz * channels;
+  if (n == 0) return LBM_OK;
+  if (groups8(channels, {ldx, ldy}, {dx, dy}, 8 * (int64_t)g.nx * g.ny * g.nz) && (uintptr_t)arg % 8 == 0) {
+    hipLaunchKernelGGL(k_maxpool_backward8, dim3((unsigned)((n / 8 + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), g, channels / 8, static_cast<const bf16 *>(dy), ldy, arg,
+                       static_cast<bf16 *>(dx), ldx, accumulate);
+    NN_TRY(hipGetLastError());
+    return LBM_OK;
+  }
   hipLaunchKernelGGL(k_maxpool_backward, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), g,
                      channels, static_cast<const bf16 *>(dy), ldy, arg, static_cast<bf16 *>(dx), ldx, accumulate);
   NN_TRY(hipGetLastError());
@@ -1390,6 +1547,14 @@ extern "C" int lbm_nn_maxpool2_backward(const int32_t grid[3], int32_t channels,
 extern "C" int lbm_nn_relu_backward(int64_t n, int32_t channels, const void *y, int32_t ld_y, void *dy, int32_t ld_dy,
                                     void *stream) {
   if (!y || !dy || n < 0 || channels <= 0) return set_error(LBM_ERR_ARG, "lbm_nn_relu_backward: args");
+  if (n == 0) return LBM_OK;
+  if (groups8(channels, {ld_y, ld_dy}, {y, dy}, n)) {
+    hipLaunchKernelGGL(k_relu_backward8, dim3((unsigned)((n * (channels / 8) + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), (int)n, channels / 8, static_cast<const bf16 *>(y), ld_y,
+                       static_cast<bf16 *>(dy), ld_dy);
+    NN_TRY(hipGetLastError());
+    return LBM_OK;
+  }
   hipLaunchKernelGGL(k_relu_backward, dim3(grid_for(n * channels)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
                      channels, static_cast<const bf16 *>(y), ld_y, static_cast<bf16 *>(dy), ld_dy);
   NN_TRY(hipGetLastError());
@@ -1419,7 +1584,10 @@ extern "C" int lbm_nn_adam(int64_t n, float *p, float *m, float *v, const float 
 
 extern "C" int lbm_nn_mix(int64_t n, const float *y, const float dir[3], float *p, void *stream) {
   if (!y || !dir || !p || n < 0) return set_error(LBM_ERR_ARG, "lbm_nn_mix: args");
-  hipLaunchKernelGGL(k_mix, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, y, dir[0], dir[1],
+  if ((uintptr_t)y % 16 || (uintptr_t)p % 16) return set_error(LBM_ERR_ARG, "lbm_nn_mix: y and p must be 16-byte aligned");
+  if (n == 0) return LBM_OK;
+  if (n > (int64_t)INT32_MAX * 256) return set_error(LBM_ERR_SHAPE, "lbm_nn_mix: too many nodes");
+  hipLaunchKernelGGL(k_mix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), n, y, dir[0], dir[1],
                      dir[2], p);
   NN_TRY(hipGetLastError());
   return LBM_OK;
@@ -1428,7 +1596,10 @@ extern "C" int lbm_nn_mix(int64_t n, const float *y, const float dir[3], float *
 extern "C" int lbm_nn_mix_backward(int64_t n, const void *dp, int32_t ldp, const float dir[3], void *dy, int32_t ldy,
                                    void *stream) {
   if (!dp || !dir || !dy || n < 0 || ldp < 4 || ldy < 12) return set_error(LBM_ERR_ARG, "lbm_nn_mix_backward: args");
-  hipLaunchKernelGGL(k_mix_backward, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
+  if (ldy % 8 || (uintptr_t)dy % 16) return set_error(LBM_ERR_ARG, "lbm_nn_mix_backward: dy rows need ldy % 8 == 0, 16-byte aligned");
+  if (n == 0) return LBM_OK;
+  if (n > (int64_t)INT32_MAX * 256) return set_error(LBM_ERR_SHAPE, "lbm_nn_mix_backward: too many nodes");
+  hipLaunchKernelGGL(k_mix_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), n,
                      static_cast<const bf16 *>(dp), ldp, dir[0], dir[1], dir[2], static_cast<bf16 *>(dy), ldy);
   NN_TRY(hipGetLastError());
   return LBM_OK;

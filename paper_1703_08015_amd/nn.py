@@ -18,6 +18,7 @@ class Gemm(ctypes.Structure):
         ("taps", ctypes.c_int32), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32),
         ("x", ctypes.c_void_p), ("ldx", ctypes.c_int32), ("w", ctypes.c_void_p), ("bias", ctypes.c_void_p),
         ("y", ctypes.c_void_p), ("ldy", ctypes.c_int32), ("y_fp32", ctypes.c_int32), ("relu", ctypes.c_int32),
+        ("gate_channels", ctypes.c_int32), ("gate", ctypes.c_void_p), ("ldg", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -90,11 +91,15 @@ def _gemm(src, dst, rows, taps, cin, cout, x, ldx, w, bias, y, ldy, y_fp32, relu
 
 
 def forward(src, dst, rows, taps, cin, cout, x, ldx, w, y, ldy, bias=None, y_fp32=False, relu=False, stream=None,
-            x_offset=0, y_offset=0):
-    """y = act(gather-GEMM(x, w) + bias); x_offset / y_offset are element
-    offsets into x and y (channel slices of wider rows)."""
+            x_offset=0, y_offset=0, gate=None, ldg=0, gate_channels=0, gate_offset=0):
+    """y = act(gather-GEMM(x, w) + bias); x_offset / y_offset / gate_offset
+    are element offsets into x, y and gate (channel slices of wider rows).
+    With a gate (BF16 rows of stride ldg on the output grid), the first
+    gate_channels output channels are zeroed where the gate is not > 0."""
     g = _gemm(src, dst, rows, taps, cin, cout, x.data_ptr() + 2 * x_offset, ldx, w.data_ptr(),
               None if bias is None else bias.data_ptr(), y.data_ptr() + y.element_size() * y_offset, ldy, y_fp32, relu)
+    if gate is not None:
+        g.gate, g.ldg, g.gate_channels = gate.data_ptr() + 2 * gate_offset, ldg, gate_channels
     _check(_lib().lbm_nn_forward(ctypes.byref(g), _stream(stream)), "lbm_nn_forward")
 
 

@@ -163,16 +163,18 @@ class UNet:
         return A["out"]
 
     # ---- backward ------------------------------------------------------------
-    def _conv_backward(self, rows, cin, cout, x, ldx, w, b, y, ldy, dy, lddy, dx, lddx, relu=True, need_dx=True,
-                       dy_offset=0, y_offset=0, x_offset=0):
-        n = rows[0] * rows[1] * rows[2]
-        if relu:
-            nn.relu_backward(n, cout, y, ldy, dy, lddy, y_offset=y_offset, dy_offset=dy_offset)
-        nn.wgrad(nn.CONV3, nn.IDENT, rows, 27, cin, cout, x, ldx, dy, lddy, w.g, b.g, x_offset=x_offset,
-                 dy_offset=dy_offset, ws=self._wgrad_ws(rows, cin, cout, ldx, lddy))
+    def _conv_backward(self, rows, cin, cout, x, ldx, w, b, dy, lddy, dx, lddx, need_dx=True, gate_ch=None):
+        """dy: the gradient of the layer's pre-activation (its ReLU derivative
+        already applied where dy was produced).  dx: the gradient of the
+        pre-activation of the layer that produced x, i.e. the backward-data
+        pass gated by x > 0 on x's first gate_ch (default: all) channels,
+        which are that layer's ReLU outputs."""
+        nn.wgrad(nn.CONV3, nn.IDENT, rows, 27, cin, cout, x, ldx, dy, lddy, w.g, b.g,
+                 ws=self._wgrad_ws(rows, cin, cout, ldx, lddy))
         if need_dx:
             wt = self._wt(w, nn.CONV3, 27, cin, cout)
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, x_offset=dy_offset)
+            nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, gate=x, ldg=ldx,
+                       gate_channels=cin if gate_ch is None else gate_ch)
 
     def _wgrad_ws(self, rows, cin, cout, ldx, lddy):
         """The shared workspace of the 3x3x3 weight gradients (partial sums
@@ -198,7 +200,10 @@ class UNet:
 
     def backward(self, dout):
         """dout: BF16 (nz, ny, nx, out_pad) gradient of the loss wrt the head
-        output (channels out_ch.. zero).  Accumulates parameter gradients."""
+        output (channels out_ch.. zero).  Accumulates parameter gradients.
+        Every backward-data pass writes the gradient of the pre-activation of
+        the layer below it (its ReLU derivative fused as a gate by the
+        forward activation), so no separate ReLU-backward pass runs."""
         t = self.torch
         _, A, grids = self._cache
         L, C = self.L, self.C
@@ -212,17 +217,18 @@ class UNet:
         nn.wgrad(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g)
         wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
         d_below = G["d2", 0] if L > 1 else G["cat", 0]
-        nn.forward(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow)
+        nn.forward(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
+                   gate=below, ldg=ldbelow, gate_channels=C[0])
         # decoder, top level first (reverse of the forward order)
         for k, l in enumerate(range(0, L - 1)):
             idx = L - 2 - l  # position of level l in self.up / self.dec
             rows, rows_c = self._rows(grids[l]), self._rows(grids[l + 1])
             uw, ub = self.up[idx]
             (w1, b1), (w2, b2) = self.dec[idx]
-            self._conv_backward(rows, C[l], C[l], A["d1", l], C[l], w2, b2, A["d2", l], C[l], G["d2", l], C[l],
-                                G["d1", l], C[l])
-            self._conv_backward(rows, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1, b1, A["d1", l], C[l], G["d1", l],
-                                C[l], G["cat", l], 2 * C[l])
+            self._conv_backward(rows, C[l], C[l], A["d1", l], C[l], w2, b2, G["d2", l], C[l], G["d1", l], C[l])
+            # the concat input: only its skip half [0, C) is a ReLU output
+            self._conv_backward(rows, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1, b1, G["d1", l], C[l], G["cat", l],
+                                2 * C[l], gate_ch=C[l])
             # transposed conv: input = level l+1 output (d2 of l+1, or the bottom cat buffer)
             if l + 1 == L - 1:
                 xin, ldxin, dxin = A["cat", L - 1], A["cat", L - 1].shape[-1], G["cat", L - 1]
@@ -232,23 +238,24 @@ class UNet:
                      dy_offset=C[l])
             wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
             nn.forward(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
-                       x_offset=C[l])
+                       x_offset=C[l], gate=xin, ldg=ldxin, gate_channels=C[l + 1])
         # encoder, bottom level first
         for l in range(L - 1, -1, -1):
             rows = self._rows(grids[l])
             (w1, b1), (w2, b2) = self.enc[l]
             width = A["cat", l].shape[-1]
-            self._conv_backward(rows, C[l], C[l], A["e1", l], C[l], w2, b2, A["cat", l], width, G["cat", l], width,
-                                G["e1", l], C[l])
+            self._conv_backward(rows, C[l], C[l], A["e1", l], C[l], w2, b2, G["cat", l], width, G["e1", l], C[l])
             if l > 0:
-                self._conv_backward(rows, C[l - 1], C[l], A["pool", l], C[l - 1], w1, b1, A["e1", l], C[l],
-                                    G["e1", l], C[l], G["pool", l], C[l - 1])
-                # pooled gradient joins the skip gradient already in the first half of cat[l-1]
+                # the pooled gradient is gated by the pooled value, which is the
+                # winning corner's ReLU output, before it joins the skip
+                # gradient already in the first half of cat[l-1]
+                self._conv_backward(rows, C[l - 1], C[l], A["pool", l], C[l - 1], w1, b1, G["e1", l], C[l],
+                                    G["pool", l], C[l - 1])
                 nn.maxpool2_backward(rows, C[l - 1], G["pool", l], C[l - 1], A["arg", l], G["cat", l - 1],
                                      2 * C[l - 1], accumulate=True)
             else:
-                self._conv_backward(rows, self.in_ch, C[0], self._x, self.in_ch, w1, b1, A["e1", 0], C[0], G["e1", 0],
-                                    C[0], None, 0, need_dx=False)
+                self._conv_backward(rows, self.in_ch, C[0], self._x, self.in_ch, w1, b1, G["e1", 0], C[0], None, 0,
+                                    need_dx=False)
 
     def _grads(self, A, grids):
         t = self.torch

@@ -254,6 +254,73 @@ def test_maxpool_relu_mse_adam(torch):
     assert np.array_equal(host(p16), bf(host(P)))
 
 
+@pytest.mark.parametrize("channels,ld,off", [(24, 48, 0), (24, 48, 24), (16, 16, 0), (12, 12, 0), (8, 20, 4)])
+def test_pool_and_relu_paths(torch, channels, ld, off):
+    """Max pooling, its backward and the ReLU backward on both kernel forms:
+    whole 16-byte channel groups (channels, row stride and offset multiples of
+    8) and the element-wise fallback (12 channels; stride 20).  Inputs are
+    ReLU outputs, so ties at 0 are common: the first corner wins, as in the
+    oracle, and the results are exact."""
+    coarse = (3, 5, 4)
+    fine = tuple(2 * v for v in coarse)
+    xf = np.zeros(fine + (ld,))
+    xf[..., off:off + channels] = np.maximum(bf(rng.normal(size=fine + (channels,))), 0.0)
+    y = torch.zeros(coarse + (channels,), dtype=torch.bfloat16, device="cuda")
+    arg = torch.empty(coarse + (channels,), dtype=torch.uint8, device="cuda")
+    nn.maxpool2(rows_of(coarse), channels, dev(torch, xf), ld, y, channels, arg, x_offset=off)
+    wy, warg = onn.maxpool2(xf[..., off:off + channels])
+    assert np.array_equal(host(y), wy) and np.array_equal(arg.cpu().numpy(), warg)
+    dy = bf(rng.normal(size=coarse + (channels,)))
+    base = bf(rng.normal(size=fine + (ld,)))
+    dx = dev(torch, base)
+    nn.maxpool2_backward(rows_of(coarse), channels, dev(torch, dy), channels, arg, dx, ld, accumulate=True,
+                         dx_offset=off)
+    want = base.copy()
+    want[..., off:off + channels] = bf(base[..., off:off + channels] + onn.maxpool2_backward(warg, dy))
+    assert np.array_equal(host(dx), want)
+    g = bf(rng.normal(size=fine + (ld,)))
+    gd = dev(torch, g)
+    n = int(np.prod(fine))
+    nn.relu_backward(n, channels, dev(torch, xf), ld, gd, ld, y_offset=off, dy_offset=off)
+    want = g.copy()
+    want[..., off:off + channels] = onn.relu_backward(xf[..., off:off + channels], g[..., off:off + channels])
+    assert np.array_equal(host(gd), want)
+
+
+@pytest.mark.parametrize("src,grid,taps,cin,cout,gate_ch,ldg,goff", [
+    (nn.CONV3, (4, 5, 6), 27, 24, 48, 24, 48, 0),     # generic kernel, the skip half of a concat gradient
+    (nn.CONV3, (4, 5, 6), 27, 16, 24, 24, 32, 8),     # generic kernel, gate rows wider than the output
+    (nn.IDENT, (4, 5, 6), 1, 16, 24, 24, 24, 0),      # 1x1 (the head's backward-data pass)
+    (nn.GATHER2, (2, 3, 3), 8, 24, 48, 48, 48, 0),    # a transposed conv's backward-data pass
+    (nn.CONV3, (32, 36, 68), 27, 24, 24, 24, 24, 0),  # brick kernel, partial bricks
+    (nn.CONV3, (32, 32, 64), 27, 48, 48, 24, 48, 0),  # brick kernel, gate on half the channels
+])
+def test_gate_equals_relu_backward(torch, src, grid, taps, cin, cout, gate_ch, ldg, goff):
+    """A gated forward pass writes exactly what the ungated pass followed by
+    lbm_nn_relu_backward on its first gate_ch channels writes (bit for bit):
+    the fused ReLU derivative of the backward-data passes."""
+    fine = tuple(2 * v for v in grid) if src == nn.GATHER2 else grid
+    x = bf(rng.normal(size=fine + (cin,)))
+    w = bf(rng.normal(size=(cout, taps, cin)) * 0.1)
+    gate = bf(rng.normal(size=grid + (ldg,)))
+    gate[..., goff] = 0.0  # exact zeros close the gate too
+    y0 = torch.empty(grid + (cout,), dtype=torch.bfloat16, device="cuda")
+    y1 = torch.empty_like(y0)
+    X, W, Gt = dev(torch, x), dev(torch, w), dev(torch, gate)
+    nn.forward(src, nn.IDENT, rows_of(grid), taps, cin, cout, X, cin, W, y0, cout)
+    nn.forward(src, nn.IDENT, rows_of(grid), taps, cin, cout, X, cin, W, y1, cout, gate=Gt, ldg=ldg,
+               gate_channels=gate_ch, gate_offset=goff)
+    n = int(np.prod(grid))
+    nn.relu_backward(n, gate_ch, Gt, ldg, y0, cout, y_offset=goff)
+    torch.cuda.synchronize()
+    a, b = y0.cpu(), y1.cpu()
+    assert torch.equal(a.view(torch.int16), b.view(torch.int16))
+    assert (host(y1)[..., :gate_ch][gate[..., goff:goff + gate_ch] <= 0] == 0).all()
+    with pytest.raises(nn.LbmError):
+        nn.forward(src, nn.IDENT, rows_of(grid), taps, cin, cout, X, cin, W, y1, cout, gate=Gt, ldg=ldg,
+                   gate_channels=cout + 8)
+
+
 def test_force_mix(torch):
     y = rng.normal(size=(30, 12)).astype(np.float32)
     d = np.array([0.36, -0.48, 0.8])
