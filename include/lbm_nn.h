@@ -79,16 +79,16 @@ int lbm_nn_forward(const lbm_nn_gemm *g, void *stream);
  * one); at most 2048 output channels then (else LBM_ERR_SHAPE). */
 int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream);
 
-/* lbm_nn_wgrad with a caller workspace for the 3x3x3 weight gradient of large
- * grids (at least 2048 bricks of 8x4x4 voxels): each block writes its partial
- * sums there and a second kernel adds the blocks in a fixed order, instead of
- * one FP32 atomic per weight and block (same result to rounding, identical
- * from run to run).  ws: device FP32, at least lbm_nn_wgrad_workspace(g)
- * floats, overwritten; ws may be NULL (then atomics).  LBM_ERR_ARG if
- * ws_floats is too small. */
+/* lbm_nn_wgrad with a caller workspace: each block of the weight-gradient
+ * kernel writes its partial sums there and a second kernel adds the blocks in
+ * a fixed order, instead of one FP32 atomic per weight and block (same result
+ * to rounding, identical from run to run, and no atomic contention).  With a
+ * workspace the 3x3x3 weight gradient also takes its brick kernel on smaller
+ * grids.  ws: device FP32, at least lbm_nn_wgrad_workspace(g) floats,
+ * overwritten; ws may be NULL (then atomics).  LBM_ERR_ARG if ws_floats is too
+ * small. */
 int lbm_nn_wgrad_ws(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int64_t ws_floats, void *stream);
-/* Workspace floats lbm_nn_wgrad_ws needs for g (0 when the layer does not use
- * one); -1 for an invalid g. */
+/* Workspace floats lbm_nn_wgrad_ws needs for g; -1 for an invalid g. */
 int64_t lbm_nn_wgrad_workspace(const lbm_nn_gemm *g);
 
 /* Weights of the backward-data pass of a layer, so that lbm_nn_forward with

@@ -73,7 +73,8 @@ __device__ __forceinline__ int64_t dst_voxel(int64_t m, int t, const Grid &rows,
   if constexpr (DST == LBM_NN_IDENT) {
     return m;
   } else {
-    const int x = (int)(m % rows.nx), y = (int)((m / rows.nx) % rows.ny), z = (int)(m / ((int64_t)rows.nx * rows.ny));
+    const int mi = (int)m;  // rows are checked to number fewer than 2^31
+    const int x = mi % rows.nx, y = (mi / rows.nx) % rows.ny, z = mi / (rows.nx * rows.ny);
     return vidx(2 * x + (t & 1), 2 * y + ((t >> 1) & 1), 2 * z + (t >> 2), out);
   }
 }
@@ -108,15 +109,18 @@ __device__ __forceinline__ int64_t gather_row(int x, int y, int z, int64_t m, in
 
 template <int SRC, int DST, int NW, int RF, bool F32, bool RELU>
 __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
-  __shared__ __attribute__((aligned(16))) bf16 sb[2][16 * NW][kLdsK];
+  // LDS: the weight tiles during the K loop; for BF16 outputs the C tile
+  // [64*RF rows][16*NW + 8] afterwards, so that each thread stores whole
+  // 16-byte channel groups of one output row
+  constexpr int OS = 16 * NW + 8;
+  constexpr int kSb = 2 * 16 * NW * kLdsK, kOt = F32 ? 0 : 64 * RF * OS;
+  __shared__ __attribute__((aligned(16))) bf16 lds[kSb > kOt ? kSb : kOt];
+  auto sb = [&](int buf, int row) { return lds + (buf * 16 * NW + row) * kLdsK; };
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, kb = lane >> 4;
   const int64_t mb = (int64_t)blockIdx.x * (64 * RF) + wv * 16 * RF;
   const int n0 = blockIdx.y * 16 * NW;
-  const int tfix = blockIdx.z;  // the tap of a SCATTER2 launch
   const int ktot = a.taps * a.cin;
-  const int kbeg = DST == LBM_NN_SCATTER2 ? tfix * a.cin : 0;
-  const int kend = DST == LBM_NN_SCATTER2 ? kbeg + a.cin : ktot;
 
   int64_t m[RF];
   bool mv[RF];
@@ -134,85 +138,127 @@ __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
     }
   }
 
-  // weight staging: thread -> (column, 8-wide k group)
-  const int scol = tid >> 2, sk = 8 * (tid & 3);
-  auto stage = [&](int buf, int k0) {
-    if (scol < 16 * NW) {
-      const int n = n0 + scol, k = k0 + sk;
-      bf16x8 v = {};
-      if (n < a.cout && k < kend) v = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)n * ktot + k);
-      *reinterpret_cast<bf16x8 *>(&sb[buf][scol][sk]) = v;
-    }
-  };
+  // A SCATTER2 block computes all 8 taps of its rows in turn: the taps' fine
+  // output voxels interleave, so one block writes whole runs of output rows.
+  constexpr int NT = DST == LBM_NN_SCATTER2 ? 8 : 1;
+  for (int tfix = 0; tfix < NT; ++tfix) {
+    const int kbeg = DST == LBM_NN_SCATTER2 ? tfix * a.cin : 0;
+    const int kend = DST == LBM_NN_SCATTER2 ? kbeg + a.cin : ktot;
 
-  // this lane's k group kk = k0 + 8*kb as (tap t, channel c); each load
-  // advances it by one 32-wide K step (zeros past the end)
-  int kk = kbeg + 8 * kb;
-  int t = kk / a.cin, c = kk - t * a.cin;
-  auto load_rows = [&](bf16x8(&dst)[RF]) {
-#pragma unroll
-    for (int f = 0; f < RF; ++f) {
-      dst[f] = bf16x8{};
-      if (mv[f] && kk < kend)
-        dst[f] = *reinterpret_cast<const bf16x8 *>(a.x + gather_row<SRC>(px[f], py[f], pz[f], m[f], t, a.in_grid) *
-                                                             a.ldx + c);
-    }
-    kk += 32;
-    c += 32;
-    while (c >= a.cin) {
-      c -= a.cin;
-      ++t;
-    }
-  };
-
-  f32x4 acc[RF][NW];
-#pragma unroll
-  for (int f = 0; f < RF; ++f)
-#pragma unroll
-    for (int j = 0; j < NW; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  bf16x8 cur[RF];
-  load_rows(cur);
-  stage(0, kbeg);
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    if (k0 + 32 < kend) stage(buf ^ 1, k0 + 32);
-    bf16x8 nxt[RF];
-    load_rows(nxt);
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sb[buf][16 * j + r][8 * kb]);
-#pragma unroll
-      for (int f = 0; f < RF; ++f) acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[f], bv, acc[f][j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int f = 0; f < RF; ++f) cur[f] = nxt[f];
-    __syncthreads();
-    buf ^= 1;
-  }
-
-#pragma unroll
-  for (int f = 0; f < RF; ++f) {
-#pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const int n = n0 + 16 * j + r;
-      if (n >= a.cout) continue;
-      const float bias = a.bias ? a.bias[n] : 0.f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t mo = mb + 16 * f + 4 * kb + i;
-        if (mo >= a.M) continue;
-        float v = acc[f][j][i] + bias;
-        if (RELU) v = fmaxf(v, 0.f);
-        const int64_t dv = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid);
-        if (n < a.gate_ch && !gate_open(a.gate[dv * a.ldg + n])) v = 0.f;
-        const int64_t d = dv * a.ldy + n;
-        if (F32)
-          static_cast<float *>(a.y)[d] = v;
-        else
-          static_cast<bf16 *>(a.y)[d] = (bf16)v;
+    // weight staging: thread -> (column, 8-wide k group)
+    const int scol = tid >> 2, sk = 8 * (tid & 3);
+    auto stage = [&](int buf, int k0) {
+      if (scol < 16 * NW) {
+        const int n = n0 + scol, k = k0 + sk;
+        bf16x8 v = {};
+        if (n < a.cout && k < kend) v = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)n * ktot + k);
+        *reinterpret_cast<bf16x8 *>(sb(buf, scol) + sk) = v;
       }
+    };
+
+    // this lane's k group kk = k0 + 8*kb as (tap t, channel c); each load
+    // advances it by one 32-wide K step (zeros past the end)
+    int kk = kbeg + 8 * kb;
+    int t = kk / a.cin, c = kk - t * a.cin;
+    auto load_rows = [&](bf16x8(&dst)[RF]) {
+#pragma unroll
+      for (int f = 0; f < RF; ++f) {
+        dst[f] = bf16x8{};
+        if (mv[f] && kk < kend)
+          dst[f] = *reinterpret_cast<const bf16x8 *>(a.x + gather_row<SRC>(px[f], py[f], pz[f], m[f], t, a.in_grid) *
+                                                               a.ldx + c);
+      }
+      kk += 32;
+      c += 32;
+      while (c >= a.cin) {
+        c -= a.cin;
+        ++t;
+      }
+    };
+
+    f32x4 acc[RF][NW];
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+      for (int j = 0; j < NW; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    bf16x8 cur[RF];
+    load_rows(cur);
+    stage(0, kbeg);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+      if (k0 + 32 < kend) stage(buf ^ 1, k0 + 32);
+      bf16x8 nxt[RF];
+      load_rows(nxt);
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(sb(buf, 16 * j + r) + 8 * kb);
+#pragma unroll
+        for (int f = 0; f < RF; ++f) acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur[f], bv, acc[f][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int f = 0; f < RF; ++f) cur[f] = nxt[f];
+      __syncthreads();  // (after the last step: every wavefront's weight reads are done)
+      buf ^= 1;
+    }
+
+    if constexpr (F32) {
+      // FP32 rows (the network's head): one element per lane and row
+#pragma unroll
+      for (int f = 0; f < RF; ++f) {
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+          const int n = n0 + 16 * j + r;
+          if (n >= a.cout) continue;
+          const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t mo = mb + 16 * f + 4 * kb + i;
+            if (mo >= a.M) continue;
+            float v = acc[f][j][i] + bias;
+            if (RELU) v = fmaxf(v, 0.f);
+            const int64_t dv = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid);
+            if (n < a.gate_ch && !gate_open(a.gate[dv * a.ldg + n])) v = 0.f;
+            static_cast<float *>(a.y)[dv * a.ldy + n] = v;
+          }
+        }
+      }
+    } else {
+      // bias and ReLU, then the tile goes through LDS as [row][channel]
+      bf16 *ot = lds;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int n = n0 + 16 * j + r;
+        const float bias = (a.bias && n < a.cout) ? a.bias[n] : 0.f;
+#pragma unroll
+        for (int f = 0; f < RF; ++f)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = acc[f][j][i] + bias;
+            if (RELU) v = fmaxf(v, 0.f);
+            ot[(wv * 16 * RF + 16 * f + 4 * kb + i) * OS + 16 * j + r] = (bf16)v;
+          }
+      }
+      __syncthreads();
+      // thread -> (row, 8-channel group); consecutive threads take consecutive
+      // groups of one row, then the next row
+      for (int e = tid; e < 64 * RF * 2 * NW; e += 256) {
+        const int rl = e / (2 * NW), q = e % (2 * NW);
+        const int64_t mo = (int64_t)blockIdx.x * (64 * RF) + rl;
+        const int n = n0 + 8 * q;
+        if (mo >= a.M || n >= a.cout) continue;
+        bf16x8 o = *reinterpret_cast<const bf16x8 *>(ot + rl * OS + 8 * q);
+        const int64_t dv = dst_voxel<DST>(mo, tfix, a.rows, a.out_grid);
+        if (n < a.gate_ch) {  // whole 8-channel groups (gate_ch is a multiple of 8)
+          const bf16x8 gv = *reinterpret_cast<const bf16x8 *>(a.gate + dv * a.ldg + n);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (!gate_open(gv[u])) o[u] = (bf16)0.f;
+        }
+        *reinterpret_cast<bf16x8 *>(static_cast<bf16 *>(a.y) + dv * a.ldy + n) = o;
+      }
+      __syncthreads();  // the tile's reads are done before LDS takes weights again
     }
   }
 }
@@ -497,7 +543,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the wave, so only wave-level synchronisation), and the next iteration's
 // rows are loaded into registers while the current MFMAs run.
 template <int SRC, int DST, int CF, int NF>
-__global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks) {
+__global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks, float *ws) {
   __shared__ __attribute__((aligned(16))) bf16 sx[4][16 * CF][32 + kWgradPad];
   __shared__ __attribute__((aligned(16))) bf16 sy[4][16 * NF][32 + kWgradPad];
   __shared__ float red[4][16 * CF][16 * NF + 1];
@@ -568,12 +614,21 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wv][16 * i + 4 * kb + q][16 * j + r] = acc[i][j][q];
   __syncthreads();
+  // the block's sums: with a workspace into its own slot [16*CF][16*NF] (slots
+  // ordered [tile = (nb, cb, t)][chunk]; k_wgrad_sum adds the chunks in a fixed
+  // order), else one FP32 atomic add per weight
   const int ktot = a.taps * a.cin;
+  float *slot = ws ? ws + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * (256 * CF * NF)
+                   : nullptr;
   for (int e = threadIdx.x; e < 256 * CF * NF; e += 256) {
     const int cl = e / (16 * NF), nl = e % (16 * NF);
+    const float s = red[0][cl][nl] + red[1][cl][nl] + red[2][cl][nl] + red[3][cl][nl];
+    if (slot) {
+      slot[e] = s;
+      continue;
+    }
     const int c = cbase + cl, n = nbase + nl;
     if (c >= a.cin || n >= a.cout) continue;
-    const float s = red[0][cl][nl] + red[1][cl][nl] + red[2][cl][nl] + red[3][cl][nl];
     atomicAdd(dw + (int64_t)n * ktot + (int64_t)t * a.cin + c, s);
   }
 }
@@ -755,15 +810,18 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
   }
 }
 
-// dw += the sum over the blocks of one channel tile of their partial slots,
-// in two passes with a fixed order (run to run identical).  Pass 1: thread
-// (e, part) sums the slots of blocks part*per .. part*per + per - 1 with eight
-// independent partial sums (eight loads in flight) and writes the total into
-// the first of those slots, which only it reads.  Pass 2 (parts = 0): thread e
-// adds the parts' totals in order into dw.  e = (t * 16*CF + cl) * 16*NF + nl.
+// dw += the sum over the blocks of one tile of their partial slots, in two
+// passes with a fixed order (run to run identical).  A slot holds slot_taps
+// taps x [16*cf][16*nf]: all 27 taps for the brick kernel (tiles = channel
+// tiles cb + cblocks * nb), one tap for k_wgrad (tiles = t + taps * (cb +
+// cblocks * nb)).  Pass 1: thread (e, part) sums the slots of blocks
+// part*per .. part*per + per - 1 with eight independent partial sums (eight
+// loads in flight) and writes the total into the first of those slots, which
+// only it reads.  Pass 2: thread e adds the parts' totals in order into dw.
 __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int blocks, int per, int cf, int nf,
-                                                   int cblocks, int cin, int cout, float *dw, int pass) {
-  const int E = 27 * 256 * cf * nf;
+                                                   int cblocks, int slot_taps, int taps, int cin, int cout, float *dw,
+                                                   int pass) {
+  const int E = slot_taps * 256 * cf * nf;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= E) return;
   const int parts = (blocks + per - 1) / per;
@@ -781,13 +839,26 @@ __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int b
     return;
   }
   const int tile = blockIdx.y;
-  const int nl = e % (16 * nf), cl = (e / (16 * nf)) % (16 * cf), t = e / (256 * cf * nf);
-  const int c = (tile % cblocks) * 16 * cf + cl, n = (tile / cblocks) * 16 * nf + nl;
+  const int nl = e % (16 * nf), cl = (e / (16 * nf)) % (16 * cf), ts = e / (256 * cf * nf);
+  const int ct = slot_taps == taps ? tile : tile / taps;  // channel tile cb + cblocks * nb
+  const int t = slot_taps == taps ? ts : tile % taps;
+  const int c = (ct % cblocks) * 16 * cf + cl, n = (ct / cblocks) * 16 * nf + nl;
   if (c >= cin || n >= cout) return;
   const float *p = ws + (int64_t)tile * blocks * E + e;
   float sum = 0.f;
   for (int q = 0; q < parts; ++q) sum += p[(int64_t)q * per * E];
-  dw[((int64_t)n * 27 + t) * cin + c] += sum;
+  dw[((int64_t)n * taps + t) * cin + c] += sum;
+}
+
+// both passes of k_wgrad_sum over `tiles` tiles of `blocks` slots each
+hipError_t launch_wgrad_sum(float *ws, int64_t blocks, int64_t tiles, int cf, int nf, int cblocks, int slot_taps,
+                            int taps, int cin, int cout, float *dw, hipStream_t s) {
+  const int E = slot_taps * 256 * cf * nf, per = 32, parts = (int)((blocks + per - 1) / per);
+  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)(tiles * parts)), dim3(256), 0, s, ws,
+                     (int)blocks, per, cf, nf, cblocks, slot_taps, taps, cin, cout, dw, 1);
+  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,
+                     (int)blocks, per, cf, nf, cblocks, slot_taps, taps, cin, cout, dw, 2);
+  return hipGetLastError();
 }
 
 // bias gradient: db[n] += sum over rows of dy[row][n], a column sum of a
@@ -1230,14 +1301,14 @@ hipError_t launch_fwd_rf(const GemmArgs &a, int nw, dim3 grid, hipStream_t s) {
 }
 
 template <int SRC, int DST, bool F32, bool RELU>
-hipError_t launch_fwd(const GemmArgs &a, int scatter_taps, hipStream_t s) {
+hipError_t launch_fwd(const GemmArgs &a, hipStream_t s) {
   const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
   const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
   // 256 rows per block where that still gives the device >= 512 blocks, else 64
-  const int64_t big = (a.M + 255) / 256 * gy * scatter_taps;
+  const int64_t big = (a.M + 255) / 256 * gy;
   if (big >= 512)
-    return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy, scatter_taps), s);
-  return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy, scatter_taps), s);
+    return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy), s);
+  return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy), s);
 }
 
 template <int NW, int CC>
@@ -1274,6 +1345,8 @@ bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t
   else
     return false;
   const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
+  // the halo's periodic wrap needs the grid to be at least one brick along every axis
+  if (a.rows.nx < kBrickX || a.rows.ny < kBrickY || a.rows.nz < kBrickZ) return false;
   const int64_t bricks = (int64_t)((a.rows.nx + kBrickX - 1) / kBrickX) * ((a.rows.ny + kBrickY - 1) / kBrickY) *
                          ((a.rows.nz + kBrickZ - 1) / kBrickZ);
   const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
@@ -1289,29 +1362,56 @@ bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t
 }
 
 template <int SRC, int DST>
-hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, int st, hipStream_t s) {
+hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, hipStream_t s) {
   if constexpr (SRC == LBM_NN_CONV3 && DST == LBM_NN_IDENT) {
     hipError_t e = hipSuccess;
     if (try_brick(a, f32, relu, s, &e)) return e;
   }
-  if (f32) return relu ? launch_fwd<SRC, DST, true, true>(a, st, s) : launch_fwd<SRC, DST, true, false>(a, st, s);
-  return relu ? launch_fwd<SRC, DST, false, true>(a, st, s) : launch_fwd<SRC, DST, false, false>(a, st, s);
+  if (f32) return relu ? launch_fwd<SRC, DST, true, true>(a, s) : launch_fwd<SRC, DST, true, false>(a, s);
+  return relu ? launch_fwd<SRC, DST, false, true>(a, s) : launch_fwd<SRC, DST, false, false>(a, s);
 }
 
-template <int SRC, int DST, int CF, int NF>
-hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, hipStream_t s) {
-  const int cblocks = (a.cin + 16 * CF - 1) / (16 * CF), nblocks = (a.cout + 16 * NF - 1) / (16 * NF);
-  const int64_t other = (int64_t)a.taps * cblocks * nblocks;
+// Grid of k_wgrad: (voxel chunks, taps * cblocks, nblocks), about 2048 blocks
+// with chunks of a multiple of 128 voxels.
+struct GenericWgradGrid {
+  int cblocks, nblocks;
+  int64_t chunk, chunks;
+};
+GenericWgradGrid generic_wgrad_grid(const GemmArgs &a, int cf, int nf) {
+  GenericWgradGrid w;
+  w.cblocks = (a.cin + 16 * cf - 1) / (16 * cf);
+  w.nblocks = (a.cout + 16 * nf - 1) / (16 * nf);
+  const int64_t other = (int64_t)a.taps * w.cblocks * w.nblocks;
   int64_t chunks = (2048 + other - 1) / other;
   const int64_t max_chunks = (a.M + 127) / 128;
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;
   int64_t chunk = (a.M + chunks - 1) / chunks;
-  chunk = (chunk + 127) / 128 * 128;
-  chunks = (a.M + chunk - 1) / chunk;
-  hipLaunchKernelGGL((k_wgrad<SRC, DST, CF, NF>), dim3((unsigned)chunks, (unsigned)(a.taps * cblocks), (unsigned)nblocks),
-                     dim3(256), 0, s, a, dw, chunk, cblocks);
-  return hipGetLastError();
+  w.chunk = (chunk + 127) / 128 * 128;
+  w.chunks = (a.M + w.chunk - 1) / w.chunk;
+  return w;
+}
+void generic_wgrad_frags(const GemmArgs &a, int *cf, int *nf) {
+  *cf = a.cin <= 16 ? 1 : 2;
+  *nf = a.cout <= 16 ? 1 : 2;
+}
+int64_t generic_wgrad_ws_floats(const GemmArgs &a) {
+  int cf, nf;
+  generic_wgrad_frags(a, &cf, &nf);
+  const GenericWgradGrid w = generic_wgrad_grid(a, cf, nf);
+  return w.chunks * a.taps * w.cblocks * w.nblocks * 256 * cf * nf;
+}
+
+template <int SRC, int DST, int CF, int NF>
+hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+  const GenericWgradGrid w = generic_wgrad_grid(a, CF, NF);
+  hipLaunchKernelGGL((k_wgrad<SRC, DST, CF, NF>), dim3((unsigned)w.chunks, (unsigned)(a.taps * w.cblocks),
+                                                       (unsigned)w.nblocks),
+                     dim3(256), 0, s, a, dw, w.chunk, w.cblocks, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ws) return e;
+  return launch_wgrad_sum(ws, w.chunks, (int64_t)a.taps * w.cblocks * w.nblocks, CF, NF, w.cblocks, 1, a.taps, a.cin,
+                          a.cout, dw, s);
 }
 
 // Grid of the brick weight gradient: about two blocks per compute unit in
@@ -1345,12 +1445,7 @@ hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, hipStr
                      (int)w.per, w.cblocks, ws);
   e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
-  const int E = 27 * 256 * CF * NF, per = 32, parts = (int)((w.gx + per - 1) / per);
-  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)(tiles * parts)), dim3(256), 0, s, ws,
-                     (int)w.gx, per, CF, NF, w.cblocks, a.cin, a.cout, dw, 1);
-  hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,
-                     (int)w.gx, per, CF, NF, w.cblocks, a.cin, a.cout, dw, 2);
-  return hipGetLastError();
+  return launch_wgrad_sum(ws, w.gx, tiles, CF, NF, w.cblocks, 27, 27, a.cin, a.cout, dw, s);
 }
 
 // channel tile width (in 16-channel fragments, 1..3) that pads c channels least
@@ -1363,21 +1458,30 @@ int wgrad_frags(int c, int max_frags) {
   return best;
 }
 
-// The brick weight gradient for 3x3x3 convolutions on grids of at least
-// 2048 bricks (64^3 and up).
-bool wgrad_brick_applies(const GemmArgs &a) {
-  const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
-                          ((a.rows.nz + kWbZ - 1) / kWbZ);
-  return nbricks >= 2048;
-}
 void wgrad_brick_frags(const GemmArgs &a, int *cf, int *nf) {
   *cf = wgrad_frags(a.cin, 3);
   *nf = wgrad_frags(a.cout, *cf == 3 ? 2 : 3);
 }
+
+// The brick weight gradient for 3x3x3 convolutions: with a workspace on any
+// grid that gives at least 128 (brick run, channel tile) blocks, without one
+// (FP32 atomics, whose contention grows with the block count) on grids of at
+// least 2048 bricks of 8x4x4.  The halo's periodic wrap needs the grid to be
+// at least one brick along every axis.
+bool wgrad_brick_applies(const GemmArgs &a, bool with_ws) {
+  if (a.rows.nx < kWbX || a.rows.ny < kWbY || a.rows.nz < kWbZ) return false;
+  const int64_t nbricks = (int64_t)((a.rows.nx + kWbX - 1) / kWbX) * ((a.rows.ny + kWbY - 1) / kWbY) *
+                          ((a.rows.nz + kWbZ - 1) / kWbZ);
+  if (!with_ws) return nbricks >= 2048;
+  int cf, nf;
+  wgrad_brick_frags(a, &cf, &nf);
+  const WgradGrid w = wgrad_grid(a, cf, nf);
+  return w.gx * w.cblocks * w.nblocks >= 128;
+}
 // Workspace floats the brick weight gradient's partial sums need (0 when the
 // brick kernel does not apply).
 int64_t wgrad_brick_ws_floats(const GemmArgs &a) {
-  if (!wgrad_brick_applies(a)) return 0;
+  if (!wgrad_brick_applies(a, true)) return 0;
   int cf, nf;
   wgrad_brick_frags(a, &cf, &nf);
   const WgradGrid w = wgrad_grid(a, cf, nf);
@@ -1387,7 +1491,7 @@ int64_t wgrad_brick_ws_floats(const GemmArgs &a) {
 // Runs the brick weight gradient if it applies (returns false to use k_wgrad
 // instead); ws: partial sums (wgrad_brick_ws_floats) or NULL for atomics.
 bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, hipStream_t s, hipError_t *err) {
-  if (!wgrad_brick_applies(a)) return false;
+  if (!wgrad_brick_applies(a, ws != nullptr)) return false;
   int cf, nf;
   wgrad_brick_frags(a, &cf, &nf);
   switch (cf * 4 + nf) {
@@ -1404,12 +1508,20 @@ bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, hipStream_t s, hip
 }
 
 template <int SRC, int DST>
-hipError_t launch_wgrad(const GemmArgs &a, float *dw, hipStream_t s) {
-  const int cf = a.cin <= 16 ? 1 : 2, nf = a.cout <= 16 ? 1 : 2;
-  if (cf == 1 && nf == 1) return launch_wgrad_cf<SRC, DST, 1, 1>(a, dw, s);
-  if (cf == 1) return launch_wgrad_cf<SRC, DST, 1, 2>(a, dw, s);
-  if (nf == 1) return launch_wgrad_cf<SRC, DST, 2, 1>(a, dw, s);
-  return launch_wgrad_cf<SRC, DST, 2, 2>(a, dw, s);
+hipError_t launch_wgrad(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+  int cf, nf;
+  generic_wgrad_frags(a, &cf, &nf);
+  if (cf == 1 && nf == 1) return launch_wgrad_cf<SRC, DST, 1, 1>(a, dw, ws, s);
+  if (cf == 1) return launch_wgrad_cf<SRC, DST, 1, 2>(a, dw, ws, s);
+  if (nf == 1) return launch_wgrad_cf<SRC, DST, 2, 1>(a, dw, ws, s);
+  return launch_wgrad_cf<SRC, DST, 2, 2>(a, dw, ws, s);
+}
+
+// workspace floats of lbm_nn_wgrad_ws for a layer (the brick kernel's where it applies)
+int64_t wgrad_ws_floats(const lbm_nn_gemm *g, const GemmArgs &a) {
+  if (g->src_mode == LBM_NN_CONV3 && g->dst_mode == LBM_NN_IDENT && wgrad_brick_applies(a, true))
+    return wgrad_brick_ws_floats(a);
+  return generic_wgrad_ws_floats(a);
 }
 
 }  // namespace
@@ -1426,13 +1538,13 @@ extern "C" int lbm_nn_forward(const lbm_nn_gemm *g, void *stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool f32 = g->y_fp32 != 0, relu = g->relu != 0;
   if (g->dst_mode == LBM_NN_SCATTER2) {
-    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, f32, relu, 8, s)));
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, f32, relu, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
-    NN_TRY((fwd_act<LBM_NN_CONV3, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+    NN_TRY((fwd_act<LBM_NN_CONV3, LBM_NN_IDENT>(a, f32, relu, s)));
   } else if (g->src_mode == LBM_NN_GATHER2) {
-    NN_TRY((fwd_act<LBM_NN_GATHER2, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+    NN_TRY((fwd_act<LBM_NN_GATHER2, LBM_NN_IDENT>(a, f32, relu, s)));
   } else {
-    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_IDENT>(a, f32, relu, 1, s)));
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_IDENT>(a, f32, relu, s)));
   }
   return LBM_OK;
 }
@@ -1443,8 +1555,7 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
   if (rc) return rc;
   if (!dw) return set_error(LBM_ERR_ARG, "lbm_nn_wgrad: NULL dw");
   if (ws) {
-    const int64_t need =
-        (g->src_mode == LBM_NN_CONV3 && g->dst_mode == LBM_NN_IDENT) ? wgrad_brick_ws_floats(to_args(g)) : 0;
+    const int64_t need = wgrad_ws_floats(g, to_args(g));
     if (ws_floats < need)
       return set_error(LBM_ERR_ARG, "lbm_nn_wgrad_ws: workspace of %lld floats, %lld needed", (long long)ws_floats,
                        (long long)need);
@@ -1453,22 +1564,22 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
   const GemmArgs a = to_args(g);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (g->dst_mode == LBM_NN_SCATTER2) {
-    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, s)));
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, ws, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
     hipError_t e = hipSuccess;
-    if (!try_wgrad_brick(a, dw, ws, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, s);
+    if (!try_wgrad_brick(a, dw, ws, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, s);
     NN_TRY(e);
   } else if (g->src_mode == LBM_NN_GATHER2) {
-    NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, s)));
+    NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, ws, s)));
   } else {
-    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, s)));
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, ws, s)));
   }
   if (db) {
     // all output voxels: M rows, or M * 8 fine voxels of a 2x2x2 transposed convolution
     const int64_t rows = g->dst_mode == LBM_NN_SCATTER2 ? (int64_t)a.out_grid.nx * a.out_grid.ny * a.out_grid.nz : a.M;
-    // about 2048 blocks (each block's rows: at least 256, so that its row
-    // lanes have several rows each on small grids)
-    int64_t chunk = (rows + 2047) / 2048;
+    // about 512 blocks (fewer atomic adds on the same channels; each block
+    // keeps four rows' loads in flight per lane) of at least 256 rows
+    int64_t chunk = (rows + 511) / 512;
     if (chunk < 256) chunk = 256;
     const unsigned gx = (unsigned)((rows + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_colsum, dim3(gx), dim3(256), 0, s, static_cast<const bf16 *>(a.y), rows, a.ldy, a.cout, db,
@@ -1484,8 +1595,7 @@ extern "C" int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *st
 
 extern "C" int64_t lbm_nn_wgrad_workspace(const lbm_nn_gemm *g) {
   if (check_gemm(g, true)) return -1;
-  if (g->src_mode != LBM_NN_CONV3 || g->dst_mode != LBM_NN_IDENT) return 0;
-  return wgrad_brick_ws_floats(to_args(g));
+  return wgrad_ws_floats(g, to_args(g));
 }
 
 extern "C" int lbm_nn_wgrad_ws(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int64_t ws_floats,

@@ -170,17 +170,17 @@ class UNet:
         pass gated by x > 0 on x's first gate_ch (default: all) channels,
         which are that layer's ReLU outputs."""
         nn.wgrad(nn.CONV3, nn.IDENT, rows, 27, cin, cout, x, ldx, dy, lddy, w.g, b.g,
-                 ws=self._wgrad_ws(rows, cin, cout, ldx, lddy))
+                 ws=self._wgrad_ws(nn.CONV3, nn.IDENT, rows, 27, cin, cout, ldx, lddy))
         if need_dx:
             wt = self._wt(w, nn.CONV3, 27, cin, cout)
             nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, gate=x, ldg=ldx,
                        gate_channels=cin if gate_ch is None else gate_ch)
 
-    def _wgrad_ws(self, rows, cin, cout, ldx, lddy):
-        """The shared workspace of the 3x3x3 weight gradients (partial sums
-        per block, added in a fixed order), grown to the largest layer; None
-        where a layer needs none."""
-        n = nn.wgrad_workspace(nn.CONV3, nn.IDENT, rows, 27, cin, cout, ldx, lddy)
+    def _wgrad_ws(self, src, dst, rows, taps, cin, cout, ldx, lddy):
+        """The shared workspace of the weight gradients (partial sums per
+        block, added in a fixed order), grown to the largest layer; None where
+        a layer needs none."""
+        n = nn.wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy)
         if n == 0:
             return None
         ws = getattr(self, "_ws", None)
@@ -214,7 +214,8 @@ class UNet:
         rows0 = self._rows(grids[0])
         below = A["d2", 0] if L > 1 else A["cat", 0]
         ldbelow = C[0] if L > 1 else A["cat", 0].shape[-1]
-        nn.wgrad(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g)
+        nn.wgrad(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g,
+                 ws=self._wgrad_ws(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, ldbelow, self.out_pad))
         wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
         d_below = G["d2", 0] if L > 1 else G["cat", 0]
         nn.forward(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
@@ -235,7 +236,7 @@ class UNet:
             else:
                 xin, ldxin, dxin = A["d2", l + 1], C[l + 1], G["d2", l + 1]
             nn.wgrad(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], xin, ldxin, G["cat", l], 2 * C[l], uw.g, ub.g,
-                     dy_offset=C[l])
+                     dy_offset=C[l], ws=self._wgrad_ws(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], ldxin, 2 * C[l]))
             wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
             nn.forward(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
                        x_offset=C[l], gate=xin, ldg=ldxin, gate_channels=C[l + 1])

@@ -151,6 +151,45 @@ def test_conv3_wgrad_brick_kernel(torch, grid, cin, cout):
                  ws=ws[: n - 1])
 
 
+@pytest.mark.parametrize("grid,cin,cout", [
+    ((16, 16, 16), 96, 96),   # the coarse levels: few bricks, several channel tiles
+    ((18, 22, 28), 48, 48),   # partial bricks on every axis
+])
+def test_conv3_wgrad_brick_small_grid_with_workspace(torch, grid, cin, cout):
+    """With a workspace the brick weight gradient also takes small grids (at
+    least 128 brick-run x channel-tile blocks); against the oracle's dW."""
+    x = bf(rng.normal(size=grid + (cin,)))
+    dy = bf(rng.normal(size=grid + (cout,)))
+    n = nn.wgrad_workspace(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, cin, cout)
+    assert n > 0
+    ws = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((cout, 27, cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    nn.wgrad(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw, db, ws=ws)
+    _, gw, gb = onn.conv3_backward(x, np.zeros((cout, 27, cin)), dy)
+    close(host(dw), gw, 2e-5)
+    close(host(db), gb, 2e-5)
+
+
+def test_thin_grids_avoid_bricks(torch):
+    """A grid thinner than a brick along x (4 voxels) has enough bricks for
+    both brick kernels but a halo that wraps past one period; the forward pass
+    and the weight gradient take the generic kernels and match the oracle."""
+    grid = (128, 64, 4)
+    x = bf(rng.normal(size=grid + (24,)))
+    w = bf(rng.normal(size=(24, 27, 24)) * 0.1)
+    y = torch.empty(grid + (24,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.CONV3, nn.IDENT, rows_of(grid), 27, 24, 24, dev(torch, x), 24, dev(torch, w), y, 24)
+    close(host(y), onn.conv3(x, w, np.zeros(24)))
+    dy = bf(rng.normal(size=grid + (24,)))
+    _, gw, _ = onn.conv3_backward(x, np.zeros((24, 27, 24)), dy)
+    n = nn.wgrad_workspace(nn.CONV3, nn.IDENT, rows_of(grid), 27, 24, 24, 24, 24)
+    for ws in (None, torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")):
+        dw = torch.zeros((24, 27, 24), dtype=torch.float32, device="cuda")
+        nn.wgrad(nn.CONV3, nn.IDENT, rows_of(grid), 27, 24, 24, dev(torch, x), 24, dev(torch, dy), 24, dw, ws=ws)
+        close(host(dw), gw, 2e-5)
+
+
 @pytest.mark.parametrize("cin,cout", [(48, 24), (16, 8)])
 def test_up2_forward_backward(torch, cin, cout):
     coarse = (2, 3, 2)
@@ -179,6 +218,44 @@ def test_up2_forward_backward(torch, cin, cout):
              db, dy_offset=cout)
     close(host(dw), gw, 2e-5)
     close(host(db), gb, 2e-5)
+
+
+@pytest.mark.parametrize("kind", ["dense", "up2", "gather2"])
+def test_generic_wgrad_with_workspace(torch, kind):
+    """The weight gradient of the 1x1, transposed (2x2x2 stride 2) and
+    pooling-stride layers with a workspace: partial sums of up to 2048 blocks
+    per tile added in two fixed-order passes; against the oracle, identical
+    from run to run, and close to the atomic-add path."""
+    if kind == "dense":
+        src, dst, taps, rows, cin, cout = nn.IDENT, nn.IDENT, 1, (64, 64, 32), 24, 16
+        x = bf(rng.normal(size=rows + (cin,)))
+        dy = bf(rng.normal(size=rows + (cout,)))
+        want = onn.dense_backward(x, np.zeros((cout, cin)), dy)[1][:, None, :]
+    elif kind == "up2":
+        src, dst, taps, rows, cin, cout = nn.IDENT, nn.SCATTER2, 8, (16, 16, 16), 48, 24
+        x = bf(rng.normal(size=rows + (cin,)))
+        dy = bf(rng.normal(size=tuple(2 * v for v in rows) + (cout,)))
+        want = onn.up2_backward(x, np.zeros((cout, 8, cin)), dy)[1]
+    else:
+        src, dst, taps, rows, cin, cout = nn.GATHER2, nn.IDENT, 8, (16, 16, 16), 24, 48
+        x = bf(rng.normal(size=tuple(2 * v for v in rows) + (cin,)))
+        dy = bf(rng.normal(size=rows + (cout,)))
+        # the pooling-stride layer is the transposed layer's backward-data pass:
+        # its weight gradient is the transposed layer's, with x and dy swapped
+        want = np.transpose(onn.up2_backward(dy, np.zeros((cin, 8, cout)), x)[1], (2, 1, 0))
+    grid = (rows[2], rows[1], rows[0])
+    n = nn.wgrad_workspace(src, dst, grid, taps, cin, cout, cin, cout)
+    assert n > 0
+    ws = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    X, DY = dev(torch, x), dev(torch, dy)
+    runs = []
+    for w_s in (ws, ws, None):
+        dw = torch.zeros((cout, taps, cin), dtype=torch.float32, device="cuda")
+        nn.wgrad(src, dst, grid, taps, cin, cout, X, cin, DY, cout, dw, ws=w_s)
+        runs.append(host(dw))
+    close(runs[0], want, 2e-5)
+    assert np.array_equal(runs[0], runs[1])
+    close(runs[2], want, 2e-5)
 
 
 def test_head_dense_fp32_and_backward(torch):
