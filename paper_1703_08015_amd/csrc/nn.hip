@@ -639,42 +639,62 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
 // read 27 times; here a block owns a channel tile (16*CF input and 16*NF
 // output channels) and a run of 8x4x4-voxel bricks, and for each brick stages
 // the 10x6x6 input halo and the brick's dy in LDS once for all 27 taps.
-// The reduction (K) runs over voxels, so both are stored channel-major: a
-// lane's 8 K values are the 8 voxels of one x-row.  The halo is kept as three
-// copies shifted by tx = 0, 1, 2 along x, xs[tx][c][hz][hy][8], so every
-// tap's A fragment is one aligned 16-byte LDS read; dy is ys[n][z][y][8].
-// Staging gives consecutive lanes consecutive voxels of one 8-channel group,
-// so a wavefront's 2-byte LDS writes of one channel fall into adjacent words.
+// The reduction (K) runs over voxels while the rows are channels-last, so an
+// MFMA operand needs each lane's 8 K values from 8 different voxels.  The
+// tiles are staged as they are stored ([voxel][channel], one 16-byte LDS
+// write per 8 channels) and read with gfx950's transposing LDS load
+// (ds_read_b64_tr_b16): in each group of 16 lanes, lane L supplies the address
+// of 4 channels (4 (L % 4) ..) of voxel L / 4, and lane j receives channel j
+// of those 4 voxels.  Two such loads give a lane channel j of the 8 voxels of
+// one x-row: the A (x) or B (dy) fragment of one K group.  A tap's shift is
+// only an address offset into the halo.
 // K step k is the brick's z-plane k and lane group g its y-row g.
 // Wavefront w accumulates the taps w, w + 4, ... (7 or 6 of them) for the
 // whole channel tile in registers; the next brick's global rows are loaded
-// while the current brick's MFMAs run, and each weight gets one FP32 atomic
-// add per block at the end.
+// while the current brick's MFMAs run.
 constexpr int kWbX = 8, kWbY = 4, kWbZ = 4;             // brick (output voxels)
-constexpr int kWhY = kWbY + 2, kWhZ = kWbZ + 2;         // halo rows along y and z
-constexpr int kWHalo = (kWbX + 2) * kWhY * kWhZ;        // 360 halo voxels
-constexpr int kWxStr = kWhY * kWhZ * 8 + 8;             // per-channel stride of a shifted copy (bf16)
-constexpr int kWyStr = kWbX * kWbY * kWbZ + 8;          // per-channel stride of ys (bf16)
-constexpr int kWTaps = 7;                               // taps per wavefront (27 = 7 + 7 + 7 + 6)
+constexpr int kWhX = kWbX + 2, kWhY = kWbY + 2, kWhZ = kWbZ + 2;  // halo extent
+constexpr int kWHalo = kWhX * kWhY * kWhZ;              // 360 halo voxels
 
+// W wavefronts per block (4, or 8 for the wider channel tiles, so that the
+// accumulators of a wavefront's taps leave room for two wavefronts per SIMD);
+// wavefront w takes the taps w, w + W, ... (TAPS or TAPS - 1 of them).
 template <int CF, int NF>
 struct WBrick {
+  static constexpr int W = CF * NF <= 4 ? 4 : 8, T = 64 * W;       // wavefronts, threads
+  static constexpr int TAPS = (27 + W - 1) / W, FULL = 27 - (TAPS - 1) * W;  // FULL wavefronts take TAPS taps
   static constexpr int GX = 2 * CF, GY = 2 * NF;                    // 8-channel groups per voxel
-  static constexpr int NSX = (kWHalo * GX + 255) / 256;             // staging loads per thread
-  static constexpr int NSY = (kWbX * kWbY * kWbZ * GY + 255) / 256;
-  static constexpr int LDS = (3 * 16 * CF * kWxStr + 16 * NF * kWyStr) * 2;  // bytes
+  static constexpr int NSX = (kWHalo * GX + T - 1) / T;             // staging loads per thread
+  static constexpr int NSY = (kWbX * kWbY * kWbZ * GY + T - 1) / T;
+  static constexpr int PX = 16 * CF + 8, PY = 16 * NF + 8;          // voxel pitches (bf16), 16-byte rows
+  static constexpr int LDS = (kWHalo * PX + kWbX * kWbY * kWbZ * PY) * 2;  // bytes
 };
 
+typedef short v4s16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s16 lds_v4s16;
+
+// The 8 K values of one MFMA operand row from two transposing LDS loads: p0
+// and p1 are this lane's addresses for voxels 0-3 and 4-7 of its K group.
+__device__ __forceinline__ bf16x8 tr_load8(const bf16 *p0, const bf16 *p1) {
+  const v4s16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p0));
+  const v4s16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p1));
+  typedef short v8s16 __attribute__((ext_vector_type(8)));
+  const v8s16 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
 template <int CF, int NF>
-__global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block, int cblocks,
-                                                     float *ws) {
+__global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block,
+                                                                       int cblocks, float *ws) {
   using WB = WBrick<CF, NF>;
   extern __shared__ __attribute__((aligned(16))) bf16 wlds[];
-  bf16 *xs = wlds;                                 // [3][16*CF][kWxStr]
-  bf16 *ys = wlds + 3 * 16 * CF * kWxStr;          // [16*NF][kWyStr]
+  bf16 *xs = wlds;                          // [kWHalo][PX]: halo voxel (hx + 10 (hy + 6 hz))
+  bf16 *ys = wlds + kWHalo * WB::PX;        // [128][PY]: brick voxel (x + 8 (y + 4 z))
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the tap branches below stay scalar
   const int r = lane & 15, g = lane >> 4;
+  // transposing loads: this lane supplies voxel tv (and tv + 4) of its x-row, channels 4 tq ..
+  const int tv = (lane & 15) >> 2, tq = lane & 3;
   const Grid gr = a.rows;  // CONV3: input grid == output grid
   const int cbase = (blockIdx.y % cblocks) * 16 * CF, nbase = (blockIdx.y / cblocks) * 16 * NF;
   const int bxn = (gr.nx + kWbX - 1) / kWbX, byn = (gr.ny + kWbY - 1) / kWbY, bzn = (gr.nz + kWbZ - 1) / kWbZ;
@@ -683,9 +703,9 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
   const int b1 = min(b0 + bricks_per_block, nbricks);
   const bf16 *__restrict__ dy = static_cast<const bf16 *>(a.y);
 
-  f32x4 acc[kWTaps][CF][NF];
+  f32x4 acc[WB::TAPS][CF][NF];
 #pragma unroll
-  for (int m = 0; m < kWTaps; ++m)
+  for (int m = 0; m < WB::TAPS; ++m)
 #pragma unroll
     for (int i = 0; i < CF; ++i)
 #pragma unroll
@@ -693,16 +713,17 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
 
   bf16x8 vx[WB::NSX], vy[WB::NSY];
   // global rows of brick b into registers (zeros past the channel counts and
-  // for output voxels outside the grid)
+  // for output voxels outside the grid); consecutive threads take consecutive
+  // 8-channel groups of one voxel
   auto load = [&](int b) {
     const int ox = (b % bxn) * kWbX, oy = ((b / bxn) % byn) * kWbY, oz = (b / (bxn * byn)) * kWbZ;
 #pragma unroll
     for (int it = 0; it < WB::NSX; ++it) {
-      const int e = tid + 256 * it;
+      const int e = tid + WB::T * it;
       vx[it] = bf16x8{};
       if (e < kWHalo * WB::GX) {
-        const int hv = e % kWHalo, q = e / kWHalo;
-        const int hx = hv % (kWbX + 2), hy = (hv / (kWbX + 2)) % kWhY, hz = hv / ((kWbX + 2) * kWhY);
+        const int hv = e / WB::GX, q = e % WB::GX;
+        const int hx = hv % kWhX, hy = (hv / kWhX) % kWhY, hz = hv / (kWhX * kWhY);
         const int c = cbase + 8 * q;
         if (c < a.cin)
           vx[it] = *reinterpret_cast<const bf16x8 *>(
@@ -711,10 +732,10 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
     }
 #pragma unroll
     for (int it = 0; it < WB::NSY; ++it) {
-      const int e = tid + 256 * it;
+      const int e = tid + WB::T * it;
       vy[it] = bf16x8{};
       if (e < kWbX * kWbY * kWbZ * WB::GY) {
-        const int v = e % (kWbX * kWbY * kWbZ), q = e / (kWbX * kWbY * kWbZ);
+        const int v = e / WB::GY, q = e % WB::GY;
         const int x = ox + v % kWbX, y = oy + (v / kWbX) % kWbY, z = oz + v / (kWbX * kWbY);
         const int n = nbase + 8 * q;
         if (x < gr.nx && y < gr.ny && z < gr.nz && n < a.cout)
@@ -722,33 +743,19 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
       }
     }
   };
-  // registers -> LDS, channel-major (every entry of xs and ys is written)
+  // registers -> LDS as stored: [voxel][channel], one 16-byte write per group
   auto stage = [&]() {
 #pragma unroll
     for (int it = 0; it < WB::NSX; ++it) {
-      const int e = tid + 256 * it;
-      if (e < kWHalo * WB::GX) {
-        const int hv = e % kWHalo, q = e / kWHalo;
-        const int hx = hv % (kWbX + 2), row = hv / (kWbX + 2);  // row = hz * kWhY + hy
-#pragma unroll
-        for (int tx = 0; tx < 3; ++tx) {
-          const int j = hx - tx;
-          if (j < 0 || j >= 8) continue;
-          bf16 *dst = xs + (tx * 16 * CF + 8 * q) * kWxStr + row * 8 + j;
-#pragma unroll
-          for (int k = 0; k < 8; ++k) dst[k * kWxStr] = vx[it][k];
-        }
-      }
+      const int e = tid + WB::T * it;
+      if (e < kWHalo * WB::GX)
+        *reinterpret_cast<bf16x8 *>(xs + (e / WB::GX) * WB::PX + 8 * (e % WB::GX)) = vx[it];
     }
 #pragma unroll
     for (int it = 0; it < WB::NSY; ++it) {
-      const int e = tid + 256 * it;
-      if (e < kWbX * kWbY * kWbZ * WB::GY) {
-        const int v = e % (kWbX * kWbY * kWbZ), q = e / (kWbX * kWbY * kWbZ);
-        bf16 *dst = ys + (8 * q) * kWyStr + v;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) dst[k * kWyStr] = vy[it][k];
-      }
+      const int e = tid + WB::T * it;
+      if (e < kWbX * kWbY * kWbZ * WB::GY)
+        *reinterpret_cast<bf16x8 *>(ys + (e / WB::GY) * WB::PY + 8 * (e % WB::GY)) = vy[it];
     }
   };
 
@@ -761,26 +768,26 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
 #pragma unroll
     for (int k = 0; k < kWbZ; ++k) {
       bf16x8 bv[NF];
+      const bf16 *yrow = ys + (tv + kWbX * (g + kWbY * k)) * WB::PY + 4 * tq;
 #pragma unroll
-      for (int j = 0; j < NF; ++j)
-        bv[j] = *reinterpret_cast<const bf16x8 *>(ys + (16 * j + r) * kWyStr + (k * kWbY + g) * 8);
+      for (int j = 0; j < NF; ++j) bv[j] = tr_load8(yrow + 16 * j, yrow + 4 * WB::PY + 16 * j);
       auto tap = [&](int m) {
-        const int t = wv + 4 * m;
+        const int t = wv + WB::W * m;
         const int tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
+        const bf16 *xrow = xs + ((tv + tx) + kWhX * ((g + ty) + kWhY * (k + tz))) * WB::PX + 4 * tq;
 #pragma unroll
         for (int i = 0; i < CF; ++i) {
-          const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
-              xs + (tx * 16 * CF + 16 * i + r) * kWxStr + ((k + tz) * kWhY + (g + ty)) * 8);
+          const bf16x8 av = tr_load8(xrow + 16 * i, xrow + 4 * WB::PX + 16 * i);
 #pragma unroll
           for (int j = 0; j < NF; ++j)
             acc[m][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[m][i][j], 0, 0, 0);
         }
       };
-      // taps wv + 4m < 27 for m < 6 on every wavefront; the seventh only on
-      // wavefronts 0-2 (one uniform branch)
+      // taps wv + W m < 27 for m < TAPS - 1 on every wavefront; the last one
+      // only on wavefronts below FULL (one uniform branch)
 #pragma unroll
-      for (int m = 0; m < kWTaps - 1; ++m) tap(m);
-      if (wv < 3) tap(kWTaps - 1);
+      for (int m = 0; m < WB::TAPS - 1; ++m) tap(m);
+      if (wv < WB::FULL) tap(WB::TAPS - 1);
     }
   }
   // lane holds C[c = 16i + 4g + q][n = 16j + r] of tap t.  With a workspace,
@@ -790,8 +797,8 @@ __global__ void __launch_bounds__(256) k_wgrad_brick(GemmArgs a, float *dw, int 
   const int ktot = 27 * a.cin;
   float *slot = ws ? ws + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (27 * 256 * CF * NF) : nullptr;
 #pragma unroll
-  for (int m = 0; m < kWTaps; ++m) {
-    const int t = wv + 4 * m;
+  for (int m = 0; m < WB::TAPS; ++m) {
+    const int t = wv + WB::W * m;
     if (t >= 27) continue;
 #pragma unroll
     for (int i = 0; i < CF; ++i)
@@ -1441,7 +1448,7 @@ hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, hipStr
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad_brick<CF, NF>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, WB::LDS);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)w.gx, (unsigned)tiles), dim3(256), WB::LDS, s, a, dw,
+  hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)w.gx, (unsigned)tiles), dim3(WB::T), WB::LDS, s, a, dw,
                      (int)w.per, w.cblocks, ws);
   e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
