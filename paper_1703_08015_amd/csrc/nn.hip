@@ -685,7 +685,7 @@ __device__ __forceinline__ bf16x8 tr_load8(const bf16 *p0, const bf16 *p1) {
 
 template <int CF, int NF>
 __global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block,
-                                                                       int cblocks, float *ws) {
+                                                                       int cblocks, float *ws, float *db) {
   using WB = WBrick<CF, NF>;
   extern __shared__ __attribute__((aligned(16))) bf16 wlds[];
   bf16 *xs = wlds;                          // [kWHalo][PX]: halo voxel (hx + 10 (hy + 6 hz))
@@ -759,12 +759,21 @@ __global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(G
     }
   };
 
+  // bias gradient (with db, on the blocks of the first input-channel tile):
+  // thread -> column bc of the output tile and every BL-th voxel of each brick
+  constexpr int BC = 16 * NF, BL = WB::T / BC;
+  const bool bias = db && blockIdx.y % cblocks == 0;
+  const int bc = tid % BC, bl = tid / BC;
+  float bsum = 0.f;
+
   if (b0 < b1) load(b0);
   for (int b = b0; b < b1; ++b) {
     __syncthreads();  // the previous brick's LDS reads are done
     stage();
     __syncthreads();
     if (b + 1 < b1) load(b + 1);  // in flight during the MFMAs
+    if (bias && bl < BL)
+      for (int v = bl; v < kWbX * kWbY * kWbZ; v += BL) bsum += (float)ys[v * WB::PY + bc];
 #pragma unroll
     for (int k = 0; k < kWbZ; ++k) {
       bf16x8 bv[NF];
@@ -788,6 +797,17 @@ __global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(G
 #pragma unroll
       for (int m = 0; m < WB::TAPS - 1; ++m) tap(m);
       if (wv < WB::FULL) tap(WB::TAPS - 1);
+    }
+  }
+  if (bias) {  // (uniform per block) the voxel lanes meet in LDS; one atomic add per column
+    float *red = reinterpret_cast<float *>(wlds);
+    __syncthreads();  // the last brick's LDS reads are done
+    red[tid] = bl < BL ? bsum : 0.f;
+    __syncthreads();
+    if (tid < BC && nbase + tid < a.cout) {
+      float t = 0.f;
+      for (int l = 0; l < BL; ++l) t += red[l * BC + tid];
+      atomicAdd(db + nbase + tid, t);
     }
   }
   // lane holds C[c = 16i + 4g + q][n = 16j + r] of tap t.  With a workspace,
@@ -1441,7 +1461,7 @@ WgradGrid wgrad_grid(const GemmArgs &a, int cf, int nf) {
 }
 
 template <int CF, int NF>
-hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s) {
   using WB = WBrick<CF, NF>;
   const WgradGrid w = wgrad_grid(a, CF, NF);
   const int tiles = w.cblocks * w.nblocks;
@@ -1449,7 +1469,7 @@ hipError_t launch_wgrad_brick_cf(const GemmArgs &a, float *dw, float *ws, hipStr
                                      hipFuncAttributeMaxDynamicSharedMemorySize, WB::LDS);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_wgrad_brick<CF, NF>), dim3((unsigned)w.gx, (unsigned)tiles), dim3(WB::T), WB::LDS, s, a, dw,
-                     (int)w.per, w.cblocks, ws);
+                     (int)w.per, w.cblocks, ws, db);
   e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
   return launch_wgrad_sum(ws, w.gx, tiles, CF, NF, w.cblocks, 27, 27, a.cin, a.cout, dw, s);
@@ -1496,20 +1516,22 @@ int64_t wgrad_brick_ws_floats(const GemmArgs &a) {
 }
 
 // Runs the brick weight gradient if it applies (returns false to use k_wgrad
-// instead); ws: partial sums (wgrad_brick_ws_floats) or NULL for atomics.
-bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, hipStream_t s, hipError_t *err) {
+// instead); ws: partial sums (wgrad_brick_ws_floats) or NULL for atomics; db:
+// the bias gradient, accumulated from the staged dy tiles (one atomic add per
+// block and channel), or NULL.
+bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s, hipError_t *err) {
   if (!wgrad_brick_applies(a, ws != nullptr)) return false;
   int cf, nf;
   wgrad_brick_frags(a, &cf, &nf);
   switch (cf * 4 + nf) {
-    case 5: *err = launch_wgrad_brick_cf<1, 1>(a, dw, ws, s); break;
-    case 6: *err = launch_wgrad_brick_cf<1, 2>(a, dw, ws, s); break;
-    case 7: *err = launch_wgrad_brick_cf<1, 3>(a, dw, ws, s); break;
-    case 9: *err = launch_wgrad_brick_cf<2, 1>(a, dw, ws, s); break;
-    case 10: *err = launch_wgrad_brick_cf<2, 2>(a, dw, ws, s); break;
-    case 11: *err = launch_wgrad_brick_cf<2, 3>(a, dw, ws, s); break;
-    case 13: *err = launch_wgrad_brick_cf<3, 1>(a, dw, ws, s); break;
-    default: *err = launch_wgrad_brick_cf<3, 2>(a, dw, ws, s); break;
+    case 5: *err = launch_wgrad_brick_cf<1, 1>(a, dw, ws, db, s); break;
+    case 6: *err = launch_wgrad_brick_cf<1, 2>(a, dw, ws, db, s); break;
+    case 7: *err = launch_wgrad_brick_cf<1, 3>(a, dw, ws, db, s); break;
+    case 9: *err = launch_wgrad_brick_cf<2, 1>(a, dw, ws, db, s); break;
+    case 10: *err = launch_wgrad_brick_cf<2, 2>(a, dw, ws, db, s); break;
+    case 11: *err = launch_wgrad_brick_cf<2, 3>(a, dw, ws, db, s); break;
+    case 13: *err = launch_wgrad_brick_cf<3, 1>(a, dw, ws, db, s); break;
+    default: *err = launch_wgrad_brick_cf<3, 2>(a, dw, ws, db, s); break;
   }
   return true;
 }
@@ -1574,7 +1596,10 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
     NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, ws, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
     hipError_t e = hipSuccess;
-    if (!try_wgrad_brick(a, dw, ws, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, s);
+    if (try_wgrad_brick(a, dw, ws, db, s, &e))
+      db = nullptr;  // done with the weights
+    else
+      e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, s);
     NN_TRY(e);
   } else if (g->src_mode == LBM_NN_GATHER2) {
     NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, ws, s)));
