@@ -71,6 +71,18 @@ typedef struct {
  * no separate lbm_nn_relu_backward pass over the gradient is needed. */
 int lbm_nn_forward(const lbm_nn_gemm *g, void *stream);
 
+/* lbm_nn_forward with a caller workspace: on grids too small to fill the
+ * device (fewer than 1024 blocks of 64 rows) with long K (at least 32 steps of
+ * 32), BF16 layers without a scatter split K over S blocks per tile, each
+ * writing FP32 partial sums to ws, and a second kernel adds them in a fixed
+ * order (same result to rounding, identical from run to run) with bias,
+ * activation and gate.  ws: device FP32, at least lbm_nn_forward_workspace(g)
+ * floats, overwritten; NULL = lbm_nn_forward.  LBM_ERR_ARG if ws_floats is
+ * too small. */
+int lbm_nn_forward_ws(const lbm_nn_gemm *g, float *ws, int64_t ws_floats, void *stream);
+/* Workspace floats lbm_nn_forward_ws uses for g (0: none); -1 for an invalid g. */
+int64_t lbm_nn_forward_workspace(const lbm_nn_gemm *g);
+
 /* Weight gradient of the same layer: dw[n][t*cin + c] += sum_m x[src(m,t)][c]
  * * dy[dst(m)][n], with g->y the BF16 gradient dy (row stride ldy) and dw an
  * FP32 [cout][taps*cin] accumulator (not cleared); g->w and g->bias unused.

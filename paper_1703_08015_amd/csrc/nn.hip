@@ -108,7 +108,7 @@ __device__ __forceinline__ int64_t gather_row(int x, int y, int z, int64_t m, in
 }
 
 template <int SRC, int DST, int NW, int RF, bool F32, bool RELU>
-__global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
+__global__ void __launch_bounds__(256) k_forward(GemmArgs a, float *part, int kper) {
   // LDS: the weight tiles during the K loop; for BF16 outputs the C tile
   // [64*RF rows][16*NW + 8] afterwards, so that each thread stores whole
   // 16-byte channel groups of one output row
@@ -142,8 +142,9 @@ __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
   // output voxels interleave, so one block writes whole runs of output rows.
   constexpr int NT = DST == LBM_NN_SCATTER2 ? 8 : 1;
   for (int tfix = 0; tfix < NT; ++tfix) {
-    const int kbeg = DST == LBM_NN_SCATTER2 ? tfix * a.cin : 0;
-    const int kend = DST == LBM_NN_SCATTER2 ? kbeg + a.cin : ktot;
+    // split K (part != NULL, IDENT dst only): block z takes k in [z kper, (z + 1) kper)
+    const int kbeg = DST == LBM_NN_SCATTER2 ? tfix * a.cin : (part ? (int)blockIdx.z * kper : 0);
+    const int kend = DST == LBM_NN_SCATTER2 ? kbeg + a.cin : (part ? min(kbeg + kper, ktot) : ktot);
 
     // weight staging: thread -> (column, 8-wide k group)
     const int scol = tid >> 2, sk = 8 * (tid & 3);
@@ -203,7 +204,23 @@ __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
       buf ^= 1;
     }
 
-    if constexpr (F32) {
+    if (part) {
+      // split K: this block's FP32 partial sums, part[z][row][n] (bias, ReLU
+      // and gate follow in k_forward_finish)
+      float *pz = part + (int64_t)blockIdx.z * a.M * a.cout;
+#pragma unroll
+      for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+          const int n = n0 + 16 * j + r;
+          if (n >= a.cout) continue;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int64_t mo = mb + 16 * f + 4 * kb + i;
+            if (mo < a.M) pz[mo * a.cout + n] = acc[f][j][i];
+          }
+        }
+    } else if constexpr (F32) {
       // FP32 rows (the network's head): one element per lane and row
 #pragma unroll
       for (int f = 0; f < RF; ++f) {
@@ -261,6 +278,42 @@ __global__ void __launch_bounds__(256) k_forward(GemmArgs a) {
       __syncthreads();  // the tile's reads are done before LDS takes weights again
     }
   }
+}
+
+// Split-K epilogue: y[row][n] = act(sum over the splits z = 0 .. S-1, in that
+// order, of part[z][row][n] + bias[n]), gated like k_forward; BF16 rows, one
+// thread per (row, 8-channel group).
+template <bool RELU>
+__global__ void __launch_bounds__(256) k_forward_finish(GemmArgs a, const float *__restrict__ part, int S) {
+  const int groups = a.cout / 8;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.M * groups) return;
+  const int64_t row = e / groups;
+  const int n = 8 * (int)(e % groups);
+  float v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = a.bias ? a.bias[n + u] : 0.f;
+  float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int z = 0; z < S; ++z) {
+    const float4 *p = reinterpret_cast<const float4 *>(part + ((int64_t)z * a.M + row) * a.cout + n);
+    const float4 lo = p[0], hi = p[1];
+    sum[0] += lo.x, sum[1] += lo.y, sum[2] += lo.z, sum[3] += lo.w;
+    sum[4] += hi.x, sum[5] += hi.y, sum[6] += hi.z, sum[7] += hi.w;
+  }
+  bf16x8 o;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    float x = sum[u] + v[u];
+    if (RELU) x = fmaxf(x, 0.f);
+    o[u] = (bf16)x;
+  }
+  if (n < a.gate_ch) {
+    const bf16x8 gv = *reinterpret_cast<const bf16x8 *>(a.gate + row * a.ldg + n);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (!gate_open(gv[u])) o[u] = (bf16)0.f;
+  }
+  *reinterpret_cast<bf16x8 *>(static_cast<bf16 *>(a.y) + row * a.ldy + n) = o;
 }
 
 // ---- CONV3 forward on spatial bricks -----------------------------------------
@@ -1317,25 +1370,61 @@ int check_gemm(const lbm_nn_gemm *g, bool wgrad) {
   } while (0)
 
 template <int SRC, int DST, int RF, bool F32, bool RELU>
-hipError_t launch_fwd_rf(const GemmArgs &a, int nw, dim3 grid, hipStream_t s) {
+hipError_t launch_fwd_rf(const GemmArgs &a, int nw, dim3 grid, float *part, int kper, hipStream_t s) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((k_forward<SRC, DST, 1, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_forward<SRC, DST, 2, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_forward<SRC, DST, 3, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_forward<SRC, DST, 4, RF, F32, RELU>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_forward<SRC, DST, 1, RF, F32, RELU>), grid, dim3(256), 0, s, a, part, kper); break;
+    case 2: hipLaunchKernelGGL((k_forward<SRC, DST, 2, RF, F32, RELU>), grid, dim3(256), 0, s, a, part, kper); break;
+    case 3: hipLaunchKernelGGL((k_forward<SRC, DST, 3, RF, F32, RELU>), grid, dim3(256), 0, s, a, part, kper); break;
+    default: hipLaunchKernelGGL((k_forward<SRC, DST, 4, RF, F32, RELU>), grid, dim3(256), 0, s, a, part, kper); break;
   }
   return hipGetLastError();
 }
 
+int fwd_nw(const GemmArgs &a) { return a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4)); }
+
+// Split-K plan of k_forward for small grids (fewer than 1024 blocks of 64 rows
+// and at least 32 K steps of 32): S splits of kper (a multiple of 32) so that
+// the launch has about 1024 blocks with at least 8 K steps each; S = 1: none.
+// BF16 outputs with IDENT destinations only.
+struct SplitPlan {
+  int S, kper;
+};
+SplitPlan split_plan(const lbm_nn_gemm *g, const GemmArgs &a) {
+  SplitPlan p{1, 0};
+  if (g->y_fp32 || g->dst_mode != LBM_NN_IDENT) return p;
+  const int nw = fwd_nw(a);
+  const int64_t blocks = (a.M + 63) / 64 * ((a.cout + 16 * nw - 1) / (16 * nw));
+  const int ksteps = (a.taps * a.cin + 31) / 32;
+  if (blocks >= 1024 || ksteps < 32) return p;
+  int S = (int)((1024 + blocks - 1) / blocks);
+  if (S > ksteps / 8) S = ksteps / 8;
+  if (S < 2) return p;
+  const int per_steps = (ksteps + S - 1) / S;
+  p.kper = 32 * per_steps;
+  p.S = (ksteps + per_steps - 1) / per_steps;
+  return p;
+}
+
 template <int SRC, int DST, bool F32, bool RELU>
-hipError_t launch_fwd(const GemmArgs &a, hipStream_t s) {
-  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
+hipError_t launch_fwd(const GemmArgs &a, hipStream_t s, const SplitPlan &sp = SplitPlan{1, 0}, float *part = nullptr) {
+  const int nw = fwd_nw(a);
   const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
+  if constexpr (DST == LBM_NN_IDENT && !F32) {
+    if (sp.S > 1) {
+      hipError_t e = launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy, sp.S), part,
+                                                           sp.kper, s);
+      if (e != hipSuccess) return e;
+      const int64_t n = a.M * (a.cout / 8);
+      hipLaunchKernelGGL(k_forward_finish<RELU>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
+                         (const float *)part, sp.S);
+      return hipGetLastError();
+    }
+  }
   // 256 rows per block where that still gives the device >= 512 blocks, else 64
   const int64_t big = (a.M + 255) / 256 * gy;
   if (big >= 512)
-    return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy), s);
-  return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy), s);
+    return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy), nullptr, 0, s);
+  return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy), nullptr, 0, s);
 }
 
 template <int NW, int CC>
@@ -1360,8 +1449,12 @@ hipError_t launch_brick_nw(const GemmArgs &a, int cc, bool relu, dim3 grid, hipS
 // 8 (an 8-channel input), 24 (24 or 48 channels: a 48-wide chunk would need
 // 86 KB of LDS and leave one block per CU) or 32 (multiples of 32), and enough
 // bricks to fill the device; returns false to use k_forward instead.
-bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t *err) {
-  if (f32) return false;
+// channel chunk of the brick kernel for a 3x3x3 convolution with BF16
+// output, or 0 where it does not apply (an unsupported input width, a grid
+// thinner than a brick, whose halo would wrap past one period, or too few
+// bricks to fill the device)
+int brick_chunk(const GemmArgs &a, bool f32) {
+  if (f32) return 0;
   int cc;
   if (a.cin == 8)
     cc = 8;
@@ -1370,15 +1463,22 @@ bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t
   else if (a.cin % 32 == 0)
     cc = 32;
   else
-    return false;
-  const int nw = a.cout <= 16 ? 1 : (a.cout <= 32 ? 2 : (a.cout % 48 == 0 ? 3 : 4));
-  // the halo's periodic wrap needs the grid to be at least one brick along every axis
-  if (a.rows.nx < kBrickX || a.rows.ny < kBrickY || a.rows.nz < kBrickZ) return false;
+    return 0;
+  if (a.rows.nx < kBrickX || a.rows.ny < kBrickY || a.rows.nz < kBrickZ) return 0;
+  const int nw = fwd_nw(a);
   const int64_t bricks = (int64_t)((a.rows.nx + kBrickX - 1) / kBrickX) * ((a.rows.ny + kBrickY - 1) / kBrickY) *
                          ((a.rows.nz + kBrickZ - 1) / kBrickZ);
-  const unsigned gy = (unsigned)((a.cout + 16 * nw - 1) / (16 * nw));
-  if (bricks * gy < 256) return false;
-  const dim3 grid((unsigned)bricks, gy, 1);
+  if (bricks * ((a.cout + 16 * nw - 1) / (16 * nw)) < 256) return 0;
+  return cc;
+}
+
+bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t *err) {
+  const int cc = brick_chunk(a, f32);
+  if (!cc) return false;
+  const int nw = fwd_nw(a);
+  const int64_t bricks = (int64_t)((a.rows.nx + kBrickX - 1) / kBrickX) * ((a.rows.ny + kBrickY - 1) / kBrickY) *
+                         ((a.rows.nz + kBrickZ - 1) / kBrickZ);
+  const dim3 grid((unsigned)bricks, (unsigned)((a.cout + 16 * nw - 1) / (16 * nw)), 1);
   switch (nw) {
     case 1: *err = launch_brick_nw<1>(a, cc, relu, grid, s); break;
     case 2: *err = launch_brick_nw<2>(a, cc, relu, grid, s); break;
@@ -1389,13 +1489,25 @@ bool try_brick(const GemmArgs &a, bool f32, bool relu, hipStream_t s, hipError_t
 }
 
 template <int SRC, int DST>
-hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, hipStream_t s) {
+hipError_t fwd_act(const GemmArgs &a, bool f32, bool relu, const SplitPlan &sp, float *part, hipStream_t s) {
   if constexpr (SRC == LBM_NN_CONV3 && DST == LBM_NN_IDENT) {
     hipError_t e = hipSuccess;
     if (try_brick(a, f32, relu, s, &e)) return e;
   }
   if (f32) return relu ? launch_fwd<SRC, DST, true, true>(a, s) : launch_fwd<SRC, DST, true, false>(a, s);
-  return relu ? launch_fwd<SRC, DST, false, true>(a, s) : launch_fwd<SRC, DST, false, false>(a, s);
+  return relu ? launch_fwd<SRC, DST, false, true>(a, s, sp, part) : launch_fwd<SRC, DST, false, false>(a, s, sp, part);
+}
+
+// whether lbm_nn_forward takes the brick kernel for this layer (no workspace then)
+bool takes_brick(const lbm_nn_gemm *g, const GemmArgs &a) {
+  return g->src_mode == LBM_NN_CONV3 && g->dst_mode == LBM_NN_IDENT && brick_chunk(a, g->y_fp32 != 0) != 0;
+}
+
+// workspace floats of lbm_nn_forward_ws (the split-K partial sums; 0: none)
+int64_t fwd_ws_floats(const lbm_nn_gemm *g, const GemmArgs &a) {
+  if (takes_brick(g, a)) return 0;
+  const SplitPlan sp = split_plan(g, a);
+  return sp.S > 1 ? (int64_t)sp.S * a.M * a.cout : 0;
 }
 
 // Grid of k_wgrad: (voxel chunks, taps * cblocks, nblocks), about 2048 blocks
@@ -1560,22 +1672,41 @@ int64_t wgrad_ws_floats(const lbm_nn_gemm *g, const GemmArgs &a) {
 using namespace lbm::nn;
 using lbm::set_error;
 
-extern "C" int lbm_nn_forward(const lbm_nn_gemm *g, void *stream) {
+static int forward_impl(const lbm_nn_gemm *g, float *ws, int64_t ws_floats, void *stream) {
   int rc = check_gemm(g, false);
   if (rc) return rc;
   const GemmArgs a = to_args(g);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool f32 = g->y_fp32 != 0, relu = g->relu != 0;
+  SplitPlan sp{1, 0};
+  if (ws) {
+    const int64_t need = fwd_ws_floats(g, a);
+    if (ws_floats < need)
+      return set_error(LBM_ERR_ARG, "lbm_nn_forward_ws: workspace of %lld floats, %lld needed", (long long)ws_floats,
+                       (long long)need);
+    if (need > 0) sp = split_plan(g, a);
+  }
   if (g->dst_mode == LBM_NN_SCATTER2) {
-    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, f32, relu, s)));
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, f32, relu, sp, ws, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
-    NN_TRY((fwd_act<LBM_NN_CONV3, LBM_NN_IDENT>(a, f32, relu, s)));
+    NN_TRY((fwd_act<LBM_NN_CONV3, LBM_NN_IDENT>(a, f32, relu, sp, ws, s)));
   } else if (g->src_mode == LBM_NN_GATHER2) {
-    NN_TRY((fwd_act<LBM_NN_GATHER2, LBM_NN_IDENT>(a, f32, relu, s)));
+    NN_TRY((fwd_act<LBM_NN_GATHER2, LBM_NN_IDENT>(a, f32, relu, sp, ws, s)));
   } else {
-    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_IDENT>(a, f32, relu, s)));
+    NN_TRY((fwd_act<LBM_NN_IDENT, LBM_NN_IDENT>(a, f32, relu, sp, ws, s)));
   }
   return LBM_OK;
+}
+
+extern "C" int lbm_nn_forward(const lbm_nn_gemm *g, void *stream) { return forward_impl(g, nullptr, 0, stream); }
+
+extern "C" int lbm_nn_forward_ws(const lbm_nn_gemm *g, float *ws, int64_t ws_floats, void *stream) {
+  return forward_impl(g, ws, ws_floats, stream);
+}
+
+extern "C" int64_t lbm_nn_forward_workspace(const lbm_nn_gemm *g) {
+  if (check_gemm(g, false)) return -1;
+  return fwd_ws_floats(g, to_args(g));
 }
 
 // Weight gradient with an optional workspace for the brick kernel's partial sums.

@@ -34,6 +34,7 @@ def _lib():
         G = ctypes.POINTER(Gemm)
         sig = {
             "lbm_nn_forward": [G, P],
+            "lbm_nn_forward_ws": [G, P, I64, P],
             "lbm_nn_wgrad": [G, P, P, P],
             "lbm_nn_wgrad_ws": [G, P, P, P, I64, P],
             "lbm_nn_backward_weights": [I32, I32, I32, I32, P, P, P],
@@ -53,8 +54,9 @@ def _lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = args
-        L.lbm_nn_wgrad_workspace.restype = I64
-        L.lbm_nn_wgrad_workspace.argtypes = [G]
+        for name in ("lbm_nn_wgrad_workspace", "lbm_nn_forward_workspace"):
+            getattr(L, name).restype = I64
+            getattr(L, name).argtypes = [G]
         _sigs_done = True
     return L
 
@@ -91,16 +93,30 @@ def _gemm(src, dst, rows, taps, cin, cout, x, ldx, w, bias, y, ldy, y_fp32, relu
 
 
 def forward(src, dst, rows, taps, cin, cout, x, ldx, w, y, ldy, bias=None, y_fp32=False, relu=False, stream=None,
-            x_offset=0, y_offset=0, gate=None, ldg=0, gate_channels=0, gate_offset=0):
+            x_offset=0, y_offset=0, gate=None, ldg=0, gate_channels=0, gate_offset=0, ws=None):
     """y = act(gather-GEMM(x, w) + bias); x_offset / y_offset / gate_offset
     are element offsets into x, y and gate (channel slices of wider rows).
     With a gate (BF16 rows of stride ldg on the output grid), the first
-    gate_channels output channels are zeroed where the gate is not > 0."""
+    gate_channels output channels are zeroed where the gate is not > 0.
+    ws (FP32, at least forward_workspace(...) elements): lbm_nn_forward_ws."""
     g = _gemm(src, dst, rows, taps, cin, cout, x.data_ptr() + 2 * x_offset, ldx, w.data_ptr(),
               None if bias is None else bias.data_ptr(), y.data_ptr() + y.element_size() * y_offset, ldy, y_fp32, relu)
     if gate is not None:
         g.gate, g.ldg, g.gate_channels = gate.data_ptr() + 2 * gate_offset, ldg, gate_channels
-    _check(_lib().lbm_nn_forward(ctypes.byref(g), _stream(stream)), "lbm_nn_forward")
+    if ws is None:
+        _check(_lib().lbm_nn_forward(ctypes.byref(g), _stream(stream)), "lbm_nn_forward")
+    else:
+        _check(_lib().lbm_nn_forward_ws(ctypes.byref(g), _ptr(ws), int(ws.numel()), _stream(stream)),
+               "lbm_nn_forward_ws")
+
+
+def forward_workspace(src, dst, rows, taps, cin, cout, ldx, ldy, y_fp32=False):
+    """FP32 elements of the workspace lbm_nn_forward_ws uses for this layer."""
+    g = _gemm(src, dst, rows, taps, cin, cout, 16, ldx, 16, None, 16, ldy, y_fp32, False)
+    n = int(_lib().lbm_nn_forward_workspace(ctypes.byref(g)))
+    if n < 0:
+        raise LbmError(-1, "lbm_nn_forward_workspace", "invalid layer")
+    return n
 
 
 def wgrad(src, dst, rows, taps, cin, cout, x, ldx, dy, lddy, dw, db=None, stream=None, x_offset=0, dy_offset=0,

@@ -139,10 +139,10 @@ class UNet:
             if l > 0:
                 nn.maxpool2(rows, C[l - 1], A["cat", l - 1], 2 * C[l - 1], A["pool", l], C[l - 1], A["arg", l])
                 src, srcld, srcc = A["pool", l], C[l - 1], C[l - 1]
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, srcc, C[l], src, srcld, w1.b16, A["e1", l], C[l], bias=b1.p,
+            self._fwd(nn.CONV3, nn.IDENT, rows, 27, srcc, C[l], src, srcld, w1.b16, A["e1", l], C[l], bias=b1.p,
                        relu=True)
             width = A["cat", l].shape[-1]
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["e1", l], C[l], w2.b16, A["cat", l], width,
+            self._fwd(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["e1", l], C[l], w2.b16, A["cat", l], width,
                        bias=b2.p, relu=True)
         below = A["cat", L - 1]
         for k, l in enumerate(range(L - 2, -1, -1)):
@@ -150,15 +150,15 @@ class UNet:
             uw, ub = self.up[k]
             (w1, b1), (w2, b2) = self.dec[k]
             ldb = below.shape[-1]
-            nn.forward(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], below, ldb, uw.b16, A["cat", l], 2 * C[l],
+            self._fwd(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], below, ldb, uw.b16, A["cat", l], 2 * C[l],
                        bias=ub.p, y_offset=C[l])
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1.b16, A["d1", l], C[l],
+            self._fwd(nn.CONV3, nn.IDENT, rows, 27, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1.b16, A["d1", l], C[l],
                        bias=b1.p, relu=True)
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["d1", l], C[l], w2.b16, A["d2", l], C[l],
+            self._fwd(nn.CONV3, nn.IDENT, rows, 27, C[l], C[l], A["d1", l], C[l], w2.b16, A["d2", l], C[l],
                        bias=b2.p, relu=True)
             below = A["d2", l]
         hw, hb = self.head
-        nn.forward(nn.IDENT, nn.IDENT, self._rows(grids[0]), 1, C[0], self.out_ch, below, C[0], hw.b16, A["out"],
+        self._fwd(nn.IDENT, nn.IDENT, self._rows(grids[0]), 1, C[0], self.out_ch, below, C[0], hw.b16, A["out"],
                    self.out_ch, bias=hb.p, y_fp32=True)
         return A["out"]
 
@@ -173,20 +173,30 @@ class UNet:
                  ws=self._wgrad_ws(nn.CONV3, nn.IDENT, rows, 27, cin, cout, ldx, lddy))
         if need_dx:
             wt = self._wt(w, nn.CONV3, 27, cin, cout)
-            nn.forward(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, gate=x, ldg=ldx,
+            self._fwd(nn.CONV3, nn.IDENT, rows, 27, cout, cin, dy, lddy, wt, dx, lddx, gate=x, ldg=ldx,
                        gate_channels=cin if gate_ch is None else gate_ch)
 
-    def _wgrad_ws(self, src, dst, rows, taps, cin, cout, ldx, lddy):
-        """The shared workspace of the weight gradients (partial sums per
-        block, added in a fixed order), grown to the largest layer; None where
-        a layer needs none."""
-        n = nn.wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy)
+    def _fwd(self, src, dst, rows, taps, cin, cout, x, ldx, w, y, ldy, y_fp32=False, **kw):
+        """nn.forward with the shared workspace where the layer splits K (the
+        small grids of the coarse levels)."""
+        n = nn.forward_workspace(src, dst, rows, taps, cin, cout, ldx, ldy, y_fp32)
+        nn.forward(src, dst, rows, taps, cin, cout, x, ldx, w, y, ldy, y_fp32=y_fp32, ws=self._shared_ws(n), **kw)
+
+    def _shared_ws(self, n):
+        """A view of n floats of the workspace shared by every layer (grown to
+        the largest); None for n = 0."""
         if n == 0:
             return None
         ws = getattr(self, "_ws", None)
         if ws is None or ws.numel() < n:
             ws = self._ws = self.torch.empty(n, dtype=self.torch.float32, device=self.device)
         return ws[:n]
+
+    def _wgrad_ws(self, src, dst, rows, taps, cin, cout, ldx, lddy):
+        """The shared workspace of the weight gradients (partial sums per
+        block, added in a fixed order), grown to the largest layer; None where
+        a layer needs none."""
+        return self._shared_ws(nn.wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy))
 
     def _wt(self, w, mode, taps, cin, cout):
         t = self.torch
@@ -218,7 +228,7 @@ class UNet:
                  ws=self._wgrad_ws(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, ldbelow, self.out_pad))
         wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
         d_below = G["d2", 0] if L > 1 else G["cat", 0]
-        nn.forward(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
+        self._fwd(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
                    gate=below, ldg=ldbelow, gate_channels=C[0])
         # decoder, top level first (reverse of the forward order)
         for k, l in enumerate(range(0, L - 1)):
@@ -238,7 +248,7 @@ class UNet:
             nn.wgrad(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], xin, ldxin, G["cat", l], 2 * C[l], uw.g, ub.g,
                      dy_offset=C[l], ws=self._wgrad_ws(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], ldxin, 2 * C[l]))
             wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
-            nn.forward(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
+            self._fwd(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
                        x_offset=C[l], gate=xin, ldg=ldxin, gate_channels=C[l + 1])
         # encoder, bottom level first
         for l in range(L - 1, -1, -1):

@@ -151,6 +151,45 @@ def test_conv3_wgrad_brick_kernel(torch, grid, cin, cout):
                  ws=ws[: n - 1])
 
 
+@pytest.mark.parametrize("grid,cin,cout,relu,gated", [
+    ((16, 16, 16), 96, 96, True, False),   # the coarse levels: 128 blocks, 81 K steps
+    ((8, 8, 8), 192, 96, False, True),     # 16 blocks, 162 K steps
+    ((12, 10, 6), 64, 48, True, True),     # a grid thinner than a brick, ragged row count
+])
+def test_split_k_forward(torch, grid, cin, cout, relu, gated):
+    """With a workspace, small grids split K over blocks: FP32 partial sums
+    added in a fixed order with bias, ReLU and gate; against the oracle,
+    identical from run to run, and close to the unsplit kernel."""
+    x = bf(rng.normal(size=grid + (cin,)))
+    w = bf(rng.normal(size=(cout, 27, cin)) * 0.05)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    gate = bf(rng.normal(size=grid + (cout,)))
+    want = onn.conv3(x, w, b)
+    if relu:
+        want = onn.relu(want)
+    if gated:
+        want = np.where(gate > 0, want, 0.0)
+    n = nn.forward_workspace(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, cin, cout)
+    assert n > 0
+    ws = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    X, W, B, Gt = dev(torch, x), dev(torch, w), dev(torch, b, torch.float32), dev(torch, gate)
+    kw = dict(gate=Gt, ldg=cout, gate_channels=cout) if gated else {}
+    outs = []
+    for w_s in (ws, ws, None):
+        y = torch.empty(grid + (cout,), dtype=torch.bfloat16, device="cuda")
+        nn.forward(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, X, cin, W, y, cout, bias=B, relu=relu, ws=w_s,
+                   **kw)
+        outs.append(y)
+    torch.cuda.synchronize()
+    for y in outs:
+        close(host(y), want)
+    assert torch.equal(outs[0].view(torch.int16), outs[1].view(torch.int16))
+    if gated:
+        assert not host(outs[0])[gate <= 0].any()
+    with pytest.raises(nn.LbmError):
+        nn.forward(nn.CONV3, nn.IDENT, rows_of(grid), 27, cin, cout, X, cin, W, outs[0], cout, ws=ws[: n - 1])
+
+
 @pytest.mark.parametrize("grid,cin,cout", [
     ((16, 16, 16), 96, 96),   # the coarse levels: few bricks, several channel tiles
     ((18, 22, 28), 48, 48),   # partial bricks on every axis
