@@ -316,6 +316,130 @@ __global__ void __launch_bounds__(256) k_forward_finish(GemmArgs a, const float 
   *reinterpret_cast<bf16x8 *>(static_cast<bf16 *>(a.y) + row * a.ldy + n) = o;
 }
 
+// ---- transposed 2x2x2 stride-2 convolution (scatter) forward ---------------
+// Every tap reads the same coarse rows, so a block loads its A fragments once
+// (all K steps, in registers) and runs its taps in turn: tap t's weight tile
+// (16*NW columns x cin) is staged in LDS, double-buffered, with the next tap's
+// tile loaded during this tap's MFMAs; the output tile goes through LDS into
+// 16-byte stores of the tap's fine voxels.  Block z takes taps
+// [z * 8 / gridDim.z, (z + 1) * 8 / gridDim.z) (small grids spread the taps
+// over more blocks).  BF16 output; cin <= 32 * KSM.
+template <int NW, int RF, bool RELU>
+__global__ void __launch_bounds__(256) k_up2(GemmArgs a) {
+  constexpr int KSM = 8 / RF;                       // K steps held in registers
+  constexpr int OS = 16 * NW + 8;
+  constexpr int WPT = (16 * NW * KSM * 4 + 255) / 256;  // weight staging loads per thread
+  extern __shared__ __attribute__((aligned(16))) bf16 ulds[];
+  const int ks = (a.cin + 31) / 32, wp = 32 * ks + 8;  // K steps; weight tile pitch (bf16)
+  bf16 *wbuf = ulds;                                 // [2][16*NW][wp]
+  bf16 *ot = ulds + 2 * 16 * NW * wp;                // [64*RF][OS]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = lane & 15, kb = lane >> 4;
+  const int64_t rb = (int64_t)blockIdx.x * (64 * RF);  // first row of the block
+  const int n0 = blockIdx.y * 16 * NW;
+  const int tpb = 8 / gridDim.z, t0 = blockIdx.z * tpb, ktot = 8 * a.cin;
+
+  bf16x8 av[KSM][RF];
+#pragma unroll
+  for (int st = 0; st < KSM; ++st)
+#pragma unroll
+    for (int f = 0; f < RF; ++f) {
+      const int64_t m = rb + wv * 16 * RF + 16 * f + r;
+      const int c = 32 * st + 8 * kb;
+      av[st][f] = bf16x8{};
+      if (st < ks && m < a.M && c < a.cin) av[st][f] = *reinterpret_cast<const bf16x8 *>(a.x + m * a.ldx + c);
+    }
+
+  // weight tile of tap t: entry e = (column, 8-wide k group), zeros past cin and cout
+  bf16x8 wreg[WPT];
+  const int wgroups = 16 * NW * 4 * ks;
+  auto load_w = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + 256 * u;
+      const int col = e / (4 * ks), k = 8 * (e % (4 * ks));
+      wreg[u] = bf16x8{};
+      if (e < wgroups && n0 + col < a.cout && k < a.cin)
+        wreg[u] = *reinterpret_cast<const bf16x8 *>(a.w + (int64_t)(n0 + col) * ktot + t * a.cin + k);
+    }
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < wgroups)
+        *reinterpret_cast<bf16x8 *>(wbuf + (buf * 16 * NW + e / (4 * ks)) * wp + 8 * (e % (4 * ks))) = wreg[u];
+    }
+  };
+
+  load_w(t0);
+  store_w(0);
+  int buf = 0;
+  for (int t = t0; t < t0 + tpb; ++t) {
+    __syncthreads();  // tap t's weights are staged; the previous tile's reads are done
+    if (t + 1 < t0 + tpb) load_w(t + 1);  // in flight during this tap's MFMAs
+    f32x4 acc[RF][NW];
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+      for (int j = 0; j < NW; ++j) acc[f][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < KSM; ++st) {
+      if (st >= ks) break;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(wbuf + (buf * 16 * NW + 16 * j + r) * wp + 32 * st + 8 * kb);
+#pragma unroll
+        for (int f = 0; f < RF; ++f) acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[st][f], bv, acc[f][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const int n = n0 + 16 * j + r;
+      const float bias = (a.bias && n < a.cout) ? a.bias[n] : 0.f;
+#pragma unroll
+      for (int f = 0; f < RF; ++f)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float v = acc[f][j][i] + bias;
+          if (RELU) v = fmaxf(v, 0.f);
+          ot[(wv * 16 * RF + 16 * f + 4 * kb + i) * OS + 16 * j + r] = (bf16)v;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * RF * 2 * NW; e += 256) {
+      const int rl = e / (2 * NW), q = e % (2 * NW);
+      const int64_t mo = rb + rl;
+      const int n = n0 + 8 * q;
+      if (mo >= a.M || n >= a.cout) continue;
+      bf16x8 o = *reinterpret_cast<const bf16x8 *>(ot + rl * OS + 8 * q);
+      const int64_t dv = dst_voxel<LBM_NN_SCATTER2>(mo, t, a.rows, a.out_grid);
+      if (n < a.gate_ch) {
+        const bf16x8 gv = *reinterpret_cast<const bf16x8 *>(a.gate + dv * a.ldg + n);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (!gate_open(gv[u])) o[u] = (bf16)0.f;
+      }
+      *reinterpret_cast<bf16x8 *>(static_cast<bf16 *>(a.y) + dv * a.ldy + n) = o;
+    }
+    if (t + 1 < t0 + tpb) store_w(buf ^ 1);
+    buf ^= 1;
+  }
+}
+
+template <int NW, int RF>
+hipError_t launch_up2_nw(const GemmArgs &a, bool relu, dim3 grid, size_t lds, hipStream_t s) {
+  const void *k = relu ? reinterpret_cast<const void *>(&k_up2<NW, RF, true>)
+                       : reinterpret_cast<const void *>(&k_up2<NW, RF, false>);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (relu)
+    hipLaunchKernelGGL((k_up2<NW, RF, true>), grid, dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_up2<NW, RF, false>), grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
 // ---- CONV3 forward on spatial bricks -----------------------------------------
 // A block owns an 8x8x4 brick of output voxels and 16*NW output channels; for
 // each chunk of CC input channels it stages the brick's 10x10x6 input halo
@@ -1422,6 +1546,31 @@ hipError_t launch_fwd(const GemmArgs &a, hipStream_t s, const SplitPlan &sp = Sp
   }
   // 256 rows per block where that still gives the device >= 512 blocks, else 64
   const int64_t big = (a.M + 255) / 256 * gy;
+  if constexpr (DST == LBM_NN_SCATTER2 && !F32) {
+    const int ks = (a.cin + 31) / 32;
+    const int rf = big >= 512 && ks <= 2 ? 4 : 1;
+    const size_t lds = (size_t)(2 * 16 * nw * (32 * ks + 8) + 64 * rf * (16 * nw + 8)) * 2;
+    if (ks <= 8 / rf && lds <= 65536) {
+      const int64_t blocks = (a.M + 64 * rf - 1) / (64 * rf) * gy;
+      unsigned tz = 1;
+      while (blocks * tz < 512 && tz < 8) tz *= 2;
+      const dim3 grid((unsigned)((a.M + 64 * rf - 1) / (64 * rf)), gy, tz);
+      if (rf == 4) {
+        switch (nw) {
+          case 1: return launch_up2_nw<1, 4>(a, RELU, grid, lds, s);
+          case 2: return launch_up2_nw<2, 4>(a, RELU, grid, lds, s);
+          case 3: return launch_up2_nw<3, 4>(a, RELU, grid, lds, s);
+          default: return launch_up2_nw<4, 4>(a, RELU, grid, lds, s);
+        }
+      }
+      switch (nw) {
+        case 1: return launch_up2_nw<1, 1>(a, RELU, grid, lds, s);
+        case 2: return launch_up2_nw<2, 1>(a, RELU, grid, lds, s);
+        case 3: return launch_up2_nw<3, 1>(a, RELU, grid, lds, s);
+        default: return launch_up2_nw<4, 1>(a, RELU, grid, lds, s);
+      }
+    }
+  }
   if (big >= 512)
     return launch_fwd_rf<SRC, DST, 4, F32, RELU>(a, nw, dim3((unsigned)((a.M + 255) / 256), gy), nullptr, 0, s);
   return launch_fwd_rf<SRC, DST, 1, F32, RELU>(a, nw, dim3((unsigned)((a.M + 63) / 64), gy), nullptr, 0, s);

@@ -297,6 +297,26 @@ def test_generic_wgrad_with_workspace(torch, kind):
     close(runs[2], want, 2e-5)
 
 
+@pytest.mark.parametrize("coarse,cin,cout", [
+    ((6, 5, 7), 192, 96),    # 6 K steps held in registers, two column tiles, taps spread over blocks
+    ((20, 18, 34), 48, 24),  # 256-row blocks, ragged last block
+    ((9, 8, 10), 96, 48),    # 3 K steps
+])
+def test_up2_forward_sizes(torch, coarse, cin, cout):
+    """The transposed convolution's forward kernel (A fragments held across its
+    8 taps, double-buffered tap weights, tile stored through LDS) against the
+    oracle, written into the second half of a concatenation buffer."""
+    fine = tuple(2 * v for v in coarse)
+    x = bf(rng.normal(size=coarse + (cin,)))
+    w = bf(rng.normal(size=(cout, 8, cin)) * 0.1)
+    b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
+    cat = torch.zeros(fine + (2 * cout,), dtype=torch.bfloat16, device="cuda")
+    nn.forward(nn.IDENT, nn.SCATTER2, rows_of(coarse), 8, cin, cout, dev(torch, x), cin, dev(torch, w), cat, 2 * cout,
+               bias=dev(torch, b, torch.float32), y_offset=cout)
+    close(host(cat)[..., cout:], onn.up2(x, w, b))
+    assert not host(cat)[..., :cout].any()
+
+
 def test_head_dense_fp32_and_backward(torch):
     x = bf(rng.normal(size=GRID + (24,)))
     w = np.zeros((8, 1, 24))
