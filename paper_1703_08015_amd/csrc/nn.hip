@@ -456,24 +456,34 @@ constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = 4;
 constexpr int kHaloX = kBrickX + 2, kHaloY = kBrickY + 2, kHaloZ = kBrickZ + 2;
 constexpr int kHalo = kHaloX * kHaloY * kHaloZ;
 
+// Halo layout in LDS (bf16 units): voxel (hx, hy, hz) at hx * CP + (hy + kHaloY hz) * RP.  A fragment's 16 lanes
+// read 8 voxels of two y-rows in one LDS cycle (64 banks of 4 bytes): the voxel pitch CP is an odd multiple of 4
+// banks, so the 8 voxels of a row take 8 distinct groups of 4 banks, and the row pitch RP is 32 banks modulo 64,
+// so the second row takes the other 8 groups.
 template <int CC>
 struct BrickShape {
   static constexpr int KS = CC == 8 ? 1 : (CC + 31) / 32;  // K steps per tap
-  static constexpr int width = CC == 8 ? 8 : 32 * KS;       // channels read per halo row
-  static constexpr int CP = width + 8 + ((width / 8 + 1) % 2 == 0 ? 8 : 0);  // odd number of 16-byte units
+  static constexpr int width = CC == 32 ? 32 : CC;          // channels staged per halo voxel (8, 24 or 32)
+  static constexpr int CP = CC == 32 ? 40 : 24;             // voxel pitch: 20 or 12 banks
+  static constexpr int RP = CC == 32 ? 448 : 320;           // row pitch: 224 or 160 banks (32 mod 64)
+  static constexpr int ROWS = kHaloY * kHaloZ;
+  static_assert(kHaloX * CP <= RP && (RP / 2) % 64 == 32 && (CP / 2) % 8 == 4, "halo layout");
 };
 
-constexpr int tap_offset(int t) { return (t % 3) + kHaloX * (((t / 3) % 3) + kHaloY * (t / 9)); }
+template <int CC>
+constexpr int tap_off(int t) {
+  return (t % 3) * BrickShape<CC>::CP + (((t / 3) % 3) + kHaloY * (t / 9)) * BrickShape<CC>::RP;
+}
 
 constexpr int kBrickRing8 = 3;  // K steps of weights loaded ahead in the 8-channel form
 
 template <int NW, int CC, bool RELU>
 __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   using BS = BrickShape<CC>;
-  constexpr int CP = BS::CP;
+  constexpr int CP = BS::CP, RP = BS::RP;
   // the output tile reuses the halo's LDS: 256 voxels x (16*NW + 8) bf16
   constexpr int OS = 16 * NW + 8;
-  constexpr int kLds = kHalo * CP > kBrickX * kBrickY * kBrickZ * OS ? kHalo * CP : kBrickX * kBrickY * kBrickZ * OS;
+  constexpr int kLds = BS::ROWS * RP > kBrickX * kBrickY * kBrickZ * OS ? BS::ROWS * RP : kBrickX * kBrickY * kBrickZ * OS;
   __shared__ __attribute__((aligned(16))) bf16 halo[kLds];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, kb = lane >> 4;
@@ -487,7 +497,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   // per-lane LDS element offsets of the four fragments' rows at tap (0,0,0)
   int rowbase[4];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) rowbase[f] = ((r & 7) + kHaloX * ((2 * f + (r >> 3)) + kHaloY * wv)) * CP;
+  for (int f = 0; f < 4; ++f) rowbase[f] = (r & 7) * CP + ((2 * f + (r >> 3)) + kHaloY * wv) * RP;
   // per-lane byte offsets of the weight rows (clamped to a valid output
   // channel) from a uniform base, so each weight load is a scalar base plus
   // a 32-bit lane offset with no per-load address arithmetic
@@ -529,7 +539,10 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
 #pragma unroll
     for (int it = 0; it < NST; ++it) {
       const int e = tid + 256 * it;
-      if (e < kHalo * G) *reinterpret_cast<bf16x8 *>(&halo[(e / G) * CP + 8 * (e % G)]) = v[it];  // zeros past CC
+      if (e < kHalo * G) {
+        const int hv = e / G;
+        *reinterpret_cast<bf16x8 *>(&halo[(hv % kHaloX) * CP + (hv / kHaloX) * RP + 8 * (e % G)]) = v[it];
+      }
     }
     __syncthreads();
     if constexpr (CC == 8) {
@@ -546,8 +559,8 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       static_for<7>([&](auto S) {
         constexpr int sidx = decltype(S)::value, s0 = 4 * sidx, slot = sidx % kBrickRing8;
         const int t = s0 + kb;
-        const int off = kb == 0 ? tap_offset(s0) : kb == 1 ? tap_offset(s0 + 1)
-                      : kb == 2 ? tap_offset(s0 + 2) : tap_offset(s0 + 3 < 27 ? s0 + 3 : 26);
+        const int off = kb == 0 ? tap_off<CC>(s0) : kb == 1 ? tap_off<CC>(s0 + 1)
+                      : kb == 2 ? tap_off<CC>(s0 + 2) : tap_off<CC>(s0 + 3 < 27 ? s0 + 3 : 26);
         const bool tv = t < 27;
         bf16x8 bv[NW];
 #pragma unroll
@@ -557,7 +570,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
         __builtin_amdgcn_sched_barrier(0);  // keep the load here: the scheduler would sink it next to its use
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off * CP]);
+          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[rowbase[f] + off]);
           if (!tv) av = bf16x8{};
 #pragma unroll
           for (int j = 0; j < NW; ++j)
@@ -592,8 +605,8 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       static_for<NSTEP>([&](auto U) {
         constexpr int u = decltype(U)::value, slot = u % R;
         constexpr int k0 = 32 * u, t0 = k0 / 24, cc0 = k0 % 24;
-        constexpr int abase_u = tap_offset(t0) * CP + cc0;
-        constexpr int acarry = t0 < 26 ? (tap_offset(t0 + 1) - tap_offset(t0)) * CP - 24 : 0;
+        constexpr int abase_u = tap_off<CC>(t0) + cc0;
+        constexpr int acarry = t0 < 26 ? tap_off<CC>(t0 + 1) - tap_off<CC>(t0) - 24 : 0;
         const bool cy = cc0 == 0 ? carry0 : (cc0 == 8 ? carry8 : carry16);
         const int aoff = abase + (cy ? acarry : 0) + abase_u;
         bf16x8 bv[NW];
@@ -604,7 +617,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
         const bool zero = u == NSTEP - 1 && k0 + 8 * kb >= 27 * 24;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[(zero ? abase : aoff) + f * 2 * kHaloX * CP]);
+          bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[(zero ? abase : aoff) + f * 2 * RP]);
           if (zero) av = bf16x8{};
 #pragma unroll
           for (int j = 0; j < NW; ++j)
@@ -627,7 +640,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       static_for<R>([&](auto P) { load_w(decltype(P)::value, ring[decltype(P)::value]); });
       static_for<NSTEP>([&](auto U) {
         constexpr int u = decltype(U)::value, t = u / BS::KS, st = u % BS::KS, slot = u % R;
-        constexpr int off = tap_offset(t) * CP;
+        constexpr int off = tap_off<CC>(t);
         bf16x8 bv[NW];
 #pragma unroll
         for (int j = 0; j < NW; ++j) bv[j] = ring[slot][j];
