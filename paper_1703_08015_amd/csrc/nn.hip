@@ -1035,6 +1035,7 @@ __global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(G
 // part*per .. part*per + per - 1 with eight independent partial sums (eight
 // loads in flight) and writes the total into the first of those slots, which
 // only it reads.  Pass 2: thread e adds the parts' totals in order into dw.
+// Pass 0 (at most per blocks): pass 1's sum of all blocks, added into dw.
 __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int blocks, int per, int cf, int nf,
                                                    int cblocks, int slot_taps, int taps, int cin, int cout, float *dw,
                                                    int pass) {
@@ -1042,8 +1043,9 @@ __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int b
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= E) return;
   const int parts = (blocks + per - 1) / per;
-  if (pass == 1) {
-    const int tile = blockIdx.y / parts, part = blockIdx.y % parts;
+  float sum = 0.f;
+  if (pass != 2) {
+    const int tile = pass == 1 ? blockIdx.y / parts : blockIdx.y, part = pass == 1 ? blockIdx.y % parts : 0;
     float *p = ws + ((int64_t)tile * blocks + (int64_t)part * per) * E + e;
     const int n = min(per, blocks - part * per);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1052,8 +1054,11 @@ __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int b
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += p[(int64_t)(b + k) * E];
     for (; b < n; ++b) acc[0] += p[(int64_t)b * E];
-    p[0] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    return;
+    sum = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    if (pass == 1) {
+      p[0] = sum;
+      return;
+    }
   }
   const int tile = blockIdx.y;
   const int nl = e % (16 * nf), cl = (e / (16 * nf)) % (16 * cf), ts = e / (256 * cf * nf);
@@ -1061,16 +1066,23 @@ __global__ void __launch_bounds__(256) k_wgrad_sum(float *__restrict__ ws, int b
   const int t = slot_taps == taps ? ts : tile % taps;
   const int c = (ct % cblocks) * 16 * cf + cl, n = (ct / cblocks) * 16 * nf + nl;
   if (c >= cin || n >= cout) return;
-  const float *p = ws + (int64_t)tile * blocks * E + e;
-  float sum = 0.f;
-  for (int q = 0; q < parts; ++q) sum += p[(int64_t)q * per * E];
+  if (pass == 2) {
+    const float *p = ws + (int64_t)tile * blocks * E + e;
+    for (int q = 0; q < parts; ++q) sum += p[(int64_t)q * per * E];
+  }
   dw[((int64_t)n * taps + t) * cin + c] += sum;
 }
 
-// both passes of k_wgrad_sum over `tiles` tiles of `blocks` slots each
+// k_wgrad_sum over `tiles` tiles of `blocks` slots each: one pass for at most
+// 32 blocks, else two
 hipError_t launch_wgrad_sum(float *ws, int64_t blocks, int64_t tiles, int cf, int nf, int cblocks, int slot_taps,
                             int taps, int cin, int cout, float *dw, hipStream_t s) {
   const int E = slot_taps * 256 * cf * nf, per = 32, parts = (int)((blocks + per - 1) / per);
+  if (parts == 1) {
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,
+                       (int)blocks, per, cf, nf, cblocks, slot_taps, taps, cin, cout, dw, 0);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)(tiles * parts)), dim3(256), 0, s, ws,
                      (int)blocks, per, cf, nf, cblocks, slot_taps, taps, cin, cout, dw, 1);
   hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,

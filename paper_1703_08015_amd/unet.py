@@ -69,8 +69,31 @@ class UNet:
         self.params += [p for pair in self.up for p in pair]
         self.params += [p for lvl in self.dec for pair in lvl for p in pair]
         self.params += list(self.head)
+        self._flatten()
         self.step_count = 0
         self._cache = None
+
+    def _flatten(self):
+        """Every parameter's master weights, moments, gradient and BF16 copy
+        become views into five flat buffers (segments padded to 8 elements, so
+        every BF16 view stays 16-byte aligned): one Adam launch and one
+        gradient clear cover the whole network."""
+        t = self.torch
+        offs, n = [], 0
+        for p in self.params:
+            offs.append(n)
+            n += (p.p.numel() + 7) // 8 * 8
+        flat = {k: t.zeros(n, dtype=t.float32, device=self.device) for k in ("p", "m", "v", "g")}
+        for p, o in zip(self.params, offs):
+            flat["p"][o:o + p.p.numel()].copy_(p.p.reshape(-1))
+        p16 = flat["p"].to(t.bfloat16)
+        for p, o in zip(self.params, offs):
+            k = p.p.numel()
+            shape = p.p.shape
+            p.p, p.m, p.v, p.g = (flat[name][o:o + k].view(shape) for name in ("p", "m", "v", "g"))
+            if p.b16 is not None:
+                p.b16 = p16[o:o + k].view(shape)
+        self._flat, self._p16 = flat, p16
 
     # ---- force-linear head -----------------------------------------------------
     def forward_mixed(self, x, direction):
@@ -279,13 +302,14 @@ class UNet:
         return self._gcache[1]
 
     def zero_grad(self):
-        for p in self.params:
-            p.g.zero_()
+        self._flat["g"].zero_()
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam update of every parameter (a single launch over the flat
+        buffers; the BF16 copies, biases' included, are refreshed with it)."""
         self.step_count += 1
-        for p in self.params:
-            nn.adam(p.p, p.m, p.v, p.g, p.b16, lr, self.step_count, beta1, beta2, eps)
+        f = self._flat
+        nn.adam(f["p"], f["m"], f["v"], f["g"], self._p16, lr, self.step_count, beta1, beta2, eps)
 
     # ---- state -------------------------------------------------------------------
     def state_dict(self):
