@@ -110,6 +110,17 @@ int64_t lbm_nn_wgrad_workspace(const lbm_nn_gemm *g);
 int lbm_nn_backward_weights(int32_t mode, int32_t taps, int32_t cin, int32_t cout, const void *w, void *wt,
                             void *stream);
 
+/* lbm_nn_backward_weights for up to LBM_NN_WT_JOBS_MAX layers in one launch
+ * (mode, taps, cin, cout, w and wt as there; the jobs are read on the host and
+ * the array may be reused when the call returns). */
+#define LBM_NN_WT_JOBS_MAX 48
+typedef struct {
+  int32_t mode, taps, cin, cout;
+  const void *w;
+  void *wt;
+} lbm_nn_wt_job;
+int lbm_nn_backward_weights_batch(int32_t count, const lbm_nn_wt_job *jobs, void *stream);
+
 /* 2x2x2 max pooling of x (fine grid 2*grid, stride ldx) into y (grid, ldy);
  * arg (uint8 per output element, c fastest over `channels`) records the
  * winning corner.  Backward: dx (fine grid, ldx) receives dy at each window's

@@ -1143,6 +1143,31 @@ __global__ void __launch_bounds__(256) k_colsum(const bf16 *y, int64_t rows, int
   }
 }
 
+// Several layers' backward-data weights in one launch: jobs in the kernel
+// argument, block b works on the job whose block range [first, first + blocks)
+// holds it.
+struct WtJobs {
+  lbm_nn_wt_job job[LBM_NN_WT_JOBS_MAX];
+  int first[LBM_NN_WT_JOBS_MAX + 1];
+  int count;
+};
+
+__global__ void __launch_bounds__(256) k_backward_weights_batch(WtJobs J) {
+  int j = 0;
+  while (j + 1 < J.count && (int)blockIdx.x >= J.first[j + 1]) ++j;
+  const lbm_nn_wt_job &b = J.job[j];
+  const int taps = b.taps, cin = b.cin, cout = b.cout;
+  const int64_t total = (int64_t)taps * cin * cout;
+  const int64_t e = (int64_t)(blockIdx.x - J.first[j]) * 256 + threadIdx.x;
+  if (e >= total) return;
+  // e indexes wt[c][t*cout + n]
+  const int c = (int)(e / ((int64_t)taps * cout));
+  const int rem = (int)(e % ((int64_t)taps * cout));
+  const int t = rem / cout, n = rem % cout;
+  const int ts = b.mode == LBM_NN_CONV3 ? (taps - 1 - t) : t;
+  static_cast<bf16 *>(b.wt)[e] = static_cast<const bf16 *>(b.w)[(int64_t)n * taps * cin + (int64_t)ts * cin + c];
+}
+
 __global__ void k_backward_weights(int mode, int taps, int cin, int cout, const bf16 *w, bf16 *wt) {
   const int64_t total = (int64_t)taps * cin * cout;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -1938,6 +1963,30 @@ extern "C" int64_t lbm_nn_wgrad_workspace(const lbm_nn_gemm *g) {
 extern "C" int lbm_nn_wgrad_ws(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int64_t ws_floats,
                                void *stream) {
   return wgrad_impl(g, dw, db, ws, ws_floats, stream);
+}
+
+extern "C" int lbm_nn_backward_weights_batch(int32_t count, const lbm_nn_wt_job *jobs, void *stream) {
+  if (count < 0 || count > LBM_NN_WT_JOBS_MAX || (count > 0 && !jobs))
+    return set_error(LBM_ERR_ARG, "lbm_nn_backward_weights_batch: %d jobs (at most %d)", count, LBM_NN_WT_JOBS_MAX);
+  WtJobs J{};
+  int64_t blocks = 0;
+  for (int j = 0; j < count; ++j) {
+    const lbm_nn_wt_job &b = jobs[j];
+    if (!b.w || !b.wt || b.taps <= 0 || b.cin <= 0 || b.cout <= 0 ||
+        (b.mode != LBM_NN_CONV3 && b.mode != LBM_NN_SCATTER2 && b.mode != LBM_NN_IDENT) ||
+        (b.mode == LBM_NN_CONV3 && b.taps != 27))
+      return set_error(LBM_ERR_ARG, "lbm_nn_backward_weights_batch: job %d", j);
+    J.job[j] = b;
+    J.first[j] = (int)blocks;
+    blocks += ((int64_t)b.taps * b.cin * b.cout + 255) / 256;
+    if (blocks > INT32_MAX) return set_error(LBM_ERR_SHAPE, "lbm_nn_backward_weights_batch: too many weights");
+  }
+  J.first[count] = (int)blocks;
+  J.count = count;
+  if (blocks == 0) return LBM_OK;
+  hipLaunchKernelGGL(k_backward_weights_batch, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), J);
+  NN_TRY(hipGetLastError());
+  return LBM_OK;
 }
 
 extern "C" int lbm_nn_backward_weights(int32_t mode, int32_t taps, int32_t cin, int32_t cout, const void *w, void *wt,

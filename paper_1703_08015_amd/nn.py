@@ -23,6 +23,11 @@ class Gemm(ctypes.Structure):
     ]
 
 
+class WtJob(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("taps", ctypes.c_int32), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32),
+                ("w", ctypes.c_void_p), ("wt", ctypes.c_void_p)]
+
+
 _sigs_done = False
 
 
@@ -38,6 +43,7 @@ def _lib():
             "lbm_nn_wgrad": [G, P, P, P],
             "lbm_nn_wgrad_ws": [G, P, P, P, I64, P],
             "lbm_nn_backward_weights": [I32, I32, I32, I32, P, P, P],
+            "lbm_nn_backward_weights_batch": [I32, ctypes.POINTER(WtJob), P],
             "lbm_nn_maxpool2": [P, I32, P, I32, P, I32, P, P],
             "lbm_nn_maxpool2_backward": [P, I32, P, I32, P, P, I32, I32, P],
             "lbm_nn_relu_backward": [I64, I32, P, I32, P, I32, P],
@@ -139,6 +145,15 @@ def wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy):
     if n < 0:
         raise LbmError(-1, "lbm_nn_wgrad_workspace", "invalid layer")
     return n
+
+
+def backward_weights_batch(jobs, stream=None):
+    """jobs: (mode, taps, cin, cout, w, wt) tuples; one launch for all."""
+    arr = (WtJob * max(len(jobs), 1))()
+    for k, (mode, taps, cin, cout, w, wt) in enumerate(jobs):
+        arr[k].mode, arr[k].taps, arr[k].cin, arr[k].cout = mode, taps, cin, cout
+        arr[k].w, arr[k].wt = w.data_ptr(), wt.data_ptr()
+    _check(_lib().lbm_nn_backward_weights_batch(len(jobs), arr, _stream(stream)), "lbm_nn_backward_weights_batch")
 
 
 def backward_weights(mode, taps, cin, cout, w, wt, stream=None):

@@ -222,14 +222,38 @@ class UNet:
         return self._shared_ws(nn.wgrad_workspace(src, dst, rows, taps, cin, cout, ldx, lddy))
 
     def _wt(self, w, mode, taps, cin, cout):
+        """The backward-data weights of a layer, as refreshed by _refresh_wt."""
+        return self._wt_cache[("wt", id(w))]
+
+    def _wt_layers(self):
+        """(weights, mode, taps, cin, cout) of every layer whose backward-data
+        pass runs (all but the first convolution)."""
+        L, C = self.L, self.C
+        out = [(self.head[0], nn.IDENT, 1, C[0], self.out_pad)]
+        for l in range(L - 1):
+            idx = L - 2 - l
+            (w1, _), (w2, _) = self.dec[idx]
+            out += [(w2, nn.CONV3, 27, C[l], C[l]),
+                    (w1, nn.CONV3, 27, 2 * C[l], C[l]), (self.up[idx][0], nn.SCATTER2, 8, C[l + 1], C[l])]
+        for l in range(L):
+            (w1, _), (w2, _) = self.enc[l]
+            out.append((w2, nn.CONV3, 27, C[l], C[l]))
+            if l > 0:
+                out.append((w1, nn.CONV3, 27, C[l - 1], C[l]))
+        return out
+
+    def _refresh_wt(self):
+        """Every layer's backward-data weights from the current BF16 weights,
+        in one launch."""
         t = self.torch
-        key = ("wt", id(w))
-        buf = self._wt_cache.get(key)
-        if buf is None:
-            buf = t.empty((cin, taps, cout), dtype=t.bfloat16, device=self.device)
-            self._wt_cache[key] = buf
-        nn.backward_weights(mode, taps, cin, cout, w.b16, buf)
-        return buf
+        jobs = []
+        for w, mode, taps, cin, cout in self._wt_layers():
+            key = ("wt", id(w))
+            buf = self._wt_cache.get(key)
+            if buf is None:
+                buf = self._wt_cache[key] = t.empty((cin, taps, cout), dtype=t.bfloat16, device=self.device)
+            jobs.append((mode, taps, cin, cout, w.b16, buf))
+        nn.backward_weights_batch(jobs)
 
     def backward(self, dout):
         """dout: BF16 (nz, ny, nx, out_pad) gradient of the loss wrt the head
@@ -242,6 +266,7 @@ class UNet:
         L, C = self.L, self.C
         if not hasattr(self, "_wt_cache"):
             self._wt_cache = {}
+        self._refresh_wt()
         G = self._grads(A, grids)
         hw, hb = self.head
         rows0 = self._rows(grids[0])

@@ -317,6 +317,27 @@ def test_up2_forward_sizes(torch, coarse, cin, cout):
     assert not host(cat)[..., :cout].any()
 
 
+def test_backward_weights_batch(torch):
+    """Several layers' backward-data weights in one launch equal the one-layer
+    calls bit for bit (3x3x3, transposed and 1x1 layers of different sizes)."""
+    specs = [(nn.CONV3, 27, 24, 48), (nn.SCATTER2, 8, 96, 48), (nn.IDENT, 1, 24, 16), (nn.CONV3, 27, 8, 24),
+             (nn.CONV3, 27, 192, 192)]
+    jobs, want = [], []
+    for mode, taps, cin, cout in specs:
+        w = dev(torch, bf(rng.normal(size=(cout, taps, cin))))
+        a = torch.empty((cin, taps, cout), dtype=torch.bfloat16, device="cuda")
+        b = torch.empty_like(a)
+        nn.backward_weights(mode, taps, cin, cout, w, a)
+        jobs.append((mode, taps, cin, cout, w, b))
+        want.append(a)
+    nn.backward_weights_batch(jobs)
+    torch.cuda.synchronize()
+    for (_, _, _, _, _, b), a in zip(jobs, want):
+        assert torch.equal(a.view(torch.int16), b.view(torch.int16))
+    with pytest.raises(nn.LbmError):
+        nn.backward_weights_batch([(nn.CONV3, 8, 24, 24, jobs[0][4], jobs[0][5])])
+
+
 def test_head_dense_fp32_and_backward(torch):
     x = bf(rng.normal(size=GRID + (24,)))
     w = np.zeros((8, 1, 24))
