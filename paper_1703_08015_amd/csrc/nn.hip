@@ -516,14 +516,25 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
 
   constexpr int G = BS::width / 8;                 // 16-byte groups per halo row that are read
   constexpr int NST = (kHalo * G + 255) / 256;     // staging loads per thread
+  // element offsets of the halo's wrapped rows (hy, hz) and columns hx, once
+  // per block, so that a staging entry's input row is a sum of two table
+  // entries instead of three wraps and a 64-bit index product per entry
+  __shared__ int64_t hrow[kHaloY * kHaloZ], hcol[kHaloX];
+  if (tid < kHaloY * kHaloZ) {
+    const int hy = tid % kHaloY, hz = tid / kHaloY;
+    hrow[tid] = ((int64_t)wrap(oy + hy - 1, g.ny) + (int64_t)g.ny * wrap(oz + hz - 1, g.nz)) * g.nx * a.ldx;
+  } else if (tid < kHaloY * kHaloZ + kHaloX) {
+    const int hx = tid - kHaloY * kHaloZ;
+    hcol[hx] = (int64_t)wrap(ox + hx - 1, g.nx) * a.ldx;
+  }
+  __syncthreads();
   // input row of each of this thread's staging entries (the same for every chunk)
   int64_t srow[NST];
 #pragma unroll
   for (int it = 0; it < NST; ++it) {
     const int e = tid + 256 * it;
-    const int hv = e / G;
-    const int hx = hv % kHaloX, hy = (hv / kHaloX) % kHaloY, hz = hv / (kHaloX * kHaloY);
-    srow[it] = vidx(wrap(ox + hx - 1, g.nx), wrap(oy + hy - 1, g.ny), wrap(oz + hz - 1, g.nz), g) * a.ldx;
+    const int hv = min(e / G, kHalo - 1);  // entries past the halo load nothing
+    srow[it] = hrow[hv / kHaloX] + hcol[hv % kHaloX];
   }
   for (int c0 = 0; c0 < a.cin; c0 += CC) {
     // issue every staging load of the chunk before the first LDS store
