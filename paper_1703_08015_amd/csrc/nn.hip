@@ -705,11 +705,31 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
   }
 }
 
-// ---- weight gradient: voxels are the reduction; LDS transposes the tiles ----
+// The transposing LDS load of gfx950 (ds_read_b64_tr_b16): in each group of
+// 16 lanes, lane L supplies the address of 4 consecutive bf16, here channels
+// 4 (L % 4) .. 4 (L % 4) + 3 of row L / 4 of a [row][channel] tile, and lane j
+// receives element r of it from lane 4 r + j / 4, element j % 4: channel j of
+// rows 0-3.  Two such loads give a lane the 8 K values of one MFMA operand row.
+typedef short v4s16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s16 lds_v4s16;
+
+// The 8 K values of one MFMA operand row from two transposing LDS loads: p0
+// and p1 are this lane's addresses for voxels 0-3 and 4-7 of its K group.
+__device__ __forceinline__ bf16x8 tr_load8(const bf16 *p0, const bf16 *p1) {
+  const v4s16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p0));
+  const v4s16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p1));
+  typedef short v8s16 __attribute__((ext_vector_type(8)));
+  const v8s16 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// ---- weight gradient: voxels are the reduction ------------------------------
 // Block: tap t, 16*CF input channels, 16*NF output channels, a voxel chunk.
-// Each wavefront stages 32 voxels of x and dy as [channel][voxel] in LDS and
-// runs CF x NF MFMAs; the four wavefronts' sums meet in LDS, then one FP32
-// atomic add per weight.
+// Each wavefront stages 32 voxels of x and dy in LDS as they are stored
+// ([voxel][channel], 16-byte writes) and reads its MFMA operands with the
+// transposing LDS load (tr_load8: channel r of the 8 voxels of K group kb); it
+// runs CF x NF MFMAs per 32 voxels, and the four wavefronts' sums meet in LDS
+// at the end.
 constexpr int kWgradPad = 8;  // bf16 of padding per LDS row
 
 // 32-bit row -> voxel maps (grids are checked to hold fewer than 2^31 rows)
@@ -745,11 +765,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // rows are loaded into registers while the current MFMAs run.
 template <int SRC, int DST, int CF, int NF>
 __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks, float *ws) {
-  __shared__ __attribute__((aligned(16))) bf16 sx[4][16 * CF][32 + kWgradPad];
-  __shared__ __attribute__((aligned(16))) bf16 sy[4][16 * NF][32 + kWgradPad];
+  __shared__ __attribute__((aligned(16))) bf16 sx[4][32][16 * CF + kWgradPad];
+  __shared__ __attribute__((aligned(16))) bf16 sy[4][32][16 * NF + kWgradPad];
   __shared__ float red[4][16 * CF][16 * NF + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, kb = lane >> 4;
+  // transposing loads: this lane supplies voxel 8 kb + tv (and + 4), channels 4 tq ..
+  const int tv = r >> 2, tq = r & 3;
   const int t = blockIdx.y % a.taps, cb = blockIdx.y / a.taps, nb = blockIdx.z;
   const int cbase = cb * 16 * CF, nbase = nb * 16 * NF;
   const int64_t v0 = (int64_t)blockIdx.x * chunk;
@@ -787,23 +809,20 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
   if (v0 < v1) load(v0, xv, yv);
   for (int64_t vb = v0; vb < v1; vb += 128) {
 #pragma unroll
-    for (int g = 0; g < CF; ++g)
+    for (int g = 0; g < CF; ++g) *reinterpret_cast<bf16x8 *>(&sx[wv][vl][8 * (g0 + 2 * g)]) = xv[g];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sx[wv][8 * (g0 + 2 * g) + q][vl] = xv[g][q];
-#pragma unroll
-    for (int g = 0; g < NF; ++g)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) sy[wv][8 * (g0 + 2 * g) + q][vl] = yv[g][q];
+    for (int g = 0; g < NF; ++g) *reinterpret_cast<bf16x8 *>(&sy[wv][vl][8 * (g0 + 2 * g)]) = yv[g];
     wave_lds_sync();
     if (vb + 128 < v1) load(vb + 128, xv, yv);  // in flight during the MFMAs
+    bf16x8 bv[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+      bv[j] = tr_load8(&sy[wv][8 * kb + tv][16 * j + 4 * tq], &sy[wv][8 * kb + 4 + tv][16 * j + 4 * tq]);
 #pragma unroll
     for (int i = 0; i < CF; ++i) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sx[wv][16 * i + r][8 * kb]);
+      const bf16x8 av = tr_load8(&sx[wv][8 * kb + tv][16 * i + 4 * tq], &sx[wv][8 * kb + 4 + tv][16 * i + 4 * tq]);
 #pragma unroll
-      for (int j = 0; j < NF; ++j) {
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sy[wv][16 * j + r][8 * kb]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
-      }
+      for (int j = 0; j < NF; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
     }
     wave_lds_sync();  // this wave's reads are done before its next staging
   }
@@ -871,18 +890,6 @@ struct WBrick {
   static constexpr int LDS = (kWHalo * PX + kWbX * kWbY * kWbZ * PY) * 2;  // bytes
 };
 
-typedef short v4s16 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) v4s16 lds_v4s16;
-
-// The 8 K values of one MFMA operand row from two transposing LDS loads: p0
-// and p1 are this lane's addresses for voxels 0-3 and 4-7 of its K group.
-__device__ __forceinline__ bf16x8 tr_load8(const bf16 *p0, const bf16 *p1) {
-  const v4s16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p0));
-  const v4s16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s16 *)(p1));
-  typedef short v8s16 __attribute__((ext_vector_type(8)));
-  const v8s16 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-  return __builtin_bit_cast(bf16x8, v);
-}
 
 template <int CF, int NF>
 __global__ void __launch_bounds__((CF * NF <= 4 ? 256 : 512), 2) k_wgrad_brick(GemmArgs a, float *dw, int bricks_per_block,
