@@ -478,7 +478,7 @@ constexpr int tap_off(int t) {
 constexpr int kBrickRing8 = 3;  // K steps of weights loaded ahead in the 8-channel form
 
 template <int NW, int CC, bool RELU>
-__global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
+__global__ void __launch_bounds__(256, (NW <= 2 ? 4 : 2)) k_conv3_brick(GemmArgs a) {
   using BS = BrickShape<CC>;
   constexpr int CP = BS::CP, RP = BS::RP;
   // the output tile reuses the halo's LDS: 256 voxels x (16*NW + 8) bf16
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(256) k_conv3_brick(GemmArgs a) {
       const bool carry8 = kb >= 2, carry16 = kb >= 1, carry0 = kb >= 3;  // carry for c0 = 8, 16, 0
       const int abase = rowbase[0] + 8 * kb;
       const uint32_t wlane = 16u * (uint32_t)kb, wcarry = (uint32_t)(a.cin - 24) * 2u;
-      constexpr int R = NW <= 2 ? 6 : 3;
+      constexpr int R = 3;
       bf16x8 ring[R][NW];
       auto load_w = [&](auto U, bf16x8(&dst)[NW]) {
         constexpr int k0 = 32 * decltype(U)::value, t0 = k0 / 24, cc0 = k0 % 24;
