@@ -88,7 +88,7 @@ int64_t lbm_nn_forward_workspace(const lbm_nn_gemm *g);
  * FP32 [cout][taps*cin] accumulator (not cleared); g->w and g->bias unused.
  * If db is not NULL it accumulates the bias gradient, the sum of dy[v][n]
  * over every output voxel v (for SCATTER2 all 8 fine voxels of each coarse
- * one); at most 2048 output channels then (else LBM_ERR_SHAPE). */
+ * one), in the same kernel (one FP32 atomic add per block and channel). */
 int lbm_nn_wgrad(const lbm_nn_gemm *g, float *dw, float *db, void *stream);
 
 /* lbm_nn_wgrad with a caller workspace: each block of the weight-gradient

@@ -764,15 +764,24 @@ __device__ __forceinline__ void wave_lds_sync() {
 // the wave, so only wave-level synchronisation), and the next iteration's
 // rows are loaded into registers while the current MFMAs run.
 template <int SRC, int DST, int CF, int NF>
-__global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks, float *ws) {
+__global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t chunk, int cblocks, float *ws,
+                                               float *db) {
   __shared__ __attribute__((aligned(16))) bf16 sx[4][32][16 * CF + kWgradPad];
   __shared__ __attribute__((aligned(16))) bf16 sy[4][32][16 * NF + kWgradPad];
   __shared__ float red[4][16 * CF][16 * NF + 1];
+  __shared__ float bred[4][16 * NF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, kb = lane >> 4;
   // transposing loads: this lane supplies voxel 8 kb + tv (and + 4), channels 4 tq ..
   const int tv = r >> 2, tq = r & 3;
   const int t = blockIdx.y % a.taps, cb = blockIdx.y / a.taps, nb = blockIdx.z;
+  // bias gradient (with db): the blocks of the first input-channel tile sum
+  // their dy rows, each output row once (every tap of a scatter writes its own
+  // fine voxels; the other layers' taps share one output row)
+  const bool bias = db && cb == 0 && (DST == LBM_NN_SCATTER2 || t == 0);
+  float bsum[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) bsum[j] = 0.f;
   const int cbase = cb * 16 * CF, nbase = nb * 16 * NF;
   const int64_t v0 = (int64_t)blockIdx.x * chunk;
   int64_t v1 = v0 + chunk;
@@ -818,6 +827,11 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
 #pragma unroll
     for (int j = 0; j < NF; ++j)
       bv[j] = tr_load8(&sy[wv][8 * kb + tv][16 * j + 4 * tq], &sy[wv][8 * kb + 4 + tv][16 * j + 4 * tq]);
+    if (bias)  // lane (r, kb) holds channel 16 j + r of the 8 voxels of K group kb
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bsum[j] += (float)bv[j][q];
 #pragma unroll
     for (int i = 0; i < CF; ++i) {
       const bf16x8 av = tr_load8(&sx[wv][8 * kb + tv][16 * i + 4 * tq], &sx[wv][8 * kb + 4 + tv][16 * i + 4 * tq]);
@@ -833,7 +847,19 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
     for (int j = 0; j < NF; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wv][16 * i + 4 * kb + q][16 * j + r] = acc[i][j][q];
+  if (bias) {  // (uniform per block) the K groups, then the wavefronts, meet; one atomic add per channel
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      float v = bsum[j];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (kb == 0) bred[wv][16 * j + r] = v;
+    }
+  }
   __syncthreads();
+  if (bias && threadIdx.x < 16 * NF && nbase + (int)threadIdx.x < a.cout)
+    atomicAdd(db + nbase + threadIdx.x, (bred[0][threadIdx.x] + bred[1][threadIdx.x]) +
+                                            (bred[2][threadIdx.x] + bred[3][threadIdx.x]));
   // the block's sums: with a workspace into its own slot [16*CF][16*NF] (slots
   // ordered [tile = (nb, cb, t)][chunk]; k_wgrad_sum adds the chunks in a fixed
   // order), else one FP32 atomic add per weight
@@ -1106,59 +1132,6 @@ hipError_t launch_wgrad_sum(float *ws, int64_t blocks, int64_t tiles, int cf, in
   hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((E + 255) / 256), (unsigned)tiles), dim3(256), 0, s, ws,
                      (int)blocks, per, cf, nf, cblocks, slot_taps, taps, cin, cout, dw, 2);
   return hipGetLastError();
-}
-
-// bias gradient: db[n] += sum over rows of dy[row][n], a column sum of a
-// (rows x ld) BF16 matrix.  For SCATTER2 every fine output voxel is exactly
-// one (coarse voxel, tap) pair, so the rows are simply all output voxels.
-// Thread t reads 8 channels (one 16-byte load) of rows r0 + k * RP, where the
-// block's 256 threads form RP row lanes x CG channel groups; the row lanes
-// meet in LDS and one atomic per channel and block adds the total.
-__global__ void __launch_bounds__(256) k_colsum(const bf16 *y, int64_t rows, int ld, int cols, float *db,
-                                                int64_t chunk) {
-  const int cg_count = (cols + 7) / 8;
-  const int rp = 256 / cg_count;  // row lanes per block (cols <= 2048)
-  const int t = threadIdx.x;
-  const int lane_row = t / cg_count, cg = t % cg_count;
-  __shared__ float red[256][8];
-  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const int64_t r0 = (int64_t)blockIdx.x * chunk;
-  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
-  if (lane_row < rp) {
-    const int c = 8 * cg;
-    int64_t r = r0 + lane_row;
-    if (c + 8 <= cols) {
-      // four rows' loads in flight per iteration
-      for (; r + 3 * rp < r1; r += 4 * rp) {
-        bf16x8 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const bf16x8 *>(y + (r + u * rp) * ld + c);
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc[q] += (float)v[u][q];
-      }
-    }
-    for (; r < r1; r += rp) {
-      const bf16 *row = y + r * ld + c;
-      if (c + 8 <= cols) {
-        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(row);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += (float)v[q];
-      } else {
-        for (int q = 0; q < cols - c; ++q) acc[q] += (float)row[q];
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q) red[t][q] = acc[q];
-  __syncthreads();
-  for (int ch = t; ch < cols; ch += 256) {
-    const int g = ch / 8, q = ch % 8;
-    float sum = 0.f;
-    for (int l = 0; l < rp; ++l) sum += red[l * cg_count + g][q];
-    atomicAdd(db + ch, sum);
-  }
 }
 
 // Several layers' backward-data weights in one launch: jobs in the kernel
@@ -1759,11 +1732,11 @@ int64_t generic_wgrad_ws_floats(const GemmArgs &a) {
 }
 
 template <int SRC, int DST, int CF, int NF>
-hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+hipError_t launch_wgrad_cf(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s) {
   const GenericWgradGrid w = generic_wgrad_grid(a, CF, NF);
   hipLaunchKernelGGL((k_wgrad<SRC, DST, CF, NF>), dim3((unsigned)w.chunks, (unsigned)(a.taps * w.cblocks),
                                                        (unsigned)w.nblocks),
-                     dim3(256), 0, s, a, dw, w.chunk, w.cblocks, ws);
+                     dim3(256), 0, s, a, dw, w.chunk, w.cblocks, ws, db);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !ws) return e;
   return launch_wgrad_sum(ws, w.chunks, (int64_t)a.taps * w.cblocks * w.nblocks, CF, NF, w.cblocks, 1, a.taps, a.cin,
@@ -1865,14 +1838,15 @@ bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, float *db, hipStre
   return true;
 }
 
+// the generic weight gradient; db (or NULL): the bias gradient, summed in the same kernel
 template <int SRC, int DST>
-hipError_t launch_wgrad(const GemmArgs &a, float *dw, float *ws, hipStream_t s) {
+hipError_t launch_wgrad(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s) {
   int cf, nf;
   generic_wgrad_frags(a, &cf, &nf);
-  if (cf == 1 && nf == 1) return launch_wgrad_cf<SRC, DST, 1, 1>(a, dw, ws, s);
-  if (cf == 1) return launch_wgrad_cf<SRC, DST, 1, 2>(a, dw, ws, s);
-  if (nf == 1) return launch_wgrad_cf<SRC, DST, 2, 1>(a, dw, ws, s);
-  return launch_wgrad_cf<SRC, DST, 2, 2>(a, dw, ws, s);
+  if (cf == 1 && nf == 1) return launch_wgrad_cf<SRC, DST, 1, 1>(a, dw, ws, db, s);
+  if (cf == 1) return launch_wgrad_cf<SRC, DST, 1, 2>(a, dw, ws, db, s);
+  if (nf == 1) return launch_wgrad_cf<SRC, DST, 2, 1>(a, dw, ws, db, s);
+  return launch_wgrad_cf<SRC, DST, 2, 2>(a, dw, ws, db, s);
 }
 
 // workspace floats of lbm_nn_wgrad_ws for a layer (the brick kernel's where it applies)
@@ -1937,34 +1911,19 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
       return set_error(LBM_ERR_ARG, "lbm_nn_wgrad_ws: workspace of %lld floats, %lld needed", (long long)ws_floats,
                        (long long)need);
   }
-  if (db && g->cout > 2048) return set_error(LBM_ERR_SHAPE, "lbm_nn_wgrad: bias gradient of %d > 2048 channels", g->cout);
   const GemmArgs a = to_args(g);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // the bias gradient is summed inside the weight-gradient kernels
   if (g->dst_mode == LBM_NN_SCATTER2) {
-    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, ws, s)));
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, ws, db, s)));
   } else if (g->src_mode == LBM_NN_CONV3) {
     hipError_t e = hipSuccess;
-    if (try_wgrad_brick(a, dw, ws, db, s, &e))
-      db = nullptr;  // done with the weights
-    else
-      e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, s);
+    if (!try_wgrad_brick(a, dw, ws, db, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, db, s);
     NN_TRY(e);
   } else if (g->src_mode == LBM_NN_GATHER2) {
-    NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, ws, s)));
+    NN_TRY((launch_wgrad<LBM_NN_GATHER2, LBM_NN_IDENT>(a, dw, ws, db, s)));
   } else {
-    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, ws, s)));
-  }
-  if (db) {
-    // all output voxels: M rows, or M * 8 fine voxels of a 2x2x2 transposed convolution
-    const int64_t rows = g->dst_mode == LBM_NN_SCATTER2 ? (int64_t)a.out_grid.nx * a.out_grid.ny * a.out_grid.nz : a.M;
-    // about 512 blocks (fewer atomic adds on the same channels; each block
-    // keeps four rows' loads in flight per lane) of at least 256 rows
-    int64_t chunk = (rows + 511) / 512;
-    if (chunk < 256) chunk = 256;
-    const unsigned gx = (unsigned)((rows + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_colsum, dim3(gx), dim3(256), 0, s, static_cast<const bf16 *>(a.y), rows, a.ldy, a.cout, db,
-                       chunk);
-    NN_TRY(hipGetLastError());
+    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_IDENT>(a, dw, ws, db, s)));
   }
   return LBM_OK;
 }

@@ -288,10 +288,13 @@ def test_generic_wgrad_with_workspace(torch, kind):
     ws = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
     X, DY = dev(torch, x), dev(torch, dy)
     runs = []
+    want_db = dy.reshape(-1, cout).sum(axis=0)  # every output row once
     for w_s in (ws, ws, None):
         dw = torch.zeros((cout, taps, cin), dtype=torch.float32, device="cuda")
-        nn.wgrad(src, dst, grid, taps, cin, cout, X, cin, DY, cout, dw, ws=w_s)
+        db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+        nn.wgrad(src, dst, grid, taps, cin, cout, X, cin, DY, cout, dw, db, ws=w_s)
         runs.append(host(dw))
+        close(host(db), want_db, 2e-5)
     close(runs[0], want, 2e-5)
     assert np.array_equal(runs[0], runs[1])
     close(runs[2], want, 2e-5)
