@@ -879,6 +879,125 @@ __global__ void __launch_bounds__(256) k_wgrad(GemmArgs a, float *dw, int64_t ch
   }
 }
 
+// ---- weight gradient of the transposed 2x2x2 stride-2 convolution ----------
+// dW[n][t][c] += sum over coarse rows m of x[m][c] * dy[fine(m, t)][n].  A
+// block of 8 wavefronts takes a chunk of coarse rows and one channel tile;
+// wavefront w computes tap w.  Per 64 rows the block stages the x rows once in
+// LDS (shared by the 8 taps) and each wavefront its own tap's dy rows, both as
+// stored, and reads the MFMA operands with the transposing load.  So x is read
+// once instead of once per tap.  Partial sums as in k_wgrad_brick (slot
+// [8][16*CF][16*NF] per block) or FP32 atomics; with db the bias gradient too.
+template <int CF, int NF>
+__global__ void __launch_bounds__(512) k_wgrad_up2(GemmArgs a, float *dw, int chunk, int cblocks, float *ws,
+                                                   float *db) {
+  constexpr int V = 64, PX = 16 * CF + 8, PY = 16 * NF + 8;
+  constexpr int NX = (V * 2 * CF + 511) / 512, NY = 2 * NF;  // x loads per thread (block), dy loads per lane (wave)
+  __shared__ __attribute__((aligned(16))) bf16 sx[V * PX];
+  __shared__ __attribute__((aligned(16))) bf16 sy[8][V * PY];
+  __shared__ float bred[8][16 * NF];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // the tap
+  const int r = lane & 15, kb = lane >> 4, tv = r >> 2, tq = r & 3;
+  const int cbase = (blockIdx.y % cblocks) * 16 * CF, nbase = (blockIdx.y / cblocks) * 16 * NF;
+  const int v0 = blockIdx.x * chunk, v1 = min(v0 + chunk, (int)a.M);
+  const bool bias = db && blockIdx.y % cblocks == 0;
+  const bf16 *__restrict__ dy = static_cast<const bf16 *>(a.y);
+
+  f32x4 acc[CF][NF];
+#pragma unroll
+  for (int i = 0; i < CF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) bsum[j] = 0.f;
+
+  bf16x8 xv[NX], yv[NY];
+  // rows vb .. vb + 63: x entry e = (row e / 2CF, 8-channel group e % 2CF); dy
+  // of tap w: lane l takes row l, groups 0 .. 2NF-1 (zeros past the ends)
+  auto load = [&](int vb) {
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int e = tid + 512 * u, m = vb + e / (2 * CF), c = cbase + 8 * (e % (2 * CF));
+      xv[u] = bf16x8{};
+      if (e < V * 2 * CF && m < v1 && c < a.cin) xv[u] = *reinterpret_cast<const bf16x8 *>(a.x + (int64_t)m * a.ldx + c);
+    }
+    const int m = vb + lane;
+    const int64_t fy = m < v1 ? dst_voxel32<LBM_NN_SCATTER2>(m, w, a.rows, a.out_grid) * a.ldy : 0;
+#pragma unroll
+    for (int g = 0; g < NY; ++g) {
+      const int n = nbase + 8 * g;
+      yv[g] = bf16x8{};
+      if (m < v1 && n < a.cout) yv[g] = *reinterpret_cast<const bf16x8 *>(dy + fy + n);
+    }
+  };
+
+  if (v0 < v1) load(v0);
+  for (int vb = v0; vb < v1; vb += V) {
+    __syncthreads();  // the previous rows' LDS reads are done
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+      const int e = tid + 512 * u;
+      if (e < V * 2 * CF) *reinterpret_cast<bf16x8 *>(&sx[(e / (2 * CF)) * PX + 8 * (e % (2 * CF))]) = xv[u];
+    }
+#pragma unroll
+    for (int g = 0; g < NY; ++g) *reinterpret_cast<bf16x8 *>(&sy[w][lane * PY + 8 * g]) = yv[g];
+    __syncthreads();
+    if (vb + V < v1) load(vb + V);  // in flight during the MFMAs
+#pragma unroll
+    for (int ks = 0; ks < V / 32; ++ks) {
+      const int row = 32 * ks + 8 * kb + tv;  // this lane's voxel (and + 4) for the transposing loads
+      bf16x8 bv[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j)
+        bv[j] = tr_load8(&sy[w][row * PY + 16 * j + 4 * tq], &sy[w][(row + 4) * PY + 16 * j + 4 * tq]);
+      if (bias)
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) bsum[j] += (float)bv[j][q];
+#pragma unroll
+      for (int i = 0; i < CF; ++i) {
+        const bf16x8 av = tr_load8(&sx[row * PX + 16 * i + 4 * tq], &sx[(row + 4) * PX + 16 * i + 4 * tq]);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds C[c = 16i + 4kb + q][n = 16j + r] of tap w
+  float *slot = ws ? ws + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (8 * 256 * CF * NF) : nullptr;
+#pragma unroll
+  for (int i = 0; i < CF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int cl = 16 * i + 4 * kb + q, nl = 16 * j + r;
+        if (slot) {
+          slot[(w * 16 * CF + cl) * 16 * NF + nl] = acc[i][j][q];
+        } else {
+          const int c = cbase + cl, n = nbase + nl;
+          if (c < a.cin && n < a.cout) atomicAdd(dw + ((int64_t)n * 8 + w) * a.cin + c, acc[i][j][q]);
+        }
+      }
+  if (bias) {  // (uniform per block) K groups, then taps, meet; one atomic add per channel
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      float v = bsum[j];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (kb == 0) bred[w][16 * j + r] = v;
+    }
+    __syncthreads();
+    if (tid < 16 * NF && nbase + tid < a.cout) {
+      float t = 0.f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t += bred[k][tid];
+      atomicAdd(db + nbase + tid, t);
+    }
+  }
+}
+
 // ---- weight gradient of a 3x3x3 convolution on spatial bricks ---------------
 // dW[n][t][c] += sum over output voxels v of x(v + o_t)[c] * dy(v)[n].  The
 // voxel-chunk kernel above gathers x and dy once per tap, so a large grid is
@@ -1838,6 +1957,52 @@ bool try_wgrad_brick(const GemmArgs &a, float *dw, float *ws, float *db, hipStre
   return true;
 }
 
+// Grid of k_wgrad_up2: chunks of 64-row multiples x channel tiles, about 512 blocks.
+struct Up2WgradGrid {
+  int cf, nf, cblocks, nblocks, chunk, chunks;
+};
+Up2WgradGrid up2_wgrad_grid(const GemmArgs &a) {
+  Up2WgradGrid w;
+  w.cf = wgrad_frags(a.cin, 3);
+  w.nf = wgrad_frags(a.cout, w.cf == 3 ? 2 : 3);
+  w.cblocks = (a.cin + 16 * w.cf - 1) / (16 * w.cf);
+  w.nblocks = (a.cout + 16 * w.nf - 1) / (16 * w.nf);
+  const int64_t tiles = (int64_t)w.cblocks * w.nblocks;
+  int64_t chunks = (512 + tiles - 1) / tiles;
+  int64_t chunk = (a.M + chunks - 1) / chunks;
+  chunk = (chunk + 63) / 64 * 64;
+  w.chunk = (int)chunk;
+  w.chunks = (int)((a.M + chunk - 1) / chunk);
+  return w;
+}
+int64_t up2_wgrad_ws_floats(const GemmArgs &a) {
+  const Up2WgradGrid w = up2_wgrad_grid(a);
+  return (int64_t)w.cblocks * w.nblocks * w.chunks * 8 * 256 * w.cf * w.nf;
+}
+template <int CF, int NF>
+hipError_t launch_wgrad_up2_cf(const GemmArgs &a, const Up2WgradGrid &w, float *dw, float *ws, float *db,
+                               hipStream_t s) {
+  const int tiles = w.cblocks * w.nblocks;
+  hipLaunchKernelGGL((k_wgrad_up2<CF, NF>), dim3((unsigned)w.chunks, (unsigned)tiles), dim3(512), 0, s, a, dw, w.chunk,
+                     w.cblocks, ws, db);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ws) return e;
+  return launch_wgrad_sum(ws, w.chunks, tiles, CF, NF, w.cblocks, 8, 8, a.cin, a.cout, dw, s);
+}
+hipError_t launch_wgrad_up2(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s) {
+  const Up2WgradGrid w = up2_wgrad_grid(a);
+  switch (w.cf * 4 + w.nf) {
+    case 5: return launch_wgrad_up2_cf<1, 1>(a, w, dw, ws, db, s);
+    case 6: return launch_wgrad_up2_cf<1, 2>(a, w, dw, ws, db, s);
+    case 7: return launch_wgrad_up2_cf<1, 3>(a, w, dw, ws, db, s);
+    case 9: return launch_wgrad_up2_cf<2, 1>(a, w, dw, ws, db, s);
+    case 10: return launch_wgrad_up2_cf<2, 2>(a, w, dw, ws, db, s);
+    case 11: return launch_wgrad_up2_cf<2, 3>(a, w, dw, ws, db, s);
+    case 13: return launch_wgrad_up2_cf<3, 1>(a, w, dw, ws, db, s);
+    default: return launch_wgrad_up2_cf<3, 2>(a, w, dw, ws, db, s);
+  }
+}
+
 // the generic weight gradient; db (or NULL): the bias gradient, summed in the same kernel
 template <int SRC, int DST>
 hipError_t launch_wgrad(const GemmArgs &a, float *dw, float *ws, float *db, hipStream_t s) {
@@ -1853,6 +2018,7 @@ hipError_t launch_wgrad(const GemmArgs &a, float *dw, float *ws, float *db, hipS
 int64_t wgrad_ws_floats(const lbm_nn_gemm *g, const GemmArgs &a) {
   if (g->src_mode == LBM_NN_CONV3 && g->dst_mode == LBM_NN_IDENT && wgrad_brick_applies(a, true))
     return wgrad_brick_ws_floats(a);
+  if (g->dst_mode == LBM_NN_SCATTER2) return up2_wgrad_ws_floats(a);
   return generic_wgrad_ws_floats(a);
 }
 
@@ -1915,7 +2081,7 @@ static int wgrad_impl(const lbm_nn_gemm *g, float *dw, float *db, float *ws, int
   hipStream_t s = static_cast<hipStream_t>(stream);
   // the bias gradient is summed inside the weight-gradient kernels
   if (g->dst_mode == LBM_NN_SCATTER2) {
-    NN_TRY((launch_wgrad<LBM_NN_IDENT, LBM_NN_SCATTER2>(a, dw, ws, db, s)));
+    NN_TRY(launch_wgrad_up2(a, dw, ws, db, s));
   } else if (g->src_mode == LBM_NN_CONV3) {
     hipError_t e = hipSuccess;
     if (!try_wgrad_brick(a, dw, ws, db, s, &e)) e = launch_wgrad<LBM_NN_CONV3, LBM_NN_IDENT>(a, dw, ws, db, s);
