@@ -341,6 +341,30 @@ def test_backward_weights_batch(torch):
         nn.backward_weights_batch([(nn.CONV3, 8, 24, 24, jobs[0][4], jobs[0][5])])
 
 
+@pytest.mark.parametrize("coarse,cin,cout", [
+    ((9, 7, 6), 16, 48),    # one input fragment, three output fragments (the largest LDS tiles)
+    ((6, 5, 11), 32, 48),   # two input fragments, three output fragments
+    ((8, 8, 8), 192, 96),   # four input tiles of 48 channels, three output tiles of 32
+])
+def test_up2_wgrad_shapes(torch, coarse, cin, cout):
+    """The transposed convolution's weight and bias gradients (one wavefront
+    per tap) on ragged row counts and every tile shape, with and without a
+    workspace, against the oracle."""
+    fine = tuple(2 * v for v in coarse)
+    x = bf(rng.normal(size=coarse + (cin,)))
+    dy = bf(rng.normal(size=fine + (cout,)))
+    _, gw, gb = onn.up2_backward(x, np.zeros((cout, 8, cin)), dy)
+    n = nn.wgrad_workspace(nn.IDENT, nn.SCATTER2, rows_of(coarse), 8, cin, cout, cin, cout)
+    assert n > 0
+    for ws in (None, torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")):
+        dw = torch.zeros((cout, 8, cin), dtype=torch.float32, device="cuda")
+        db = torch.zeros(cout, dtype=torch.float32, device="cuda")
+        nn.wgrad(nn.IDENT, nn.SCATTER2, rows_of(coarse), 8, cin, cout, dev(torch, x), cin, dev(torch, dy), cout, dw, db,
+                 ws=ws)
+        close(host(dw), gw, 2e-5)
+        close(host(db), gb, 2e-5)
+
+
 def test_head_dense_fp32_and_backward(torch):
     x = bf(rng.normal(size=GRID + (24,)))
     w = np.zeros((8, 1, 24))
