@@ -713,7 +713,7 @@ def main():
             "tiles_ratio": round(info["tiles_ratio"], 4), "bytes_per_fluid_node": 2 * q * SD[args.storage],
             "storage": args.storage, "tiles_per_block": args.tiles_per_block or 4,
             "tile_order": args.order, "step_kernel": args.kernel, "store_policy": args.store,
-            "model": args.model, "pattern": args.pattern, "collision": args.collision,
+            "fluid_model": args.model, "pattern": args.pattern, "collision": args.collision,
             "workspace_bytes": solver.workspace.numel(),
         },
         "roofline": {
