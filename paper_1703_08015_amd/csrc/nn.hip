@@ -447,11 +447,11 @@ hipError_t launch_up2_nw(const GemmArgs &a, bool relu, dim3 grid, size_t lds, hi
 // there, so each input row is fetched about 2.3 times per block instead of 27.
 // Wavefront w owns the z-plane w of the brick; its fragment f covers rows
 // y = 2f, 2f+1 (x = 0..7).  The tap loop is unrolled, so a tap's halo offset
-// is an immediate of the LDS read; each tap's CC channels are padded to whole
-// 32-wide K steps with zeros staged in LDS (CC = 8 packs four taps into one K
-// step instead).  Weight rows are read straight from global memory at clamped
-// addresses: padded K lanes meet zero A values, and columns past cout are never
-// stored.
+// is an immediate of the LDS read.  With CC = 32 each tap is one K step; CC = 8
+// packs four taps into one K step; CC = 24 and 48 run K over (tap, channel)
+// flattened.  Weight rows are read straight from global memory at clamped
+// addresses: K lanes past the end meet zero A values, and columns past cout
+// are never stored.
 constexpr int kBrickX = 8, kBrickY = 8, kBrickZ = 4;
 constexpr int kHaloX = kBrickX + 2, kHaloY = kBrickY + 2, kHaloZ = kBrickZ + 2;
 constexpr int kHalo = kHaloX * kHaloY * kHaloZ;
@@ -463,9 +463,9 @@ constexpr int kHalo = kHaloX * kHaloY * kHaloZ;
 template <int CC>
 struct BrickShape {
   static constexpr int KS = CC == 8 ? 1 : (CC + 31) / 32;  // K steps per tap
-  static constexpr int width = CC == 32 ? 32 : CC;          // channels staged per halo voxel (8, 24 or 32)
-  static constexpr int CP = CC == 32 ? 40 : 24;             // voxel pitch: 20 or 12 banks
-  static constexpr int RP = CC == 32 ? 448 : 320;           // row pitch: 224 or 160 banks (32 mod 64)
+  static constexpr int width = CC == 32 ? 32 : CC;          // channels staged per halo voxel (8, 24, 32 or 48)
+  static constexpr int CP = CC == 32 ? 40 : (CC == 48 ? 56 : 24);     // voxel pitch: 20, 28 or 12 banks
+  static constexpr int RP = CC == 32 ? 448 : (CC == 48 ? 576 : 320);  // row pitch: 224, 288 or 160 banks (32 mod 64)
   static constexpr int ROWS = kHaloY * kHaloZ;
   static_assert(kHaloX * CP <= RP && (RP / 2) % 64 == 32 && (CP / 2) % 8 == 4, "halo layout");
 };
@@ -477,14 +477,25 @@ constexpr int tap_off(int t) {
 
 constexpr int kBrickRing8 = 3;  // K steps of weights loaded ahead in the 8-channel form
 
+// LDS of a brick block in bf16 elements: the halo, or the output tile of 256
+// voxels x (16 NW + 8) that reuses it; past 64 KB it is dynamic LDS
+template <int NW, int CC>
+constexpr int brick_lds() {
+  constexpr int halo = BrickShape<CC>::ROWS * BrickShape<CC>::RP, out = kBrickX * kBrickY * kBrickZ * (16 * NW + 8);
+  return halo > out ? halo : out;
+}
+template <int NW, int CC>
+constexpr bool brick_dyn() { return brick_lds<NW, CC>() * 2 > 65536; }
+
 template <int NW, int CC, bool RELU>
-__global__ void __launch_bounds__(256, (NW <= 2 ? 4 : 2)) k_conv3_brick(GemmArgs a) {
+__global__ void __launch_bounds__(256, (NW <= 2 && CC != 48 ? 4 : 2)) k_conv3_brick(GemmArgs a) {
   using BS = BrickShape<CC>;
   constexpr int CP = BS::CP, RP = BS::RP;
-  // the output tile reuses the halo's LDS: 256 voxels x (16*NW + 8) bf16
   constexpr int OS = 16 * NW + 8;
-  constexpr int kLds = BS::ROWS * RP > kBrickX * kBrickY * kBrickZ * OS ? BS::ROWS * RP : kBrickX * kBrickY * kBrickZ * OS;
-  __shared__ __attribute__((aligned(16))) bf16 halo[kLds];
+  constexpr int kLds = brick_lds<NW, CC>();
+  __shared__ __attribute__((aligned(16))) bf16 halo_s[brick_dyn<NW, CC>() ? 8 : kLds];
+  extern __shared__ __attribute__((aligned(16))) bf16 halo_dyn[];
+  bf16 *const halo = brick_dyn<NW, CC>() ? halo_dyn : halo_s;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = lane & 15, kb = lane >> 4;
   const Grid g = a.rows;  // CONV3: output grid == input grid
@@ -588,26 +599,30 @@ __global__ void __launch_bounds__(256, (NW <= 2 ? 4 : 2)) k_conv3_brick(GemmArgs
             acc[f][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[f][j], 0, 0, 0);
         }
       });
-    } else if constexpr (CC == 24) {
-      // 24-channel chunks: K runs over (tap, channel) flattened, 27 * 24 = 648
-      // = 20.25 K steps of 32 instead of 27 steps padded from 24 to 32
-      // channels.  Lane group kb of step s takes k = 32 s + 8 kb: channels
-      // c .. c + 7 of tap t, with t = t0 + carry and c = c0 + 8 kb - 24 carry,
-      // where (t0, c0) is lane group 0's (a constant of the step, c0 in
-      // {0, 8, 16}) and carry = (c0 + 8 kb >= 24).  So a lane's LDS offset is a
-      // per-step constant plus 8 kb plus a carry term, and its weight offset
-      // likewise; the four fragments sit at fixed distances from fragment 0.
-      constexpr int NSTEP = (27 * 24 + 31) / 32;  // 21; lane groups 1-3 of the last step lie past k = 648
-      const bool carry8 = kb >= 2, carry16 = kb >= 1, carry0 = kb >= 3;  // carry for c0 = 8, 16, 0
+    } else if constexpr (CC == 24 || CC == 48) {
+      // 24- and 48-channel chunks: K runs over (tap, channel) flattened, 27 CC
+      // = 20.25 or 40.5 K steps of 32 instead of 27 or 54 steps padded to
+      // whole 32-channel steps.  Lane group kb of step s takes k = 32 s + 8 kb:
+      // channels c .. c + 7 of tap t, with t = t0 + carry and c = c0 + 8 kb - CC
+      // carry, where (t0, c0) is lane group 0's (a constant of the step) and
+      // carry = (c0 + 8 kb >= CC).  So a lane's LDS offset is a per-step
+      // constant plus 8 kb plus a carry term, and its weight offset likewise;
+      // the four fragments sit at fixed distances from fragment 0.
+      constexpr int NSTEP = (27 * CC + 31) / 32;  // lane groups of the last step past k = 27 CC are zero
+      const bool ge1 = kb >= 1, ge2 = kb >= 2, ge3 = kb >= 3;
+      auto carry = [&](auto C0) {  // lane group past the tap boundary, for c0 = C0
+        constexpr int p = (CC - decltype(C0)::value) / 8;  // first such lane group
+        return p == 1 ? ge1 : (p == 2 ? ge2 : (p == 3 ? ge3 : false));
+      };
       const int abase = rowbase[0] + 8 * kb;
-      const uint32_t wlane = 16u * (uint32_t)kb, wcarry = (uint32_t)(a.cin - 24) * 2u;
-      constexpr int R = 3;
+      const uint32_t wlane = 16u * (uint32_t)kb, wcarry = (uint32_t)(a.cin - CC) * 2u;
+      constexpr int R = CC == 48 && NW <= 3 ? 6 : 3;
       bf16x8 ring[R][NW];
       auto load_w = [&](auto U, bf16x8(&dst)[NW]) {
-        constexpr int k0 = 32 * decltype(U)::value, t0 = k0 / 24, cc0 = k0 % 24;
-        const bool cy = cc0 == 0 ? carry0 : (cc0 == 8 ? carry8 : carry16);
-        // lanes past the end (last step, kb >= 1) read a valid weight; their A is zero
-        const bool past = k0 + 8 * kb >= 27 * 24;
+        constexpr int k0 = 32 * decltype(U)::value, t0 = k0 / CC, cc0 = k0 % CC;
+        const bool cy = carry(std::integral_constant<int, cc0>{});
+        // lanes past the end (last step) read a valid weight; their A is zero
+        const bool past = k0 + 8 * kb >= 27 * CC;
         const uint32_t lo = past ? 0u : wlane + (cy ? wcarry : 0u);
 #pragma unroll
         for (int j = 0; j < NW; ++j) dst[j] = wload(c0 + t0 * a.cin + cc0, wrow[j] + lo);
@@ -615,17 +630,17 @@ __global__ void __launch_bounds__(256, (NW <= 2 ? 4 : 2)) k_conv3_brick(GemmArgs
       static_for<R>([&](auto P) { load_w(P, ring[decltype(P)::value]); });
       static_for<NSTEP>([&](auto U) {
         constexpr int u = decltype(U)::value, slot = u % R;
-        constexpr int k0 = 32 * u, t0 = k0 / 24, cc0 = k0 % 24;
+        constexpr int k0 = 32 * u, t0 = k0 / CC, cc0 = k0 % CC;
         constexpr int abase_u = tap_off<CC>(t0) + cc0;
-        constexpr int acarry = t0 < 26 ? tap_off<CC>(t0 + 1) - tap_off<CC>(t0) - 24 : 0;
-        const bool cy = cc0 == 0 ? carry0 : (cc0 == 8 ? carry8 : carry16);
+        constexpr int acarry = t0 < 26 ? tap_off<CC>(t0 + 1) - tap_off<CC>(t0) - CC : 0;
+        const bool cy = carry(std::integral_constant<int, cc0>{});
         const int aoff = abase + (cy ? acarry : 0) + abase_u;
         bf16x8 bv[NW];
 #pragma unroll
         for (int j = 0; j < NW; ++j) bv[j] = ring[slot][j];
         if constexpr (u + R < NSTEP) load_w(std::integral_constant<int, u + R>{}, ring[slot]);
         __builtin_amdgcn_sched_barrier(0);  // keep the load here: the scheduler would sink it next to its use
-        const bool zero = u == NSTEP - 1 && k0 + 8 * kb >= 27 * 24;
+        const bool zero = u == NSTEP - 1 && k0 + 8 * kb >= 27 * CC;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           bf16x8 av = *reinterpret_cast<const bf16x8 *>(&halo[(zero ? abase : aoff) + f * 2 * RP]);
@@ -1738,10 +1753,17 @@ hipError_t launch_fwd(const GemmArgs &a, hipStream_t s, const SplitPlan &sp = Sp
 
 template <int NW, int CC>
 hipError_t launch_brick_cc(const GemmArgs &a, bool relu, dim3 grid, hipStream_t s) {
+  const size_t dyn = brick_dyn<NW, CC>() ? 2 * (size_t)brick_lds<NW, CC>() : 0;
+  const void *k = relu ? reinterpret_cast<const void *>(&k_conv3_brick<NW, CC, true>)
+                       : reinterpret_cast<const void *>(&k_conv3_brick<NW, CC, false>);
+  if (dyn) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+  }
   if (relu)
-    hipLaunchKernelGGL((k_conv3_brick<NW, CC, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_conv3_brick<NW, CC, true>), grid, dim3(256), dyn, s, a);
   else
-    hipLaunchKernelGGL((k_conv3_brick<NW, CC, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_conv3_brick<NW, CC, false>), grid, dim3(256), dyn, s, a);
   return hipGetLastError();
 }
 
@@ -1750,14 +1772,16 @@ hipError_t launch_brick_nw(const GemmArgs &a, int cc, bool relu, dim3 grid, hipS
   switch (cc) {
     case 8: return launch_brick_cc<NW, 8>(a, relu, grid, s);
     case 24: return launch_brick_cc<NW, 24>(a, relu, grid, s);
+    case 48: return launch_brick_cc<NW, 48>(a, relu, grid, s);
     default: return launch_brick_cc<NW, 32>(a, relu, grid, s);
   }
 }
 
 // The brick kernel for a 3x3x3 convolution with BF16 output: channel chunks of
-// 8 (an 8-channel input), 24 (24 or 48 channels: a 48-wide chunk would need
-// 86 KB of LDS and leave one block per CU) or 32 (multiples of 32), and enough
-// bricks to fill the device; returns false to use k_forward instead.
+// 8 (an 8-channel input), 24 or 48 (the whole input: one halo staging per block;
+// the 48-channel halo takes 69 KB of dynamic LDS, two blocks per CU) or 32
+// (multiples of 32), and enough bricks to fill the device; returns false to use
+// k_forward instead.
 // channel chunk of the brick kernel for a 3x3x3 convolution with BF16
 // output, or 0 where it does not apply (an unsupported input width, a grid
 // thinner than a brick, whose halo would wrap past one period, or too few
@@ -1768,7 +1792,7 @@ int brick_chunk(const GemmArgs &a, bool f32) {
   if (a.cin == 8)
     cc = 8;
   else if (a.cin == 24 || a.cin == 48)
-    cc = 24;
+    cc = a.cin;
   else if (a.cin % 32 == 0)
     cc = 32;
   else
