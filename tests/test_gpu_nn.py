@@ -83,6 +83,7 @@ def test_conv3_forward_backward(torch, cin, cout, relu):
     ((16, 32, 64), 24, 64, False),  # 24-channel chunk with four 16-column groups
     ((16, 32, 64), 48, 48, True),   # one 48-channel chunk, three 16-column groups
     ((16, 32, 64), 48, 64, False),  # one 48-channel chunk, four 16-column groups
+    ((36, 64, 64), 48, 24, True),   # 640 bricks, a partial brick along x
 ])
 def test_conv3_brick_kernel(torch, grid, cin, cout, relu):
     """Grids with at least 256 8x8x4 bricks run the LDS-halo kernel; the data
