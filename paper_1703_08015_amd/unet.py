@@ -302,54 +302,58 @@ class UNet:
         if use and getattr(self, "_side_stream", None) is None:
             self._side_stream = t.cuda.Stream(device=self.device)  # default priority
         self._side = self._side_stream if use else None
-        hw, hb = self.head
-        rows0 = self._rows(grids[0])
-        below = A["d2", 0] if L > 1 else A["cat", 0]
-        ldbelow = C[0] if L > 1 else A["cat", 0].shape[-1]
-        self._wg(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g)
-        wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
-        d_below = G["d2", 0] if L > 1 else G["cat", 0]
-        self._fwd(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
-                   gate=below, ldg=ldbelow, gate_channels=C[0])
-        # decoder, top level first (reverse of the forward order)
-        for k, l in enumerate(range(0, L - 1)):
-            idx = L - 2 - l  # position of level l in self.up / self.dec
-            rows, rows_c = self._rows(grids[l]), self._rows(grids[l + 1])
-            uw, ub = self.up[idx]
-            (w1, b1), (w2, b2) = self.dec[idx]
-            self._conv_backward(rows, C[l], C[l], A["d1", l], C[l], w2, b2, G["d2", l], C[l], G["d1", l], C[l])
-            # the concat input: only its skip half [0, C) is a ReLU output
-            self._conv_backward(rows, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1, b1, G["d1", l], C[l], G["cat", l],
-                                2 * C[l], gate_ch=C[l])
-            # transposed conv: input = level l+1 output (d2 of l+1, or the bottom cat buffer)
-            if l + 1 == L - 1:
-                xin, ldxin, dxin = A["cat", L - 1], A["cat", L - 1].shape[-1], G["cat", L - 1]
-            else:
-                xin, ldxin, dxin = A["d2", l + 1], C[l + 1], G["d2", l + 1]
-            self._wg(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], xin, ldxin, G["cat", l], 2 * C[l], uw.g, ub.g,
-                     dy_offset=C[l])
-            wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
-            self._fwd(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
-                       x_offset=C[l], gate=xin, ldg=ldxin, gate_channels=C[l + 1])
-        # encoder, bottom level first
-        for l in range(L - 1, -1, -1):
-            rows = self._rows(grids[l])
-            (w1, b1), (w2, b2) = self.enc[l]
-            width = A["cat", l].shape[-1]
-            self._conv_backward(rows, C[l], C[l], A["e1", l], C[l], w2, b2, G["cat", l], width, G["e1", l], C[l])
-            if l > 0:
-                # the pooled gradient is gated by the pooled value, which is the
-                # winning corner's ReLU output, before it joins the skip
-                # gradient already in the first half of cat[l-1]
-                self._conv_backward(rows, C[l - 1], C[l], A["pool", l], C[l - 1], w1, b1, G["e1", l], C[l],
-                                    G["pool", l], C[l - 1])
-                nn.maxpool2_backward(rows, C[l - 1], G["pool", l], C[l - 1], A["arg", l], G["cat", l - 1],
-                                     2 * C[l - 1], accumulate=True)
-            else:
-                self._conv_backward(rows, self.in_ch, C[0], self._x, self.in_ch, w1, b1, G["e1", 0], C[0], None, 0,
-                                    need_dx=False)
-        if self._side is not None:
-            t.cuda.current_stream().wait_stream(self._side)
+        try:
+            hw, hb = self.head
+            rows0 = self._rows(grids[0])
+            below = A["d2", 0] if L > 1 else A["cat", 0]
+            ldbelow = C[0] if L > 1 else A["cat", 0].shape[-1]
+            self._wg(nn.IDENT, nn.IDENT, rows0, 1, C[0], self.out_pad, below, ldbelow, dout, self.out_pad, hw.g, hb.g)
+            wt = self._wt(hw, nn.IDENT, 1, C[0], self.out_pad)
+            d_below = G["d2", 0] if L > 1 else G["cat", 0]
+            self._fwd(nn.IDENT, nn.IDENT, rows0, 1, self.out_pad, C[0], dout, self.out_pad, wt, d_below, ldbelow,
+                       gate=below, ldg=ldbelow, gate_channels=C[0])
+            # decoder, top level first (reverse of the forward order)
+            for k, l in enumerate(range(0, L - 1)):
+                idx = L - 2 - l  # position of level l in self.up / self.dec
+                rows, rows_c = self._rows(grids[l]), self._rows(grids[l + 1])
+                uw, ub = self.up[idx]
+                (w1, b1), (w2, b2) = self.dec[idx]
+                self._conv_backward(rows, C[l], C[l], A["d1", l], C[l], w2, b2, G["d2", l], C[l], G["d1", l], C[l])
+                # the concat input: only its skip half [0, C) is a ReLU output
+                self._conv_backward(rows, 2 * C[l], C[l], A["cat", l], 2 * C[l], w1, b1, G["d1", l], C[l], G["cat", l],
+                                    2 * C[l], gate_ch=C[l])
+                # transposed conv: input = level l+1 output (d2 of l+1, or the bottom cat buffer)
+                if l + 1 == L - 1:
+                    xin, ldxin, dxin = A["cat", L - 1], A["cat", L - 1].shape[-1], G["cat", L - 1]
+                else:
+                    xin, ldxin, dxin = A["d2", l + 1], C[l + 1], G["d2", l + 1]
+                self._wg(nn.IDENT, nn.SCATTER2, rows_c, 8, C[l + 1], C[l], xin, ldxin, G["cat", l], 2 * C[l],
+                         uw.g, ub.g, dy_offset=C[l])
+                wt = self._wt(uw, nn.SCATTER2, 8, C[l + 1], C[l])
+                self._fwd(nn.GATHER2, nn.IDENT, rows_c, 8, C[l], C[l + 1], G["cat", l], 2 * C[l], wt, dxin, ldxin,
+                           x_offset=C[l], gate=xin, ldg=ldxin, gate_channels=C[l + 1])
+            # encoder, bottom level first
+            for l in range(L - 1, -1, -1):
+                rows = self._rows(grids[l])
+                (w1, b1), (w2, b2) = self.enc[l]
+                width = A["cat", l].shape[-1]
+                self._conv_backward(rows, C[l], C[l], A["e1", l], C[l], w2, b2, G["cat", l], width, G["e1", l], C[l])
+                if l > 0:
+                    # the pooled gradient is gated by the pooled value, which is the
+                    # winning corner's ReLU output, before it joins the skip
+                    # gradient already in the first half of cat[l-1]
+                    self._conv_backward(rows, C[l - 1], C[l], A["pool", l], C[l - 1], w1, b1, G["e1", l], C[l],
+                                        G["pool", l], C[l - 1])
+                    nn.maxpool2_backward(rows, C[l - 1], G["pool", l], C[l - 1], A["arg", l], G["cat", l - 1],
+                                         2 * C[l - 1], accumulate=True)
+                else:
+                    self._conv_backward(rows, self.in_ch, C[0], self._x, self.in_ch, w1, b1, G["e1", 0], C[0], None, 0,
+                                        need_dx=False)
+        finally:
+            # join the streams also when a pass raises, so that nothing
+            # queued later on the current stream overlaps a weight gradient
+            if self._side is not None:
+                t.cuda.current_stream().wait_stream(self._side)
 
     def _grads(self, A, grids):
         t = self.torch
