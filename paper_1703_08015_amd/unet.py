@@ -48,10 +48,11 @@ class UNet:
         self.out_scale = out_scale
         # weight gradients run on a second stream beside the backward-data
         # passes (same kernels and results; False keeps one stream), on grids
-        # of at least overlap_min_voxels: a training step at 64^3 takes the
-        # same time either way, 80^3 to 128^3 gain 5-9%
+        # of at least overlap_min_voxels: 96^3 to 128^3 gain 5-9% per training
+        # step; at 64^3 two streams took 1.33-1.53 ms from run to run against
+        # 1.40 ms on one
         self.overlap = True
-        self.overlap_min_voxels = 1 << 18
+        self.overlap_min_voxels = 1 << 19
         self._side = None
         gen = torch.Generator().manual_seed(seed)
         P = lambda shape, fan, **kw: Param(torch, shape, fan, self.device, gen, **kw)
